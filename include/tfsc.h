@@ -1,0 +1,207 @@
+/*
+ * tfsc -- semi-coherent time-frequency detection statistic for LISA
+ * stellar-mass binary searches (arXiv 2510.19047), on AMD MI355X (gfx950).
+ *
+ * C ABI of libtfsc.so.  Every array argument is a DEVICE pointer owned by the
+ * caller (the library never allocates or frees device memory).  Every call is
+ * asynchronous and stream-ordered on `stream` (a hipStream_t; NULL = the
+ * default stream).  Errors are reported as tfsc_status codes; no exception
+ * crosses the ABI.  Argument checks that need device data (none today) would
+ * be reported through per-template flags, never through a fault.
+ *
+ * Notation (paper Sec. "Methods"): the data are cut into Nt tranches of
+ * M samples (duration dT = M dt, bin spacing delta f = 1/dT); each tranche is
+ * Fourier transformed once; a template's frequency track visits one
+ * tranche-bin pixel per bin of its N_F = 21 bin window per tranche; tranches
+ * are grouped into N_seg equal segments (coherence length T_seg).
+ */
+#ifndef TFSC_H
+#define TFSC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TFSC_ABI_VERSION 1
+
+typedef enum {
+    TFSC_OK = 0,
+    TFSC_ERR_ARG = 1,          /* NULL pointer or out-of-range scalar       */
+    TFSC_ERR_SHAPE = 2,        /* inconsistent sizes                        */
+    TFSC_ERR_DTYPE = 3,        /* unsupported element type / combination    */
+    TFSC_ERR_WORKSPACE = 4,    /* workspace missing or too small            */
+    TFSC_ERR_UNSUPPORTED = 5,  /* valid request this build does not handle  */
+    TFSC_ERR_HIP = 6           /* a HIP runtime call failed                 */
+} tfsc_status;
+
+typedef enum { TFSC_F64 = 0, TFSC_F32 = 1, TFSC_BF16 = 2, TFSC_F16 = 3 } tfsc_dtype;
+
+/* Pixel store layouts (complex values stored as interleaved (re, im)):
+ *   LAYER_MAJOR   [C][K][Nt]  -- tranches contiguous within one frequency layer
+ *   TRANCHE_MAJOR [C][Nt][K]  -- bins contiguous within one tranche          */
+typedef enum { TFSC_LAYER_MAJOR = 0, TFSC_TRANCHE_MAJOR = 1 } tfsc_layout;
+
+/* Sampling grid.  C = 1 (TDI A) or 2 (A, E); M even, 64 <= M <= 4096 and a
+ * power of two (the transform's FFT); K = M/2 + 1 bins per tranche;
+ * n_fresnel must be 21 (paper: N_F = 21 bins centred on the bin just above
+ * the track frequency).  tukey_alpha is the data window's shape (paper: 0.1;
+ * 0 = rectangular); it only enters tfsc_transform.                          */
+typedef struct {
+    int32_t n_channels;
+    int32_t tranche_len;
+    int32_t n_tranches;
+    int32_t n_fresnel;
+    double dt;
+    double tukey_alpha;
+} tfsc_grid;
+
+/* Whitened TF pixels D[c][k][m] plus the template weights.  pix holds
+ * complex values of `dtype` in `layout`; for BF16/F16 the true value is
+ * layer_scale[c*K + k] * stored (layer_scale is [C][K] FP32, NULL otherwise).
+ * inv_asd[K] = u_k = 1/sqrt(S0(f_k)) and tranche_w[Nt] = w_m = 1/sqrt(mu_m)
+ * (0 = tranche excluded, e.g. it overlaps a data gap).  The template pixel of
+ * channel c is T_c(t_m, f_m) h_m(f_k) u_k w_m (paper Eqs. (tdi2),
+ * (inner-tranche-tf)).  tfsc_transform writes all five arrays.             */
+typedef struct {
+    tfsc_dtype dtype;
+    tfsc_layout layout;
+    void *pix;
+    float *layer_scale;
+    double *inv_asd;
+    double *tranche_w;
+} tfsc_pixels;
+
+/* Template bank, structure of arrays, n templates, FP64:
+ * mc [Msun] chirp mass; eta symmetric mass ratio (0.01..0.25); f0 [Hz] GW
+ * frequency at t = 0; cos_theta, phi source direction (polar, azimuth);
+ * psi polarisation angle; cos_iota inclination.  Track: 2PN TaylorT3.       */
+typedef struct {
+    int64_t n;
+    const double *mc, *eta, *f0, *cos_theta, *phi, *psi, *cos_iota;
+} tfsc_bank;
+
+/* Segment layout.  nseg_fixed > 0 gives every template that many segments;
+ * 0 selects the per-template rule N_seg = 16 * 2^n, n = #{i=1..4 :
+ * fdot0 >= 1.34e-12 Hz/s * 2^(3i - 3/2)} (16..256).  Segment s of a template
+ * holds tranches m with floor(m N_seg / Nt) = s.  nseg[n] and
+ * seg_offset[n+1] (exclusive prefix sum of nseg) are written by
+ * tfsc_segment_layout and read by the statistic calls.                     */
+typedef struct {
+    int32_t nseg_fixed;
+    int32_t *nseg;
+    int64_t *seg_offset;
+} tfsc_segments;
+
+/* Arithmetic and schedule of the statistic kernels.
+ * precision: TFSC_F64 -- response, Fresnel kernel and sums in FP64;
+ *            TFSC_F32 -- FP32 response, Fresnel kernel and tranche sums
+ *                        (segment sums stay FP64).  The track (phase,
+ *                        frequency, chirp, bin index, track end) is always
+ *                        FP64.
+ * schedule:  TFSC_SCHED_THREAD -- one thread per template walking its
+ *                        tranches (the paper's mapping); any layout.
+ *            TFSC_SCHED_WAVE   -- one 64-lane wavefront per template, lanes
+ *                        over consecutive tranches, persistent grid pulling
+ *                        templates from a device work counter; LAYER_MAJOR.
+ * block_waves / groups_per_cu: launch shape of the WAVE schedule (0 = tuned
+ * default); order: optional [n] permutation of template indices giving the
+ * processing order (NULL = bank order); results are written at the
+ * template's own index whatever the order.                                 */
+enum { TFSC_SCHED_THREAD = 0, TFSC_SCHED_WAVE = 1 };
+typedef struct {
+    int32_t precision;
+    int32_t schedule;
+    int32_t block_waves;
+    int32_t groups_per_cu;
+    const int32_t *order;
+} tfsc_options;
+
+/* Per-template flag bits written by tfsc_bank_statistic. */
+enum {
+    TFSC_FLAG_INVALID = 1,      /* parameters out of range: statistic 0      */
+    TFSC_FLAG_EMPTY = 2,        /* no active tranche                         */
+    TFSC_FLAG_BAND_END = 4,     /* track ended by the band or compactness    */
+    TFSC_FLAG_MERGE_END = 8,    /* track ended by the merger condition       */
+    TFSC_FLAG_ALL_EXCLUDED = 16 /* every active tranche excluded (w_m = 0)   */
+};
+
+enum { TFSC_WS_LAYOUT = 0, TFSC_WS_STATISTIC = 1, TFSC_WS_VJP = 2, TFSC_WS_TRANSFORM = 3 };
+
+int tfsc_abi_version(void);
+const char *tfsc_status_string(int status);
+
+/* Bytes of device workspace call `which` (TFSC_WS_*) needs for this grid,
+ * bank size and options (0 if none).  Workspace contents need not be
+ * initialised; calls sharing one workspace must not overlap in time.      */
+size_t tfsc_workspace_bytes(const tfsc_grid *grid, int64_t n_templates, const tfsc_options *opt, int which);
+
+/* Data -> TF pixels (paper Sec. "Implementation details": each tranche is
+ * Tukey-windowed and Fourier transformed once; a per-tranche PSD models
+ * locally stationary noise; tranches overlapping gaps are left out of
+ * Eq. (inner-tf)).
+ *   x [C][N] time series (N = M Nt), x_dtype TFSC_F64 or TFSC_F32;
+ *   psd0 [K] one-sided PSD S0(f_k) at f_k = k/dT (> 0 for 1 <= k < M/2);
+ *   tranche_psd_scale [Nt] mu_m (> 0): tranche m has PSD mu_m S0;
+ *   tranche_keep [Nt] uint8, 0 = exclude tranche m.
+ * Writes out->pix (D = X sqrt(2 dt / (M W2 mu_m S0(f_k))), X the windowed
+ * DFT with the tranche start as time origin, W2 = mean(w^2); excluded
+ * tranches are 0), out->inv_asd, out->tranche_w, and out->layer_scale for
+ * 16-bit stores (per layer max |component|, FP32).  out->dtype may be F64
+ * (x F64 only), F32, BF16 or F16; 16-bit outputs need TFSC_WS_TRANSFORM
+ * workspace.                                                               */
+tfsc_status tfsc_transform(const tfsc_grid *grid, const void *x, int x_dtype, const double *psd0,
+                           const double *tranche_psd_scale, const uint8_t *tranche_keep, tfsc_pixels *out,
+                           void *ws, size_t ws_bytes, void *stream);
+
+/* Per-template setup (paper Sec. "Methods": N_seg = tau / T_seg; here set
+ * per template from fdot at t = 0, or fixed).  Writes seg->nseg and
+ * seg->seg_offset; needs TFSC_WS_LAYOUT workspace.                         */
+tfsc_status tfsc_segment_layout(const tfsc_grid *grid, const tfsc_bank *bank, tfsc_segments *seg, void *ws,
+                                size_t ws_bytes, void *stream);
+
+/* The statistic (paper Eqs. (Upsilon-seg), (overlap-n), (inner-segment-tf),
+ * (inner-tranche-tf), (fresnel-ft)): for each template,
+ *   z_n = sum_{c, m in segment n, k in the 21 bins} conj(D_cmk) Y_cmk,
+ *   N_n = sum |Y_cmk|^2,  Upsilon_n = 2 |z_n|^2 / N_n (0 if N_n = 0),
+ *   Upsilon = sum_n Upsilon_n,
+ * with Y_cmk = T_c(t_m, f_m) h_m(f_k) u_k w_m, h_m the Fresnel-kernel
+ * tranche spectrum of the TaylorT3 track expanded at the tranche start, and
+ * the bins k = ceil(f_m dT) - 10 .. + 10 inside [1, M/2 - 1].
+ * Outputs (FP64): seg_terms[seg_offset[n]], stat[n], flags[n] (TFSC_FLAG_*);
+ * seg_zn[seg_offset[n]][3] = (Re z_n, Im z_n, N_n) if non-NULL (the VJP's
+ * input).  The kernels use u_k 2^-e with e the binary exponent of
+ * max_k u_k (an exact power-of-two rescaling that keeps FP32 sums in range);
+ * Upsilon is unchanged by it, z_n and N_n carry factors 2^-e and 2^-2e.
+ * Needs TFSC_WS_STATISTIC workspace.                                        */
+tfsc_status tfsc_bank_statistic(const tfsc_grid *grid, const tfsc_pixels *pix, const tfsc_bank *bank,
+                                const tfsc_segments *seg, const tfsc_options *opt, double *seg_terms, double *stat,
+                                double *seg_zn, int32_t *flags, void *ws, size_t ws_bytes, void *stream);
+
+/* Vector-Jacobian product of the statistic: g_params[n][5] =
+ * d(sum_n g_seg_n Upsilon_n + g_stat Upsilon)/d(ln Mc, f0, cos theta, phi, psi)
+ * holding the integer structure (bins, Fresnel branches, track end, N_seg)
+ * fixed; the track is recomputed, nothing per pixel is stored.  seg_zn is
+ * the forward's output for the same inputs; g_stat[n] and/or g_seg
+ * [seg_offset[n]] (either may be NULL).  Needs TFSC_WS_VJP workspace.       */
+tfsc_status tfsc_statistic_vjp(const tfsc_grid *grid, const tfsc_pixels *pix, const tfsc_bank *bank,
+                               const tfsc_segments *seg, const tfsc_options *opt, const double *seg_zn,
+                               const double *g_stat, const double *g_seg, double *g_params, void *ws,
+                               size_t ws_bytes, void *stream);
+
+/* The FP64 track behind every statistic call, for inspection: out[n][Nt][4]
+ * holds (Phi_m, f_m, fdot_m, code_m) at each tranche start t_m = m dT, with
+ * code_m = 0 for an active tranche, else the TFSC_FLAG_* bit of the
+ * condition that ends the track there (Phi, f, fdot are 0 where the merger
+ * condition holds).  Invalid templates give code TFSC_FLAG_INVALID.  Same
+ * arithmetic, bit for bit, as the statistic kernels (paper Sec.
+ * "Time-frequency waveform representation": second-order expansion at the
+ * tranche start; Appendix A compactness).                                  */
+tfsc_status tfsc_track(const tfsc_grid *grid, const tfsc_bank *bank, double *out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TFSC_H */

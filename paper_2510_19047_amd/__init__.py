@@ -1,0 +1,260 @@
+"""tfsc: the semi-coherent time-frequency detection statistic of arXiv 2510.19047 on MI355X.
+
+Every step runs in the HIP kernels of ``libtfsc.so`` (C ABI in include/tfsc.h).
+This module only marshals torch device tensors and the current HIP stream into
+those calls; it never computes any part of the statistic itself, and it raises
+if the library is missing or if a tensor is not on the GPU.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+from ._lib import TfscError
+
+__all__ = ["GridSpec", "PixelStore", "BankTensors", "SegmentLayout", "StatResult", "transform", "segment_layout",
+           "bank_statistic", "statistic_vjp", "track", "TFSCStatistic", "lib", "TfscError"]
+
+_DTYPE = {"f64": _lib.F64, "f32": _lib.F32, "bf16": _lib.BF16, "f16": _lib.F16}
+_TORCH_STORE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
+_LAYOUT = {"layer": _lib.LAYER_MAJOR, "tranche": _lib.TRANCHE_MAJOR}
+_SCHED = {"thread": _lib.SCHED_THREAD, "wave": _lib.SCHED_WAVE}
+_PREC = {"f64": _lib.F64, "f32": _lib.F32}
+
+
+def lib():
+    return _lib.load()
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise TfscError("tfsc calls take device tensors only")
+    if not t.is_contiguous():
+        raise TfscError("tfsc calls take contiguous tensors only")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _ws(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+@dataclass
+class GridSpec:
+    """Sampling grid: C channels, Nt tranches of M samples at cadence dt."""
+    n_channels: int
+    tranche_len: int
+    n_tranches: int
+    dt: float = 5.0
+    tukey_alpha: float = 0.1
+
+    @property
+    def n_bins(self) -> int:
+        return self.tranche_len // 2 + 1
+
+    def c(self) -> _lib.Grid:
+        return _lib.Grid(self.n_channels, self.tranche_len, self.n_tranches, 21, float(self.dt), float(self.tukey_alpha))
+
+
+@dataclass
+class PixelStore:
+    """Whitened TF pixels plus template weights (see tfsc_pixels)."""
+    pix: torch.Tensor                 # [C][K][Nt][2] (layer) or [C][Nt][K][2] (tranche), store dtype
+    inv_asd: torch.Tensor             # [K] f64
+    tranche_w: torch.Tensor           # [Nt] f64
+    dtype: str = "f32"
+    layout: str = "layer"
+    layer_scale: torch.Tensor | None = None  # [C][K] f32 for 16-bit stores
+
+    def c(self) -> _lib.Pixels:
+        return _lib.Pixels(_DTYPE[self.dtype], _LAYOUT[self.layout], _ptr(self.pix), _ptr(self.layer_scale),
+                           _ptr(self.inv_asd), _ptr(self.tranche_w))
+
+    @staticmethod
+    def from_complex(pix: torch.Tensor, inv_asd: torch.Tensor, tranche_w: torch.Tensor, dtype: str = "f64",
+                     layout: str = "layer") -> "PixelStore":
+        """Wrap complex [C][K][Nt] pixels (already whitened) as a store of FP64 or FP32 values."""
+        if dtype not in ("f64", "f32"):
+            raise TfscError("from_complex stores f64 or f32; 16-bit stores come from transform()")
+        p = pix if layout == "layer" else pix.transpose(1, 2)
+        real = torch.view_as_real(p.contiguous().to(torch.complex128 if dtype == "f64" else torch.complex64))
+        return PixelStore(real.contiguous(), inv_asd.to(torch.float64).contiguous(),
+                          tranche_w.to(torch.float64).contiguous(), dtype, layout)
+
+
+@dataclass
+class BankTensors:
+    """Template parameters as FP64 device tensors (see tfsc_bank)."""
+    mc: torch.Tensor
+    eta: torch.Tensor
+    f0: torch.Tensor
+    cos_theta: torch.Tensor
+    phi: torch.Tensor
+    psi: torch.Tensor
+    cos_iota: torch.Tensor
+
+    FIELDS = ("mc", "eta", "f0", "cos_theta", "phi", "psi", "cos_iota")
+
+    @property
+    def n(self) -> int:
+        return int(self.mc.numel())
+
+    @staticmethod
+    def from_host(bank, device="cuda") -> "BankTensors":
+        import numpy as np
+        return BankTensors(*(torch.as_tensor(np.ascontiguousarray(getattr(bank, k), dtype=np.float64), device=device)
+                             for k in BankTensors.FIELDS))
+
+    def c(self) -> _lib.Bank:
+        return _lib.Bank(self.n, *(_ptr(getattr(self, k)) for k in self.FIELDS))
+
+
+@dataclass
+class SegmentLayout:
+    nseg: torch.Tensor        # [n] int32
+    seg_offset: torch.Tensor  # [n+1] int64
+    nseg_fixed: int = 0
+    total: int = 0            # seg_offset[n], read once on the host
+
+    def c(self) -> _lib.Segments:
+        return _lib.Segments(int(self.nseg_fixed), _ptr(self.nseg), _ptr(self.seg_offset))
+
+
+@dataclass
+class StatResult:
+    stat: torch.Tensor        # [n] f64
+    seg_terms: torch.Tensor   # [total] f64
+    flags: torch.Tensor       # [n] int32
+    seg_zn: torch.Tensor | None = None  # [total][3] f64
+
+
+def _options(precision="f32", schedule="wave", block_waves=0, groups_per_cu=0, order=None) -> _lib.Options:
+    return _lib.Options(_PREC[precision], _SCHED[schedule], int(block_waves), int(groups_per_cu), _ptr(order))
+
+
+def transform(grid: GridSpec, x: torch.Tensor, psd0: torch.Tensor, mu: torch.Tensor, keep: torch.Tensor,
+              dtype: str = "f32", layout: str = "layer", out: PixelStore | None = None) -> PixelStore:
+    """tfsc_transform: time series [C][N] (f64 or f32) -> whitened pixel store."""
+    L = lib()
+    dev = x.device
+    K, Nt, C = grid.n_bins, grid.n_tranches, grid.n_channels
+    if out is None:
+        shape = (C, K, Nt, 2) if layout == "layer" else (C, Nt, K, 2)
+        out = PixelStore(torch.empty(shape, dtype=_TORCH_STORE[dtype], device=dev),
+                         torch.empty(K, dtype=torch.float64, device=dev), torch.empty(Nt, dtype=torch.float64, device=dev),
+                         dtype, layout,
+                         torch.empty((C, K), dtype=torch.float32, device=dev) if dtype in ("bf16", "f16") else None)
+    g = grid.c()
+    xd = _lib.F64 if x.dtype == torch.float64 else _lib.F32
+    nb = L.tfsc_workspace_bytes(ctypes.byref(g), 0, None, _lib.WS_TRANSFORM)
+    ws = _ws(nb, dev) if dtype in ("bf16", "f16") else None
+    pc = out.c()
+    st = L.tfsc_transform(ctypes.byref(g), _ptr(x), xd, _ptr(psd0), _ptr(mu), _ptr(keep), ctypes.byref(pc),
+                          _ptr(ws), nb if ws is not None else 0, _stream())
+    _lib.check(st, "tfsc_transform")
+    return out
+
+
+def segment_layout(grid: GridSpec, bank: BankTensors, nseg_fixed: int = 0) -> SegmentLayout:
+    """tfsc_segment_layout: N_seg per template and CSR offsets (reads the total back once)."""
+    L = lib()
+    dev = bank.mc.device
+    seg = SegmentLayout(torch.empty(bank.n, dtype=torch.int32, device=dev),
+                        torch.empty(bank.n + 1, dtype=torch.int64, device=dev), nseg_fixed)
+    g = grid.c()
+    nb = L.tfsc_workspace_bytes(ctypes.byref(g), bank.n, None, _lib.WS_LAYOUT)
+    ws = _ws(nb, dev)
+    sc = seg.c()
+    bc = bank.c()
+    st = L.tfsc_segment_layout(ctypes.byref(g), ctypes.byref(bc), ctypes.byref(sc), _ptr(ws), nb, _stream())
+    _lib.check(st, "tfsc_segment_layout")
+    seg.total = int(seg.seg_offset[-1].item())
+    return seg
+
+
+def bank_statistic(grid: GridSpec, pixels: PixelStore, bank: BankTensors, seg: SegmentLayout,
+                   precision: str = "f32", schedule: str = "wave", want_zn: bool = False, block_waves: int = 0,
+                   groups_per_cu: int = 0, order: torch.Tensor | None = None, out: StatResult | None = None,
+                   ws: torch.Tensor | None = None) -> StatResult:
+    """tfsc_bank_statistic: Upsilon, per-segment terms and flags for every template."""
+    L = lib()
+    dev = bank.mc.device
+    if out is None:
+        out = StatResult(torch.empty(bank.n, dtype=torch.float64, device=dev),
+                         torch.empty(max(seg.total, 1), dtype=torch.float64, device=dev),
+                         torch.empty(bank.n, dtype=torch.int32, device=dev),
+                         torch.empty((max(seg.total, 1), 3), dtype=torch.float64, device=dev) if want_zn else None)
+    g = grid.c()
+    opt = _options(precision, schedule, block_waves, groups_per_cu, order)
+    nb = L.tfsc_workspace_bytes(ctypes.byref(g), bank.n, ctypes.byref(opt), _lib.WS_STATISTIC)
+    if ws is None or ws.numel() < nb:
+        ws = _ws(nb, dev)
+    pc, bc, sc = pixels.c(), bank.c(), seg.c()
+    st = L.tfsc_bank_statistic(ctypes.byref(g), ctypes.byref(pc), ctypes.byref(bc), ctypes.byref(sc),
+                               ctypes.byref(opt), _ptr(out.seg_terms), _ptr(out.stat), _ptr(out.seg_zn),
+                               _ptr(out.flags), _ptr(ws), ws.numel(), _stream())
+    _lib.check(st, "tfsc_bank_statistic")
+    return out
+
+
+def statistic_vjp(grid: GridSpec, pixels: PixelStore, bank: BankTensors, seg: SegmentLayout, seg_zn: torch.Tensor,
+                  g_stat: torch.Tensor | None = None, g_seg: torch.Tensor | None = None, precision: str = "f32",
+                  block_waves: int = 0, groups_per_cu: int = 0, out: torch.Tensor | None = None) -> torch.Tensor:
+    """tfsc_statistic_vjp: [n][5] gradient w.r.t. (ln Mc, f0, cos theta, phi, psi)."""
+    L = lib()
+    dev = bank.mc.device
+    if out is None:
+        out = torch.empty((bank.n, 5), dtype=torch.float64, device=dev)
+    g = grid.c()
+    opt = _options(precision, "wave", block_waves, groups_per_cu, None)
+    nb = L.tfsc_workspace_bytes(ctypes.byref(g), bank.n, ctypes.byref(opt), _lib.WS_VJP)
+    ws = _ws(nb, dev)
+    pc, bc, sc = pixels.c(), bank.c(), seg.c()
+    st = L.tfsc_statistic_vjp(ctypes.byref(g), ctypes.byref(pc), ctypes.byref(bc), ctypes.byref(sc),
+                              ctypes.byref(opt), _ptr(seg_zn), _ptr(g_stat), _ptr(g_seg), _ptr(out), _ptr(ws),
+                              ws.numel(), _stream())
+    _lib.check(st, "tfsc_statistic_vjp")
+    return out
+
+
+def track(grid: GridSpec, bank: BankTensors) -> torch.Tensor:
+    """tfsc_track: [n][Nt][4] = (Phi, f, fdot, end code) at every tranche start (FP64)."""
+    L = lib()
+    out = torch.empty((bank.n, grid.n_tranches, 4), dtype=torch.float64, device=bank.mc.device)
+    g, bc = grid.c(), bank.c()
+    _lib.check(L.tfsc_track(ctypes.byref(g), ctypes.byref(bc), _ptr(out), _stream()), "tfsc_track")
+    return out
+
+
+class TFSCStatistic(torch.autograd.Function):
+    """Upsilon as a differentiable function of (ln Mc, f0, cos theta, phi, psi); the backward is the HIP VJP.
+
+    forward(ctx, ln_mc, f0, cos_theta, phi, psi, fixed) with ``fixed`` a dict holding grid, pixels, eta,
+    cos_iota, nseg_fixed and precision.  The segment layout is recomputed for the given parameters.
+    """
+
+    @staticmethod
+    def forward(ctx, ln_mc, f0, cos_theta, phi, psi, fixed):
+        grid, pixels = fixed["grid"], fixed["pixels"]
+        bank = BankTensors(torch.exp(ln_mc).contiguous(), fixed["eta"], f0.contiguous(), cos_theta.contiguous(),
+                           phi.contiguous(), psi.contiguous(), fixed["cos_iota"])
+        seg = segment_layout(grid, bank, fixed.get("nseg_fixed", 0))
+        res = bank_statistic(grid, pixels, bank, seg, precision=fixed.get("precision", "f32"), want_zn=True)
+        ctx.fixed = fixed
+        ctx.bank, ctx.seg, ctx.zn = bank, seg, res.seg_zn
+        return res.stat
+
+    @staticmethod
+    def backward(ctx, g):
+        fixed = ctx.fixed
+        gp = statistic_vjp(fixed["grid"], fixed["pixels"], ctx.bank, ctx.seg, ctx.zn,
+                           g_stat=g.contiguous().to(torch.float64), precision=fixed.get("precision", "f32"))
+        return gp[:, 0], gp[:, 1], gp[:, 2], gp[:, 3], gp[:, 4], None

@@ -1,0 +1,280 @@
+// C ABI of libtfsc.so: argument checks, workspace carving and launches.
+#include <string.h>
+
+#include "../../include/tfsc.h"
+#include "tfsc_kernels.hpp"
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+int device_cus() {
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (cached[dev] == 0) {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+        cached[dev] = cus;
+    }
+    return cached[dev];
+}
+
+bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+tfsc_status check_grid(const tfsc_grid *g) {
+    if (!g) return TFSC_ERR_ARG;
+    if (g->n_channels != 1 && g->n_channels != 2) return TFSC_ERR_SHAPE;
+    if (g->tranche_len < 64 || g->tranche_len > 4096 || !pow2(g->tranche_len)) return TFSC_ERR_SHAPE;
+    if (g->n_tranches < 1) return TFSC_ERR_SHAPE;
+    if (g->n_fresnel != 21) return TFSC_ERR_UNSUPPORTED;
+    if (!(g->dt > 0.0)) return TFSC_ERR_ARG;
+    if (!(g->tukey_alpha >= 0.0 && g->tukey_alpha <= 1.0)) return TFSC_ERR_ARG;
+    return TFSC_OK;
+}
+
+tfsc_status check_bank(const tfsc_bank *b) {
+    if (!b) return TFSC_ERR_ARG;
+    if (b->n < 0 || b->n > 0x7fffffffLL) return TFSC_ERR_SHAPE;
+    if (b->n > 0 && (!b->mc || !b->eta || !b->f0 || !b->cos_theta || !b->phi || !b->psi || !b->cos_iota))
+        return TFSC_ERR_ARG;
+    return TFSC_OK;
+}
+
+tfsc_status check_pixels(const tfsc_pixels *p, bool need_data) {
+    if (!p) return TFSC_ERR_ARG;
+    if (p->dtype < TFSC_F64 || p->dtype > TFSC_F16) return TFSC_ERR_DTYPE;
+    if (p->layout != TFSC_LAYER_MAJOR && p->layout != TFSC_TRANCHE_MAJOR) return TFSC_ERR_ARG;
+    if (need_data && !p->pix) return TFSC_ERR_ARG;
+    if (!p->inv_asd || !p->tranche_w) return TFSC_ERR_ARG;
+    if ((p->dtype == TFSC_BF16 || p->dtype == TFSC_F16) && !p->layer_scale) return TFSC_ERR_ARG;
+    return TFSC_OK;
+}
+
+struct Resolved {
+    int precision, schedule, block_waves, groups_per_cu;
+    const int32_t *order;
+};
+
+tfsc_status resolve_options(const tfsc_options *o, const tfsc_pixels *p, Resolved &r) {
+    r.precision = o ? o->precision : TFSC_F64;
+    r.schedule = o ? o->schedule : TFSC_SCHED_WAVE;
+    r.block_waves = (o && o->block_waves > 0) ? o->block_waves : 4;
+    r.groups_per_cu = (o && o->groups_per_cu > 0) ? o->groups_per_cu : 4;
+    r.order = o ? o->order : nullptr;
+    if (r.precision != TFSC_F64 && r.precision != TFSC_F32) return TFSC_ERR_DTYPE;
+    if (r.schedule != TFSC_SCHED_THREAD && r.schedule != TFSC_SCHED_WAVE) return TFSC_ERR_ARG;
+    if (r.block_waves > 16 || r.groups_per_cu > 64) return TFSC_ERR_ARG;
+    if (p) {
+        if (r.precision == TFSC_F64 && (p->dtype == TFSC_BF16 || p->dtype == TFSC_F16)) return TFSC_ERR_DTYPE;
+        if (r.precision == TFSC_F32 && p->dtype == TFSC_F64) return TFSC_ERR_DTYPE;
+        if (r.schedule == TFSC_SCHED_WAVE && p->layout != TFSC_LAYER_MAJOR) return TFSC_ERR_UNSUPPORTED;
+    }
+    return TFSC_OK;
+}
+
+size_t geo_bytes(int Nt) { return align_up(sizeof(double) * 18 * (size_t)Nt); }
+
+size_t ws_bytes_for(const tfsc_grid *g, int64_t n, int which) {
+    switch (which) {
+        case TFSC_WS_LAYOUT:
+            return align_up(sizeof(int64_t) * (size_t)((n + 255) / 256 + 1));
+        case TFSC_WS_STATISTIC:
+        case TFSC_WS_VJP:
+            return geo_bytes(g->n_tranches) + kAlign;
+        case TFSC_WS_TRANSFORM: {
+            size_t K = (size_t)g->tranche_len / 2 + 1;
+            return align_up(sizeof(float) * 2 * (size_t)g->n_channels * K * (size_t)g->n_tranches) +
+                   align_up(sizeof(uint32_t) * (size_t)g->n_channels * K);
+        }
+    }
+    return 0;
+}
+
+tfsc_status hip_status(hipError_t e) { return e == hipSuccess ? TFSC_OK : TFSC_ERR_HIP; }
+
+tfsc::StatLaunch stat_launch(const tfsc_grid *grid, const tfsc_pixels *pix, const tfsc_bank *bank,
+                             const tfsc_segments *seg, const Resolved &r, void *ws) {
+    tfsc::StatLaunch L;
+    memset(&L, 0, sizeof(L));
+    L.M = grid->tranche_len;
+    L.Nt = grid->n_tranches;
+    L.C = grid->n_channels;
+    L.dt = grid->dt;
+    L.pix_dtype = pix->dtype;
+    L.layout = pix->layout;
+    L.precision = r.precision == TFSC_F64 ? 0 : 1;
+    L.schedule = r.schedule;
+    L.block_waves = r.block_waves;
+    L.n_groups = device_cus() * r.groups_per_cu;
+    L.pix = pix->pix;
+    L.layer_scale = pix->layer_scale;
+    L.inv_asd = pix->inv_asd;
+    L.tranche_w = pix->tranche_w;
+    L.geo = reinterpret_cast<const double *>(ws);
+    L.n = bank->n;
+    L.mc = bank->mc;
+    L.eta = bank->eta;
+    L.f0 = bank->f0;
+    L.ct = bank->cos_theta;
+    L.phi = bank->phi;
+    L.psi = bank->psi;
+    L.ci = bank->cos_iota;
+    L.nseg = seg->nseg;
+    L.seg_offset = seg->seg_offset;
+    L.order = r.order;
+    char *tail = reinterpret_cast<char *>(ws) + geo_bytes(grid->n_tranches);
+    L.counter = reinterpret_cast<uint32_t *>(tail);
+    L.u_scale = reinterpret_cast<const double *>(tail + 8);
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tfsc_abi_version(void) { return TFSC_ABI_VERSION; }
+
+const char *tfsc_status_string(int s) {
+    switch (s) {
+        case TFSC_OK: return "ok";
+        case TFSC_ERR_ARG: return "invalid argument (null pointer or out-of-range value)";
+        case TFSC_ERR_SHAPE: return "inconsistent or unsupported sizes";
+        case TFSC_ERR_DTYPE: return "unsupported element type or precision combination";
+        case TFSC_ERR_WORKSPACE: return "workspace missing or too small";
+        case TFSC_ERR_UNSUPPORTED: return "request not supported by this build";
+        case TFSC_ERR_HIP: return "HIP runtime error";
+    }
+    return "unknown status";
+}
+
+size_t tfsc_workspace_bytes(const tfsc_grid *grid, int64_t n_templates, const tfsc_options *opt, int which) {
+    (void)opt;
+    if (check_grid(grid) != TFSC_OK || n_templates < 0) return 0;
+    return ws_bytes_for(grid, n_templates, which);
+}
+
+tfsc_status tfsc_segment_layout(const tfsc_grid *grid, const tfsc_bank *bank, tfsc_segments *seg, void *ws,
+                                size_t ws_bytes, void *stream) {
+    tfsc_status s;
+    if ((s = check_grid(grid)) != TFSC_OK) return s;
+    if ((s = check_bank(bank)) != TFSC_OK) return s;
+    if (!seg || !seg->seg_offset || (bank->n > 0 && !seg->nseg)) return TFSC_ERR_ARG;
+    if (seg->nseg_fixed < 0 || seg->nseg_fixed > (1 << 20)) return TFSC_ERR_ARG;
+    if (!ws || ws_bytes < ws_bytes_for(grid, bank->n, TFSC_WS_LAYOUT)) return TFSC_ERR_WORKSPACE;
+    tfsc::LayoutLaunch L;
+    L.n = bank->n;
+    L.mc = bank->mc;
+    L.eta = bank->eta;
+    L.f0 = bank->f0;
+    L.ct = bank->cos_theta;
+    L.ci = bank->cos_iota;
+    L.nseg_fixed = seg->nseg_fixed;
+    L.nseg = seg->nseg;
+    L.seg_offset = seg->seg_offset;
+    L.block_sums = reinterpret_cast<int64_t *>(ws);
+    return hip_status(tfsc::launch_layout(L, reinterpret_cast<hipStream_t>(stream)));
+}
+
+tfsc_status tfsc_bank_statistic(const tfsc_grid *grid, const tfsc_pixels *pix, const tfsc_bank *bank,
+                                const tfsc_segments *seg, const tfsc_options *opt, double *seg_terms, double *stat,
+                                double *seg_zn, int32_t *flags, void *ws, size_t ws_bytes, void *stream) {
+    tfsc_status s;
+    if ((s = check_grid(grid)) != TFSC_OK) return s;
+    if ((s = check_bank(bank)) != TFSC_OK) return s;
+    if ((s = check_pixels(pix, bank->n > 0)) != TFSC_OK) return s;
+    if (!seg || (bank->n > 0 && (!seg->nseg || !seg->seg_offset))) return TFSC_ERR_ARG;
+    Resolved r;
+    if ((s = resolve_options(opt, pix, r)) != TFSC_OK) return s;
+    if (bank->n > 0 && (!seg_terms || !stat || !flags)) return TFSC_ERR_ARG;
+    if (!ws || ws_bytes < ws_bytes_for(grid, bank->n, TFSC_WS_STATISTIC)) return TFSC_ERR_WORKSPACE;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (bank->n == 0) return TFSC_OK;
+    hipError_t e = tfsc::launch_geometry(grid->n_tranches, (double)grid->tranche_len * grid->dt,
+                                         reinterpret_cast<double *>(ws), st);
+    if (e != hipSuccess) return TFSC_ERR_HIP;
+    tfsc::StatLaunch L = stat_launch(grid, pix, bank, seg, r, ws);
+    e = tfsc::launch_weight_scale(grid->tranche_len / 2 + 1, pix->inv_asd, const_cast<double *>(L.u_scale), st);
+    if (e != hipSuccess) return TFSC_ERR_HIP;
+    L.seg_terms = seg_terms;
+    L.stat = stat;
+    L.seg_zn = seg_zn;
+    L.flags = flags;
+    return hip_status(tfsc::launch_statistic(L, st));
+}
+
+tfsc_status tfsc_statistic_vjp(const tfsc_grid *grid, const tfsc_pixels *pix, const tfsc_bank *bank,
+                               const tfsc_segments *seg, const tfsc_options *opt, const double *seg_zn,
+                               const double *g_stat, const double *g_seg, double *g_params, void *ws,
+                               size_t ws_bytes, void *stream) {
+    tfsc_status s;
+    if ((s = check_grid(grid)) != TFSC_OK) return s;
+    if ((s = check_bank(bank)) != TFSC_OK) return s;
+    if ((s = check_pixels(pix, bank->n > 0)) != TFSC_OK) return s;
+    if (!seg || (bank->n > 0 && (!seg->nseg || !seg->seg_offset))) return TFSC_ERR_ARG;
+    Resolved r;
+    if ((s = resolve_options(opt, pix, r)) != TFSC_OK) return s;
+    if (bank->n > 0 && (!seg_zn || !g_params || (!g_stat && !g_seg))) return TFSC_ERR_ARG;
+    if (!ws || ws_bytes < ws_bytes_for(grid, bank->n, TFSC_WS_VJP)) return TFSC_ERR_WORKSPACE;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (bank->n == 0) return TFSC_OK;
+    hipError_t e = tfsc::launch_geometry(grid->n_tranches, (double)grid->tranche_len * grid->dt,
+                                         reinterpret_cast<double *>(ws), st);
+    if (e != hipSuccess) return TFSC_ERR_HIP;
+    tfsc::VjpLaunch V;
+    V.s = stat_launch(grid, pix, bank, seg, r, ws);
+    e = tfsc::launch_weight_scale(grid->tranche_len / 2 + 1, pix->inv_asd, const_cast<double *>(V.s.u_scale), st);
+    if (e != hipSuccess) return TFSC_ERR_HIP;
+    V.seg_zn = seg_zn;
+    V.g_stat = g_stat;
+    V.g_seg = g_seg;
+    V.g_params = g_params;
+    return hip_status(tfsc::launch_vjp(V, st));
+}
+
+tfsc_status tfsc_transform(const tfsc_grid *grid, const void *x, int x_dtype, const double *psd0,
+                           const double *tranche_psd_scale, const uint8_t *tranche_keep, tfsc_pixels *out,
+                           void *ws, size_t ws_bytes, void *stream) {
+    tfsc_status s;
+    if ((s = check_grid(grid)) != TFSC_OK) return s;
+    if ((s = check_pixels(out, true)) != TFSC_OK) return s;
+    if (!x || !psd0 || !tranche_psd_scale || !tranche_keep) return TFSC_ERR_ARG;
+    if (x_dtype != TFSC_F64 && x_dtype != TFSC_F32) return TFSC_ERR_DTYPE;
+    if (out->dtype == TFSC_F64 && x_dtype != TFSC_F64) return TFSC_ERR_DTYPE;
+    if (out->dtype == TFSC_F64 && grid->tranche_len > 2048) return TFSC_ERR_UNSUPPORTED;
+    const bool q16 = out->dtype == TFSC_BF16 || out->dtype == TFSC_F16;
+    if (q16 && (!ws || ws_bytes < ws_bytes_for(grid, 0, TFSC_WS_TRANSFORM))) return TFSC_ERR_WORKSPACE;
+    tfsc::TransformLaunch L;
+    L.M = grid->tranche_len;
+    L.Nt = grid->n_tranches;
+    L.C = grid->n_channels;
+    L.dt = grid->dt;
+    L.alpha = grid->tukey_alpha;
+    L.x = x;
+    L.x_dtype = x_dtype;
+    L.psd0 = psd0;
+    L.mu = tranche_psd_scale;
+    L.keep = tranche_keep;
+    L.out_dtype = out->dtype;
+    L.out_layout = out->layout;
+    L.pix = out->pix;
+    L.layer_scale = out->layer_scale;
+    L.inv_asd = out->inv_asd;
+    L.tranche_w = out->tranche_w;
+    L.ws = ws;
+    return hip_status(tfsc::launch_transform(L, reinterpret_cast<hipStream_t>(stream)));
+}
+
+tfsc_status tfsc_track(const tfsc_grid *grid, const tfsc_bank *bank, double *out, void *stream) {
+    tfsc_status s;
+    if ((s = check_grid(grid)) != TFSC_OK) return s;
+    if ((s = check_bank(bank)) != TFSC_OK) return s;
+    if (bank->n > 0 && !out) return TFSC_ERR_ARG;
+    return hip_status(tfsc::launch_track(bank->n, grid->tranche_len, grid->n_tranches, grid->dt, bank->mc, bank->eta,
+                                         bank->f0, bank->cos_theta, bank->cos_iota, out,
+                                         reinterpret_cast<hipStream_t>(stream)));
+}
+
+}  // extern "C"

@@ -1,0 +1,395 @@
+// Device math for the semi-coherent time-frequency statistic (gfx950).
+//
+// * Track: 2PN TaylorT3 in theta = [eta (t_c - t) / (5 M)]^(-1/8), evaluated
+//   in FP64 with a fixed sequence of IEEE +, -, *, / and sqrt (this file is
+//   compiled with -ffp-contract=off), so the bin index, track end and N_seg
+//   are reproducible bit for bit on any IEEE machine.
+// * Tranche spectrum: the paper's Fresnel-kernel form, Eq. (fresnel-ft),
+//   rewritten exactly in bin-relative variables (see tranche_spectrum_bin).
+// * Response: rigid analytic orbits, single-link transfers and equal-arm
+//   TDI-1.5 A/E evaluated once per tranche at (t_m, f_m), Eq. (tdi2).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace tfsc {
+
+constexpr double kPi = 3.141592653589793;
+constexpr double kTwoPi = 6.283185307179586;
+constexpr double kMsunS = 4.925490947e-6;
+constexpr double kFdotRef = 1.34e-12;
+constexpr double kClight = 299792458.0;
+constexpr double kYearS = 31557600.0;
+constexpr double kArmM = 2.5e9;
+constexpr double kAuM = 1.495978707e11;
+constexpr int kHalfBins = 10;  // N_F = 2 * 10 + 1
+
+enum : int { kFlagInvalid = 1, kFlagEmpty = 2, kFlagBandEnd = 4, kFlagMergeEnd = 8, kFlagAllExcluded = 16 };
+
+// ------------------------------------------------------------------ track
+struct Track {
+    double eta, M, c8, a2, a3, a4, b2, b3, b4, tc;
+};
+
+__device__ __forceinline__ bool params_valid(double mc, double eta, double f0, double ct, double ci) {
+    if (!(mc > 0.0) || !(eta >= 0.01) || !(eta <= 0.25) || !(f0 > 0.0)) return false;
+    if (!(fabs(ct) <= 1.0) || !(fabs(ci) <= 1.0)) return false;
+    if (!isfinite(mc) || !isfinite(eta) || !isfinite(f0) || !isfinite(ct) || !isfinite(ci)) return false;
+    return true;
+}
+
+// Per-template constants: eta^(1/5) by 12 Newton steps from 1, M = Mc eta^(-3/5),
+// theta0 with f(theta0) = f0 by a 10-step cube root (from z^(1/4)) and 6 Newton
+// steps on the 2PN f(theta), t_c = 5 M theta0^-8 / eta.
+__device__ inline void track_init(Track &T, double mc, double eta, double f0) {
+    double y = 1.0;
+    for (int i = 0; i < 12; ++i) {
+        double y4 = (y * y) * (y * y);
+        y = (4.0 * y + eta / y4) / 5.0;
+    }
+    T.eta = eta;
+    T.M = (mc * kMsunS) / ((y * y) * y);
+    double e2 = eta * eta;
+    T.a2 = 743.0 / 2688.0 + (11.0 / 32.0) * eta;
+    T.a3 = -3.0 * kPi / 10.0;
+    T.a4 = (1855099.0 / 14450688.0 + (56975.0 / 258048.0) * eta) + (371.0 / 2048.0) * e2;
+    T.b2 = 3715.0 / 8064.0 + (55.0 / 96.0) * eta;
+    T.b3 = -3.0 * kPi / 4.0;
+    T.b4 = (9275495.0 / 14450688.0 + (284875.0 / 258048.0) * eta) + (1855.0 / 2048.0) * e2;
+    T.c8 = (8.0 * kPi) * T.M;
+    double z = T.c8 * f0;
+    double r = sqrt(sqrt(z));
+    for (int i = 0; i < 10; ++i) r = (2.0 * r + z / (r * r)) / 3.0;
+    double th = r;
+    for (int i = 0; i < 6; ++i) {
+        double th2 = th * th, th3 = th2 * th, th4 = th2 * th2;
+        double P = ((1.0 + T.a2 * th2) + T.a3 * th3) + T.a4 * th4;
+        double F = th3 * P - z;
+        double dP = ((3.0 + (5.0 * T.a2) * th2) + (6.0 * T.a3) * th3) + (7.0 * T.a4) * th4;
+        th = th - F / (th2 * dP);
+    }
+    double th2 = th * th, th4 = th2 * th2, th8 = th4 * th4;
+    T.tc = (5.0 * T.M) / (eta * th8);
+}
+
+// Phase Phi (rad, phi_c = 0), GW frequency f and its derivative at time t < t_c.
+__device__ inline void track_at(const Track &T, double t, double &Phi, double &f, double &fdot) {
+    double tau = T.tc - t;
+    double q = (T.eta * tau) / (5.0 * T.M);
+    double s = sqrt(sqrt(sqrt(q)));
+    double th = 1.0 / s;
+    double th2 = th * th, th3 = th2 * th, th4 = th2 * th2;
+    double Pf = ((1.0 + T.a2 * th2) + T.a3 * th3) + T.a4 * th4;
+    f = (th3 / T.c8) * Pf;
+    double dPf = ((3.0 + (5.0 * T.a2) * th2) + (6.0 * T.a3) * th3) + (7.0 * T.a4) * th4;
+    double dfdth = (th2 / T.c8) * dPf;
+    double th8 = th4 * th4, th9 = th8 * th;
+    double dthdt = (T.eta * th9) / (40.0 * T.M);
+    fdot = dfdth * dthdt;
+    double Pp = ((1.0 + T.b2 * th2) + T.b3 * th3) + T.b4 * th4;
+    double thm5 = 1.0 / (th4 * th);
+    Phi = -((2.0 * thm5) * Pp) / T.eta;
+}
+
+// Track end (paper Appendix A compactness + band edge + merger): returns 0 if
+// tranche starting at tm is active, else the flag naming the condition.
+__device__ __forceinline__ int track_step(const Track &T, double tm, double dT, double df, double fnyq,
+                                          double &Phi, double &f, double &fdot) {
+    if (tm + dT >= T.tc) return kFlagMergeEnd;
+    track_at(T, tm, Phi, f, fdot);
+    if ((f + fdot * dT >= fnyq - 11.0 * df) || (fdot * dT > 10.0 * df)) return kFlagBandEnd;
+    return 0;
+}
+
+// N_seg rule: 16 * 2^n, n = number of thresholds 1.34e-12 * 2^(3i-2) * sqrt 2 that fdot0 reaches.
+__device__ __forceinline__ int nseg_rule(double fdot0) {
+    int n = 0;
+    double r2 = sqrt(2.0);
+    for (int i = 1; i <= 4; ++i)
+        if (fdot0 >= kFdotRef * ldexp(r2, 3 * i - 2)) ++n;
+    return 16 << n;
+}
+
+// x / (2 pi) reduced to [-1/2, 1/2] revolutions (FMA-based two-constant reduction).
+__device__ __forceinline__ double phase_to_rev(double x) {
+    const double hi = 6.283185307179586232;      // 2 pi rounded to double
+    const double lo = 2.4492935982947064e-16;    // 2 pi - hi
+    double n = rint(x * (1.0 / kTwoPi));
+    double r = fma(-n, hi, x);
+    r = fma(-n, lo, r);
+    return r * (1.0 / kTwoPi);
+}
+
+__device__ __forceinline__ double frac_rev(double r) { return r - rint(r); }
+
+// ------------------------------------------------------------------ complex helpers
+template <class R>
+struct cx {
+    R re, im;
+};
+template <class R>
+__device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class R>
+__device__ __forceinline__ cx<R> cadd(cx<R> a, cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <class R>
+__device__ __forceinline__ cx<R> csub(cx<R> a, cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <class R>
+__device__ __forceinline__ cx<R> cscale(cx<R> a, R s) { return {a.re * s, a.im * s}; }
+
+// e^{2 pi i r} for r in revolutions (|r| <= 1/2 after reduction).
+__device__ __forceinline__ cx<double> expi_rev(double r) {
+    double s, c;
+    sincospi(2.0 * r, &s, &c);
+    return {c, s};
+}
+__device__ __forceinline__ cx<float> expi_rev(float r) {
+    // hardware sine/cosine take their argument in revolutions
+    return {__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r)};
+}
+__device__ __forceinline__ double sin_rev(double r) { return sinpi(2.0 * r); }
+__device__ __forceinline__ float sin_rev(float r) { return __builtin_amdgcn_sinf(r); }
+// sin(2 pi r) with relative (not only absolute) accuracy for small r
+__device__ __forceinline__ double sin_rev_accurate(double r) { return sinpi(2.0 * r); }
+__device__ __forceinline__ float sin_rev_accurate(float r) { return sinpif(2.0f * r); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// ------------------------------------------------------------------ response
+// Per-tranche geometry table (FP64, structure of arrays, row stride Nt):
+// rows 0..8 spacecraft positions p_i (light-seconds), rows 9..17 unit arm
+// vectors n_01, n_12, n_20 (from the first spacecraft to the second).
+constexpr int kGeoRows = 18;
+
+template <class R>
+struct Sky {
+    R k[3], u[3], v[3];
+    R c2, s2, ap, ci;
+    double kd[3];
+};
+
+template <class R>
+__device__ inline void sky_init(Sky<R> &S, double ct, double phi, double psi, double ci) {
+    double st = sqrt(1.0 - ct * ct);
+    double sp, cp, s2, c2;
+    sincos(phi, &sp, &cp);
+    sincos(2.0 * psi, &s2, &c2);
+    S.kd[0] = -st * cp;
+    S.kd[1] = -st * sp;
+    S.kd[2] = -ct;
+    for (int i = 0; i < 3; ++i) S.k[i] = (R)S.kd[i];
+    S.u[0] = (R)(ct * cp);
+    S.u[1] = (R)(ct * sp);
+    S.u[2] = (R)(-st);
+    S.v[0] = (R)sp;
+    S.v[1] = (R)(-cp);
+    S.v[2] = (R)0;
+    S.c2 = (R)c2;
+    S.s2 = (R)s2;
+    S.ap = (R)((1.0 + ci * ci) / 2.0);
+    S.ci = (R)ci;
+}
+
+template <class R>
+__device__ __forceinline__ R sinc_of(R x) {
+    // sin(x)/x for 0 <= x <= ~2 pi f L; series near 0
+    if (x < (R)1e-4) return (R)1 - x * x / (R)6;
+    return sin_rev(x * (R)(1.0 / kTwoPi)) * rcp(x);
+}
+
+// T_A, T_E at tranche m (time t_m) and frequency f.  geo: table above.
+template <class R>
+__device__ inline void transfer_ae(const Sky<R> &S, const double *__restrict__ geo, int m, int Nt, double f,
+                                   cx<R> &TA, cx<R> &TE) {
+    const double L = kArmM / kClight;
+    double kp[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        double px = geo[(3 * i + 0) * (size_t)Nt + m], py = geo[(3 * i + 1) * (size_t)Nt + m],
+               pz = geo[(3 * i + 2) * (size_t)Nt + m];
+        kp[i] = S.kd[0] * px + S.kd[1] * py + S.kd[2] * pz;
+    }
+    const R pfL = (R)(kPi * f * L);
+    cx<R> Gd[3], Gr[3];  // arm a: direction (s -> r) and reverse
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int s = a, r = (a + 1) % 3;
+        R n0 = (R)geo[(9 + 3 * a + 0) * (size_t)Nt + m];
+        R n1 = (R)geo[(9 + 3 * a + 1) * (size_t)Nt + m];
+        R n2 = (R)geo[(9 + 3 * a + 2) * (size_t)Nt + m];
+        R kn = S.k[0] * n0 + S.k[1] * n1 + S.k[2] * n2;
+        R nu = S.u[0] * n0 + S.u[1] * n1 + S.u[2] * n2;
+        R nv = S.v[0] * n0 + S.v[1] * n1 + S.v[2] * n2;
+        R xp0 = nu * nu - nv * nv, xx0 = (R)2 * nu * nv;
+        R xp = S.c2 * xp0 + S.s2 * xx0;
+        R xx = -S.s2 * xp0 + S.c2 * xx0;
+        cx<R> amp = {S.ap * xp, -S.ci * xx};
+        double rev = frac_rev(-0.5 * f * (L + (kp[s] + kp[r])));  // -pi f (L + k.(p_s + p_r)) / 2 pi
+        cx<R> E = expi_rev((R)rev);
+        cx<R> Ea = cmul(E, amp);
+        cx<R> B = {pfL * Ea.im, -pfL * Ea.re};  // -i pi f L e^{i ph} amp
+        Gd[a] = cscale(B, sinc_of(pfL * ((R)1 - kn)));
+        Gr[a] = cscale(B, sinc_of(pfL * ((R)1 + kn)));
+    }
+    // 0-based spacecraft: arm 0 = (0,1), arm 1 = (1,2), arm 2 = (2,0)
+    const cx<R> G01 = Gd[0], G10 = Gr[0], G12 = Gd[1], G21 = Gr[1], G20 = Gd[2], G02 = Gr[2];
+    // D = e^{-2 pi i f L};  1 - D^2 = 2 i sin(2 pi f L) D exactly.  The sine is taken of an
+    // argument folded into [-1/4, 1/4] revolutions, so it keeps full relative precision at
+    // the transfer nulls f = n / (2L) where 1 - D^2 computed directly would cancel.
+    const double rl = frac_rev(f * L);
+    cx<R> D = expi_rev((R)(-rl));
+    const double rf = rl > 0.25 ? 0.5 - rl : (rl < -0.25 ? -0.5 - rl : rl);
+    const R s2 = sin_rev_accurate((R)rf);
+    cx<R> om = {(R)-2 * s2 * D.im, (R)2 * s2 * D.re};
+    cx<R> TX = cmul(om, csub(cadd(G20, cmul(D, G02)), cadd(G10, cmul(D, G01))));
+    cx<R> TY = cmul(om, csub(cadd(G01, cmul(D, G10)), cadd(G21, cmul(D, G12))));
+    cx<R> TZ = cmul(om, csub(cadd(G12, cmul(D, G21)), cadd(G02, cmul(D, G20))));
+    const R is2 = (R)0.70710678118654752440, is6 = (R)0.40824829046386301637;
+    TA = cscale(csub(TZ, TX), is2);
+    TE = cscale(cadd(csub(TX, cscale(TY, (R)2)), TZ), is6);
+}
+
+// ------------------------------------------------------------------ tranche spectrum
+// Per-tranche constants of the Fresnel-kernel spectrum in bin units.  With
+// x = f_m dT - k_c in (-1, 0], beta = fdot dT^2 and s = sqrt(2 / beta), the
+// Fresnel arguments of bin k = k_c + j are v0 = s (x - j), v1 = s (x - j + beta),
+// and since f_k dT is an integer, Eq. (fresnel-ft) becomes
+//   h_j = P { (sgn v1 - sgn v0) (1+i)/2 e^{i(phi_m - pi (x-j)^2 / beta)}
+//             - sgn v1 (g1 + i f1) e^{i phi_end} + sgn v0 (g0 + i f0) e^{i phi_m} },
+// P = A / sqrt(2 fdot), phi_end = phi_m + 2 pi x + pi beta, using
+// C(z) + i S(z) = sgn z [(1+i)/2 - (g(|z|) + i f(|z|)) e^{i pi z^2 / 2}] with
+// the paper's f, g (rational for |z| <= 6, f = 1/(pi |z|), g = 0 above).  When
+// both |v| > 6 and no bin frequency is crossed this is
+//   h_j = i Q (e^{i phi_m} / (x - j) - e^{i phi_end} / (x - j + beta)),  Q = A dT / (2 pi).
+template <class R>
+struct TrancheSpec {
+    R x, beta, s, r6, P, Q;
+    cx<R> E0, E1;
+    double rev0;  // phi_m in revolutions, reduced
+};
+
+template <class R>
+__device__ __forceinline__ void fresnel_fg(R av, R &f, R &g) {
+    if (av > (R)6) {
+        f = rcp((R)kPi * av);
+        g = (R)0;
+    } else {
+        R a2 = av * av;
+        f = ((R)1 + (R)0.926 * av) / ((R)2 + (R)1.792 * av + (R)3.104 * a2);
+        g = (R)1 / ((R)2 + (R)4.142 * av + (R)3.492 * a2 + (R)6.670 * a2 * av);
+    }
+}
+
+template <class R>
+__device__ __forceinline__ R sgn(R v) {
+    return v > (R)0 ? (R)1 : (v < (R)0 ? (R)-1 : (R)0);
+}
+
+template <class R>
+__device__ __forceinline__ cx<R> tranche_spectrum_bin(const TrancheSpec<R> &ts, int j) {
+    R xj = ts.x - (R)j;
+    R xj1 = xj + ts.beta;
+    if (xj > ts.r6 || xj1 < -ts.r6) {
+        // fast path: asymptotic Fresnel on both edges, no stationary bin
+        R a = rcp(xj), b = rcp(xj1);
+        R re = ts.E0.re * a - ts.E1.re * b;
+        R im = ts.E0.im * a - ts.E1.im * b;
+        return {-ts.Q * im, ts.Q * re};
+    }
+    R v0 = ts.s * xj, v1 = ts.s * xj1;
+    R sg0 = sgn(v0), sg1 = sgn(v1);
+    R f0, g0, f1, g1;
+    fresnel_fg(fabs(v0), f0, g0);
+    fresnel_fg(fabs(v1), f1, g1);
+    cx<R> t0 = cmul(cx<R>{sg0 * g0, sg0 * f0}, ts.E0);
+    cx<R> t1 = cmul(cx<R>{sg1 * g1, sg1 * f1}, ts.E1);
+    cx<R> h = csub(t0, t1);
+    R ds = sg1 - sg0;
+    if (ds != (R)0) {
+        // bin frequency crossed inside the tranche: stationary-phase term
+        double rv = frac_rev(ts.rev0 - (double)(xj * xj / (ts.beta * (R)2)));
+        cx<R> e = expi_rev((R)rv);
+        R hh = ds * (R)0.5;
+        h.re += hh * (e.re - e.im);
+        h.im += hh * (e.re + e.im);
+    }
+    return cscale(h, ts.P);
+}
+
+// Tranche constants from the FP64 track.  Returns k_c.  Bin index, offset and
+// phases come from FP64; the rest is formed in R.
+template <class R>
+__device__ __forceinline__ int tranche_setup(TrancheSpec<R> &ts, double Phi, double f, double fdot, double dT) {
+    double fT = f * dT;
+    double kc = ceil(fT);
+    double x = fT - kc;
+    double beta = (fdot * dT) * dT;
+    double rev0 = phase_to_rev(Phi);
+    double rev1 = frac_rev(rev0 + x + 0.5 * beta);
+    ts.x = (R)x;
+    ts.beta = (R)beta;
+    if constexpr (sizeof(R) == 8) {
+        ts.s = sqrt(2.0 / beta);
+        double A = pow(f, 2.0 / 3.0);
+        ts.P = A / sqrt(2.0 * fdot);
+        ts.Q = A * dT / kTwoPi;
+    } else {
+        float b = (float)beta;
+        ts.s = sqrtf(2.0f * rcp(b));
+        float A = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf((float)f) * (2.0f / 3.0f));
+        ts.P = A * __builtin_amdgcn_rsqf((float)(2.0 * fdot));
+        ts.Q = A * (float)(dT / kTwoPi);
+    }
+    ts.r6 = (R)6 / ts.s;
+    ts.E0 = expi_rev((R)rev0);
+    ts.E1 = expi_rev((R)rev1);
+    ts.rev0 = rev0;
+    return (int)kc;
+}
+
+// ------------------------------------------------------------------ pixel loads
+template <class PixT>
+struct PixTraits;
+template <>
+struct PixTraits<double> {
+    using R = double;
+    static constexpr bool scaled = false;
+    __device__ static __forceinline__ cx<double> load(const void *p, size_t idx) {
+        double2 v = reinterpret_cast<const double2 *>(p)[idx];
+        return {v.x, v.y};
+    }
+};
+template <>
+struct PixTraits<float> {
+    using R = float;
+    static constexpr bool scaled = false;
+    __device__ static __forceinline__ cx<float> load(const void *p, size_t idx) {
+        float2 v = reinterpret_cast<const float2 *>(p)[idx];
+        return {v.x, v.y};
+    }
+};
+template <>
+struct PixTraits<__half> {
+    using R = float;
+    static constexpr bool scaled = true;
+    __device__ static __forceinline__ cx<float> load(const void *p, size_t idx) {
+        __half2 v = reinterpret_cast<const __half2 *>(p)[idx];
+        float2 f = __half22float2(v);
+        return {f.x, f.y};
+    }
+};
+template <>
+struct PixTraits<__hip_bfloat16> {
+    using R = float;
+    static constexpr bool scaled = true;
+    __device__ static __forceinline__ cx<float> load(const void *p, size_t idx) {
+        uint32_t w = reinterpret_cast<const uint32_t *>(p)[idx];
+        return {__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u)};
+    }
+};
+
+}  // namespace tfsc

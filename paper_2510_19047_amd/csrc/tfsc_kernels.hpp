@@ -1,0 +1,70 @@
+// Internal launch descriptors shared by the C ABI layer and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tfsc {
+
+struct LayoutLaunch {
+    int64_t n;
+    const double *mc, *eta, *f0, *ct, *ci;
+    int nseg_fixed;
+    int32_t *nseg;
+    int64_t *seg_offset;
+    int64_t *block_sums;  // workspace, ceil(n / 256) entries
+};
+
+struct StatLaunch {
+    int M, Nt, C;
+    double dt;
+    int pix_dtype;  // tfsc_dtype
+    int layout;     // tfsc_layout
+    int precision;  // 0 FP64, 1 FP32
+    int schedule;   // 0 THREAD, 1 WAVE
+    int n_groups, block_waves;
+    const void *pix;
+    const float *layer_scale;
+    const double *inv_asd, *tranche_w, *geo;
+    const double *u_scale;  // device scalar written by launch_weight_scale
+    int64_t n;
+    const double *mc, *eta, *f0, *ct, *phi, *psi, *ci;
+    const int32_t *nseg;
+    const int64_t *seg_offset;
+    const int32_t *order;
+    double *seg_terms, *stat, *seg_zn;
+    int32_t *flags;
+    uint32_t *counter;
+};
+
+struct VjpLaunch {
+    StatLaunch s;  // seg_terms / stat / flags unused
+    const double *seg_zn;
+    const double *g_stat, *g_seg;
+    double *g_params;
+};
+
+struct TransformLaunch {
+    int M, Nt, C;
+    double dt, alpha;
+    const void *x;
+    int x_dtype;
+    const double *psd0, *mu;
+    const uint8_t *keep;
+    int out_dtype, out_layout;
+    void *pix;
+    float *layer_scale;
+    double *inv_asd, *tranche_w;
+    void *ws;  // FP32 staging for 16-bit outputs
+};
+
+hipError_t launch_layout(const LayoutLaunch &L, hipStream_t st);
+hipError_t launch_geometry(int Nt, double dT, double *geo, hipStream_t st);
+hipError_t launch_weight_scale(int K, const double *inv_asd, double *scale_out, hipStream_t st);
+hipError_t launch_statistic(const StatLaunch &L, hipStream_t st);
+hipError_t launch_vjp(const VjpLaunch &L, hipStream_t st);
+hipError_t launch_transform(const TransformLaunch &L, hipStream_t st);
+hipError_t launch_track(int64_t n, int M, int Nt, double dt, const double *mc, const double *eta, const double *f0,
+                        const double *ct, const double *ci, double *out, hipStream_t st);
+
+}  // namespace tfsc

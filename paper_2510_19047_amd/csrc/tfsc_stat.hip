@@ -1,0 +1,553 @@
+// Statistic kernels: per-template setup (segment layout), per-tranche
+// geometry table, and the bank statistic under two schedules.
+//
+//   THREAD  one thread per template walks its tranches and bins in order;
+//           this is the mapping the paper describes for its own GPU code.
+//   WAVE    one 64-lane wavefront per template, lane l on tranche m0 + l,
+//           so the 21 per-bin gathers of a wave read 64 consecutive tranches
+//           of one frequency layer (contiguous in the LAYER_MAJOR store);
+//           tranche sums are reduced across lanes per segment; a persistent
+//           grid pulls templates from a device counter.
+//
+// No kernel allocates; all scratch lives in the caller's workspace.
+#include "tfsc_device.hpp"
+#include "tfsc_kernels.hpp"
+
+namespace tfsc {
+
+// ------------------------------------------------------------------ layout
+__global__ void k_layout_nseg(int64_t n, const double *__restrict__ mc, const double *__restrict__ eta,
+                              const double *__restrict__ f0, const double *__restrict__ ct,
+                              const double *__restrict__ ci, int nseg_fixed, int32_t *__restrict__ nseg,
+                              int64_t *__restrict__ block_sums) {
+    __shared__ int64_t sh[256];
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int v = 0;
+    if (i < n) {
+        bool ok = params_valid(mc[i], eta[i], f0[i], ct[i], ci[i]);
+        Track T;
+        track_init(T, ok ? mc[i] : 30.0, ok ? eta[i] : 0.25, ok ? f0[i] : 0.01);
+        double Phi, f, fd;
+        track_at(T, 0.0, Phi, f, fd);
+        v = nseg_fixed > 0 ? nseg_fixed : nseg_rule(fd);
+        nseg[i] = v;
+    }
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) block_sums[blockIdx.x] = sh[0];
+}
+
+// exclusive scan of block sums in place (one block of 1024 threads)
+__global__ void k_scan_blocks(int64_t nb, int64_t *__restrict__ block_sums) {
+    __shared__ int64_t sh[1024];
+    __shared__ int64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int64_t base = 0; base < nb; base += 1024) {
+        int64_t idx = base + threadIdx.x;
+        int64_t v = idx < nb ? block_sums[idx] : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            int64_t t = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (idx < nb) block_sums[idx] = carry + sh[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += sh[1023];
+        __syncthreads();
+    }
+}
+
+__global__ void k_layout_offsets(int64_t n, const int32_t *__restrict__ nseg, const int64_t *__restrict__ block_base,
+                                 int64_t *__restrict__ seg_offset) {
+    __shared__ int64_t sh[256];
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t v = i < n ? nseg[i] : 0;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        int64_t t = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    if (i < n) seg_offset[i + 1] = block_base[blockIdx.x] + sh[threadIdx.x];
+    if (i == 0) seg_offset[0] = 0;
+}
+
+// ------------------------------------------------------------------ geometry
+// Rigid analytic orbits (first order in e = L / (2 sqrt 3 R)) at t_m = m dT.
+__global__ void k_geometry(int Nt, double dT, double *__restrict__ geo) {
+    int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= Nt) return;
+    const double L = kArmM / kClight, R = kAuM / kClight;
+    const double e = L / (2.0 * sqrt(3.0) * R);
+    double t = (double)m * dT;
+    double a = kTwoPi * t / kYearS;
+    double p[3][3];
+    for (int i = 0; i < 3; ++i) {
+        double b = kTwoPi * i / 3.0;
+        double sa, ca, s2, c2, sb, cb, s1, c1;
+        sincos(a, &sa, &ca);
+        sincos(2.0 * a - b, &s2, &c2);
+        sincos(b, &sb, &cb);
+        sincos(a - b, &s1, &c1);
+        p[i][0] = R * ca + 0.5 * e * R * (c2 - 3.0 * cb);
+        p[i][1] = R * sa + 0.5 * e * R * (s2 - 3.0 * sb);
+        p[i][2] = -sqrt(3.0) * e * R * c1;
+    }
+    for (int i = 0; i < 3; ++i)
+        for (int x = 0; x < 3; ++x) geo[(3 * i + x) * (size_t)Nt + m] = p[i][x];
+    for (int a2 = 0; a2 < 3; ++a2) {
+        int s = a2, r = (a2 + 1) % 3;
+        double d[3], nn = 0.0;
+        for (int x = 0; x < 3; ++x) {
+            d[x] = p[r][x] - p[s][x];
+            nn += d[x] * d[x];
+        }
+        nn = sqrt(nn);
+        for (int x = 0; x < 3; ++x) geo[(9 + 3 * a2 + x) * (size_t)Nt + m] = d[x] / nn;
+    }
+}
+
+// Exact power-of-two normalisation of the template weights: scale = 2^-e with e the
+// binary exponent of max_k u_k, so that max_k u_k * scale lies in [1/2, 1).  Upsilon is
+// invariant to it; it keeps |h u|^2 inside the FP32 range (u_k ~ 1e20 in strain units).
+__global__ void k_weight_scale(int K, const double *__restrict__ inv_asd, double *__restrict__ scale_out) {
+    __shared__ double sh[256];
+    double v = 0.0;
+    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+        double u = inv_asd[k];
+        if (isfinite(u) && u > v) v = u;
+    }
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) sh[threadIdx.x] = fmax(sh[threadIdx.x], sh[threadIdx.x + o]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        int e = 0;
+        double mx = sh[0];
+        if (mx > 0.0) frexp(mx, &e);
+        scale_out[0] = ldexp(1.0, -e);
+    }
+}
+
+__global__ void k_zero_u32(uint32_t *p, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// ------------------------------------------------------------------ common pieces
+struct StatArgs {
+    int M, K, Nt, C;
+    double dt, dT, df, fnyq;
+    const void *pix;
+    const float *layer_scale;
+    const double *inv_asd;
+    const double *tranche_w;
+    const double *geo;
+    const double *u_scale;  // [1], see k_weight_scale
+    int64_t n;
+    const double *mc, *eta, *f0, *ct, *phi, *psi, *ci;
+    const int32_t *nseg;
+    const int64_t *seg_offset;
+    const int32_t *order;
+    double *seg_terms, *stat, *seg_zn;
+    int32_t *flags;
+    uint32_t *counter;
+};
+
+template <class R>
+struct SegAcc {
+    double zr, zi, N, total;
+    int cur;
+    bool any;
+};
+
+// close segments [acc.cur, upto) writing Upsilon_n and (z_n, N_n)
+__device__ __forceinline__ void close_segments(SegAcc<double> &acc, int upto, int64_t off, double *seg_terms,
+                                               double *seg_zn, bool writer) {
+    while (acc.cur < upto) {
+        double v = acc.N > 0.0 ? 2.0 * (acc.zr * acc.zr + acc.zi * acc.zi) / acc.N : 0.0;
+        if (writer) {
+            seg_terms[off + acc.cur] = v;
+            if (seg_zn) {
+                seg_zn[3 * (off + acc.cur) + 0] = acc.zr;
+                seg_zn[3 * (off + acc.cur) + 1] = acc.zi;
+                seg_zn[3 * (off + acc.cur) + 2] = acc.N;
+            }
+        }
+        if (acc.N > 0.0) acc.any = true;
+        acc.total += v;
+        acc.zr = acc.zi = acc.N = 0.0;
+        ++acc.cur;
+    }
+}
+
+// Sum over the 21 bins of tranche m: P_c = sum conj(D_ck) h_k u_k, Q = sum |h_k u_k|^2.
+template <int C, class R, class PixT, int LAYOUT, class U>
+__device__ __forceinline__ void tranche_bins(const StatArgs &a, const TrancheSpec<R> &ts, int kc, int m,
+                                             const U *__restrict__ u_tab, U u_mul, const float *__restrict__ sc_tab,
+                                             cx<R> (&P)[C], R &Q) {
+    using PT = PixTraits<PixT>;
+#pragma unroll
+    for (int c = 0; c < C; ++c) P[c] = {(R)0, (R)0};
+    Q = (R)0;
+    const int kmax = a.M / 2 - 1;
+#pragma unroll 3
+    for (int j = -kHalfBins; j <= kHalfBins; ++j) {
+        int k = kc + j;
+        if (k < 1 || k > kmax) continue;
+        cx<R> h = tranche_spectrum_bin(ts, j);
+        R w = (R)(u_tab[k] * u_mul);
+        cx<R> g = {h.re * w, h.im * w};
+        Q += g.re * g.re + g.im * g.im;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            size_t idx = LAYOUT == 0 ? ((size_t)(c * a.K + k) * a.Nt + m) : ((size_t)(c * a.Nt + m) * a.K + k);
+            const auto Dl = PT::load(a.pix, idx);
+            cx<R> D = {(R)Dl.re, (R)Dl.im};
+            if constexpr (PT::scaled) {
+                R s = (R)sc_tab[c * a.K + k];
+                D.re *= s;
+                D.im *= s;
+            }
+            P[c].re += D.re * g.re + D.im * g.im;
+            P[c].im += D.re * g.im - D.im * g.re;
+        }
+    }
+}
+
+// Tranche contribution z_m = w_m sum_c T_c P_c, N_m = w_m^2 (sum_c |T_c|^2) Q.
+template <int C, class R>
+__device__ __forceinline__ void tranche_combine(const Sky<R> &S, const StatArgs &a, int m, double f, R wm,
+                                                const cx<R> (&P)[C], R Q, R &zr, R &zi, R &nn) {
+    cx<R> TA, TE;
+    transfer_ae(S, a.geo, m, a.Nt, f, TA, TE);
+    cx<R> z = cmul(TA, P[0]);
+    R tt = TA.re * TA.re + TA.im * TA.im;
+    if constexpr (C == 2) {
+        z = cadd(z, cmul(TE, P[1]));
+        tt += TE.re * TE.re + TE.im * TE.im;
+    }
+    zr = wm * z.re;
+    zi = wm * z.im;
+    nn = wm * wm * tt * Q;
+}
+
+// ------------------------------------------------------------------ THREAD schedule
+template <int C, class R, class PixT, int LAYOUT>
+__global__ __launch_bounds__(256) void k_stat_thread(StatArgs a) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= a.n) return;
+    int64_t i = a.order ? (int64_t)a.order[t] : t;
+    if (i < 0 || i >= a.n) return;  // malformed processing order: skip rather than fault
+    const int ns = a.nseg[i];
+    const int64_t off = a.seg_offset[i];
+    SegAcc<double> acc{0, 0, 0, 0, 0, false};
+    int flag = 0;
+    if (!params_valid(a.mc[i], a.eta[i], a.f0[i], a.ct[i], a.ci[i])) {
+        flag = kFlagInvalid;
+        close_segments(acc, ns, off, a.seg_terms, a.seg_zn, true);
+        a.stat[i] = 0.0;
+        a.flags[i] = flag;
+        return;
+    }
+    Track T;
+    track_init(T, a.mc[i], a.eta[i], a.f0[i]);
+    Sky<R> S;
+    sky_init(S, a.ct[i], a.phi[i], a.psi[i], a.ci[i]);
+    const double u_mul = a.u_scale[0];
+    int m = 0;
+    for (; m < a.Nt; ++m) {
+        double tm = (double)m * a.dT, Phi, f, fdot;
+        int code = track_step(T, tm, a.dT, a.df, a.fnyq, Phi, f, fdot);
+        if (code) {
+            flag |= code;
+            break;
+        }
+        int sg = (int)(((int64_t)m * ns) / a.Nt);
+        close_segments(acc, sg, off, a.seg_terms, a.seg_zn, true);
+        double wmd = a.tranche_w[m];
+        if (wmd == 0.0) continue;
+        TrancheSpec<R> ts;
+        int kc = tranche_setup(ts, Phi, f, fdot, a.dT);
+        cx<R> P[C];
+        R Q;
+        tranche_bins<C, R, PixT, LAYOUT, double>(a, ts, kc, m, a.inv_asd, u_mul, a.layer_scale, P, Q);
+        R zr, zi, nn;
+        tranche_combine<C, R>(S, a, m, f, (R)wmd, P, Q, zr, zi, nn);
+        acc.zr += zr;
+        acc.zi += zi;
+        acc.N += nn;
+    }
+    if (m == 0) flag |= kFlagEmpty;
+    close_segments(acc, ns, off, a.seg_terms, a.seg_zn, true);
+    if (!acc.any && m > 0) flag |= kFlagAllExcluded;
+    a.stat[i] = acc.total;
+    a.flags[i] = flag;
+}
+
+// ------------------------------------------------------------------ WAVE schedule
+template <class R>
+__device__ __forceinline__ R wave_sum(R v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int C, class R, class PixT>
+__global__ __launch_bounds__(256) void k_stat_wave(StatArgs a) {
+    // template weights u_k (and 16-bit layer scales) staged in LDS once per block
+    extern __shared__ unsigned char smem_raw[];
+    R *u_tab = reinterpret_cast<R *>(smem_raw);
+    float *sc_tab = reinterpret_cast<float *>(smem_raw + sizeof(R) * a.K);
+    const double u_mul = a.u_scale[0];
+    for (int k = threadIdx.x; k < a.K; k += blockDim.x) u_tab[k] = (R)(a.inv_asd[k] * u_mul);
+    if constexpr (PixTraits<PixT>::scaled)
+        for (int k = threadIdx.x; k < C * a.K; k += blockDim.x) sc_tab[k] = a.layer_scale[k];
+    __syncthreads();
+
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        // Work fetch in converged code: every lane joins one atomic (lane 0 adds 1, the
+        // others 0) and readfirstlane makes the item a wave-uniform scalar, so no
+        // cross-lane broadcast depends on reconvergence after a lane-0-only branch.
+        const uint32_t mine = atomicAdd(a.counter, lane == 0 ? 1u : 0u);
+        const uint32_t item = __builtin_amdgcn_readfirstlane(mine);
+        if ((int64_t)item >= a.n) break;
+        const int64_t i = a.order ? (int64_t)__builtin_amdgcn_readfirstlane(a.order[item]) : (int64_t)item;
+        if (i < 0 || i >= a.n) continue;  // malformed processing order: skip rather than fault
+        const int ns = a.nseg[i];
+        const int64_t off = a.seg_offset[i];
+        SegAcc<double> acc{0, 0, 0, 0, 0, false};
+        int flag = 0;
+        const bool writer = lane == 0;
+        if (!params_valid(a.mc[i], a.eta[i], a.f0[i], a.ct[i], a.ci[i])) {
+            close_segments(acc, ns, off, a.seg_terms, a.seg_zn, writer);
+            if (writer) {
+                a.stat[i] = 0.0;
+                a.flags[i] = kFlagInvalid;
+            }
+            continue;
+        }
+        Track T;
+        track_init(T, a.mc[i], a.eta[i], a.f0[i]);
+        Sky<R> S;
+        sky_init(S, a.ct[i], a.phi[i], a.psi[i], a.ci[i]);
+        int m_end = a.Nt;
+        for (int m0 = 0; m0 < m_end; m0 += 64) {
+            const int m = m0 + lane;
+            const bool inr = m < a.Nt;
+            double Phi = 0.0, f = 0.0, fdot = 0.0;
+            int code = inr ? track_step(T, (double)m * a.dT, a.dT, a.df, a.fnyq, Phi, f, fdot) : 0;
+            const uint64_t viol = __ballot(code != 0);
+            int lim = a.Nt;
+            if (viol) {
+                const int first = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)viol) - 1);
+                lim = m0 + first;
+                flag |= __builtin_amdgcn_readlane(code, first);
+                m_end = lim;
+            }
+            const bool active = inr && m < lim;
+            R zr = 0, zi = 0, nn = 0;
+            if (active) {
+                const double wmd = a.tranche_w[m];
+                if (wmd != 0.0) {
+                    TrancheSpec<R> ts;
+                    int kc = tranche_setup(ts, Phi, f, fdot, a.dT);
+                    cx<R> P[C];
+                    R Q;
+                    tranche_bins<C, R, PixT, 0, R>(a, ts, kc, m, u_tab, (R)1, sc_tab, P, Q);
+                    tranche_combine<C, R>(S, a, m, f, (R)wmd, P, Q, zr, zi, nn);
+                }
+            }
+            // segmented reduction over the lanes of this chunk
+            const int last = min(min(m0 + 63, lim - 1), a.Nt - 1);
+            if (last >= m0) {
+                const int s_first = (int)(((int64_t)m0 * ns) / a.Nt);
+                const int s_last = (int)(((int64_t)last * ns) / a.Nt);
+                const int my_s = (int)(((int64_t)m * ns) / a.Nt);
+                for (int s = s_first; s <= s_last; ++s) {
+                    const bool mine = active && my_s == s;
+                    R vr = mine ? zr : (R)0, vi = mine ? zi : (R)0, vn = mine ? nn : (R)0;
+                    vr = wave_sum(vr);
+                    vi = wave_sum(vi);
+                    vn = wave_sum(vn);
+                    close_segments(acc, s, off, a.seg_terms, a.seg_zn, writer);
+                    acc.zr += (double)vr;
+                    acc.zi += (double)vi;
+                    acc.N += (double)vn;
+                }
+            }
+            if (viol) break;
+        }
+        if (m_end == 0) flag |= kFlagEmpty;
+        close_segments(acc, ns, off, a.seg_terms, a.seg_zn, writer);
+        if (!acc.any && m_end > 0) flag |= kFlagAllExcluded;
+        if (writer) {
+            a.stat[i] = acc.total;
+            a.flags[i] = flag;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ track inspection
+__global__ void k_track(int64_t n, int Nt, double dt, double dT, const double *__restrict__ mc,
+                        const double *__restrict__ eta, const double *__restrict__ f0, const double *__restrict__ ct,
+                        const double *__restrict__ ci, double *__restrict__ out) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * Nt) return;
+    int64_t i = e / Nt;
+    int m = (int)(e % Nt);
+    double *o = out + 4 * e;
+    o[0] = o[1] = o[2] = 0.0;
+    if (!params_valid(mc[i], eta[i], f0[i], ct[i], ci[i])) {
+        o[3] = (double)kFlagInvalid;
+        return;
+    }
+    Track T;
+    track_init(T, mc[i], eta[i], f0[i]);
+    double Phi = 0.0, f = 0.0, fdot = 0.0;
+    int code = track_step(T, (double)m * dT, dT, 1.0 / dT, 0.5 / dt, Phi, f, fdot);
+    if (code != kFlagMergeEnd) {
+        o[0] = Phi;
+        o[1] = f;
+        o[2] = fdot;
+    }
+    o[3] = (double)code;
+}
+
+hipError_t launch_track(int64_t n, int M, int Nt, double dt, const double *mc, const double *eta, const double *f0,
+                        const double *ct, const double *ci, double *out, hipStream_t st) {
+    int64_t tot = n * (int64_t)Nt;
+    if (tot == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_track, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, Nt, dt, (double)M * dt, mc,
+                       eta, f0, ct, ci, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ launchers
+hipError_t launch_layout(const LayoutLaunch &L, hipStream_t st) {
+    int64_t nb = (L.n + 255) / 256;
+    if (L.n == 0) {
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, reinterpret_cast<uint32_t *>(L.seg_offset), 2);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_layout_nseg, dim3((unsigned)nb), dim3(256), 0, st, L.n, L.mc, L.eta, L.f0, L.ct, L.ci,
+                       L.nseg_fixed, L.nseg, L.block_sums);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, st, nb, L.block_sums);
+    hipLaunchKernelGGL(k_layout_offsets, dim3((unsigned)nb), dim3(256), 0, st, L.n, L.nseg, L.block_sums,
+                       L.seg_offset);
+    return hipGetLastError();
+}
+
+hipError_t launch_geometry(int Nt, double dT, double *geo, hipStream_t st) {
+    hipLaunchKernelGGL(k_geometry, dim3((Nt + 127) / 128), dim3(128), 0, st, Nt, dT, geo);
+    return hipGetLastError();
+}
+
+static StatArgs make_args(const StatLaunch &L) {
+    StatArgs a;
+    a.M = L.M;
+    a.K = L.M / 2 + 1;
+    a.Nt = L.Nt;
+    a.C = L.C;
+    a.dt = L.dt;
+    a.dT = (double)L.M * L.dt;
+    a.df = 1.0 / a.dT;
+    a.fnyq = 0.5 / L.dt;
+    a.pix = L.pix;
+    a.layer_scale = L.layer_scale;
+    a.inv_asd = L.inv_asd;
+    a.tranche_w = L.tranche_w;
+    a.geo = L.geo;
+    a.u_scale = L.u_scale;
+    a.n = L.n;
+    a.mc = L.mc;
+    a.eta = L.eta;
+    a.f0 = L.f0;
+    a.ct = L.ct;
+    a.phi = L.phi;
+    a.psi = L.psi;
+    a.ci = L.ci;
+    a.nseg = L.nseg;
+    a.seg_offset = L.seg_offset;
+    a.order = L.order;
+    a.seg_terms = L.seg_terms;
+    a.stat = L.stat;
+    a.seg_zn = L.seg_zn;
+    a.flags = L.flags;
+    a.counter = L.counter;
+    return a;
+}
+
+template <int C, class R, class PixT>
+static hipError_t launch_thread_t(const StatArgs &a, int layout, hipStream_t st) {
+    dim3 grid((unsigned)((a.n + 255) / 256)), block(256);
+    if (layout == 0)
+        hipLaunchKernelGGL((k_stat_thread<C, R, PixT, 0>), grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL((k_stat_thread<C, R, PixT, 1>), grid, block, 0, st, a);
+    return hipGetLastError();
+}
+
+template <int C, class R, class PixT>
+static hipError_t launch_wave_t(const StatArgs &a, int n_groups, int block_waves, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, a.counter, 1);
+    size_t shmem = sizeof(R) * a.K + (PixTraits<PixT>::scaled ? sizeof(float) * C * a.K : 0);
+    hipLaunchKernelGGL((k_stat_wave<C, R, PixT>), dim3(n_groups), dim3(64 * block_waves), shmem, st, a);
+    return hipGetLastError();
+}
+
+template <int C, class R>
+static hipError_t dispatch_pix(const StatLaunch &L, const StatArgs &a, hipStream_t st) {
+    switch (L.pix_dtype) {
+        case 0:
+            if constexpr (sizeof(R) == 8) {
+                return L.schedule == 0 ? launch_thread_t<C, R, double>(a, L.layout, st)
+                                       : launch_wave_t<C, R, double>(a, L.n_groups, L.block_waves, st);
+            } else {
+                return hipErrorInvalidValue;
+            }
+        case 1:
+            return L.schedule == 0 ? launch_thread_t<C, R, float>(a, L.layout, st)
+                                   : launch_wave_t<C, R, float>(a, L.n_groups, L.block_waves, st);
+        case 2:
+            if constexpr (sizeof(R) == 4)
+                return L.schedule == 0 ? launch_thread_t<C, R, __hip_bfloat16>(a, L.layout, st)
+                                       : launch_wave_t<C, R, __hip_bfloat16>(a, L.n_groups, L.block_waves, st);
+            else
+                return hipErrorInvalidValue;
+        case 3:
+            if constexpr (sizeof(R) == 4)
+                return L.schedule == 0 ? launch_thread_t<C, R, __half>(a, L.layout, st)
+                                       : launch_wave_t<C, R, __half>(a, L.n_groups, L.block_waves, st);
+            else
+                return hipErrorInvalidValue;
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_weight_scale(int K, const double *inv_asd, double *scale_out, hipStream_t st) {
+    hipLaunchKernelGGL(k_weight_scale, dim3(1), dim3(256), 0, st, K, inv_asd, scale_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_statistic(const StatLaunch &L, hipStream_t st) {
+    StatArgs a = make_args(L);
+    if (L.n == 0) return hipSuccess;
+    if (L.C == 1) return L.precision == 0 ? dispatch_pix<1, double>(L, a, st) : dispatch_pix<1, float>(L, a, st);
+    return L.precision == 0 ? dispatch_pix<2, double>(L, a, st) : dispatch_pix<2, float>(L, a, st);
+}
+
+}  // namespace tfsc

@@ -1,0 +1,70 @@
+"""The C-ABI library loads, exports every declared symbol, and validates arguments on the host (CPU only)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "tfsc.h")) as fh:
+        src = fh.read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tfsc_[a-z_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2510_19047_amd import _lib
+    return _lib.load()
+
+
+def test_every_declared_function_is_exported(L):
+    names = _declared()
+    assert {"tfsc_transform", "tfsc_bank_statistic", "tfsc_statistic_vjp", "tfsc_segment_layout"} <= set(names)
+    for n in names:
+        assert hasattr(L, n), n
+    from paper_2510_19047_amd import _lib
+    assert set(_lib.EXPORTS) == set(names)
+
+
+def test_version_and_status_strings(L):
+    assert L.tfsc_abi_version() == 1
+    for s in range(7):
+        assert len(L.tfsc_status_string(s)) > 0
+
+
+def _grid(**kw):
+    from paper_2510_19047_amd import _lib
+    g = dict(n_channels=2, tranche_len=2048, n_tranches=6144, n_fresnel=21, dt=5.0, tukey_alpha=0.1)
+    g.update(kw)
+    return _lib.Grid(**g)
+
+
+def test_workspace_sizes(L):
+    from paper_2510_19047_amd import _lib
+    g = _grid()
+    assert L.tfsc_workspace_bytes(ctypes.byref(g), 1_000_000, None, _lib.WS_LAYOUT) >= 8 * (1_000_000 // 256)
+    assert L.tfsc_workspace_bytes(ctypes.byref(g), 10, None, _lib.WS_STATISTIC) >= 18 * 8 * 6144
+    assert L.tfsc_workspace_bytes(ctypes.byref(g), 0, None, _lib.WS_TRANSFORM) >= 2 * 1025 * 6144 * 8
+    bad = _grid(n_fresnel=20)
+    assert L.tfsc_workspace_bytes(ctypes.byref(bad), 10, None, _lib.WS_STATISTIC) == 0
+
+
+def test_argument_errors_return_codes(L):
+    from paper_2510_19047_amd import _lib
+    g = _grid()
+    bank = _lib.Bank(5)  # NULL arrays
+    seg = _lib.Segments(0, None, None)
+    assert L.tfsc_segment_layout(None, ctypes.byref(bank), ctypes.byref(seg), None, 0, None) == 1
+    assert L.tfsc_segment_layout(ctypes.byref(g), ctypes.byref(bank), ctypes.byref(seg), None, 0, None) == 1
+    assert L.tfsc_segment_layout(ctypes.byref(_grid(tranche_len=1000)), ctypes.byref(bank), ctypes.byref(seg),
+                                 None, 0, None) == 2
+    assert L.tfsc_segment_layout(ctypes.byref(_grid(n_fresnel=11)), ctypes.byref(bank), ctypes.byref(seg),
+                                 None, 0, None) == 5
+    pix = _lib.Pixels(7, 0, None, None, None, None)
+    assert L.tfsc_bank_statistic(ctypes.byref(g), ctypes.byref(pix), ctypes.byref(_lib.Bank(0)), ctypes.byref(seg),
+                                 None, None, None, None, None, None, 0, None) == 3
+    assert L.tfsc_track(ctypes.byref(g), ctypes.byref(bank), None, None) == 1

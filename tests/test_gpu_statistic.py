@@ -1,0 +1,174 @@
+"""GPU parity of the statistic path against the FP64 oracle (HIP through the C ABI)."""
+import numpy as np
+import pytest
+import torch
+
+import tfsc_inputs as ti
+from oracle import track as otrk
+
+from gpu_common import dev, gridspec, lib, note, oracle_stat, rel, small_data, store_from_oracle, tiny_data
+
+pytestmark = pytest.mark.gpu
+
+
+def _bank(tfsc, b):
+    return tfsc.BankTensors.from_host(b)
+
+
+def test_track_bit_exact():
+    tfsc = lib()
+    d = small_data()
+    g = d["grid"]
+    b = d["bank"]
+    note(f"track bit-exactness, {len(b)} templates x {g.n_tranches} tranches")
+    out = tfsc.track(gridspec(g), _bank(tfsc, b)).cpu().numpy()
+    lay = otrk.Layout(b, g)
+    t = torch.arange(g.n_tranches, dtype=torch.float64) * g.tranche_dur
+    checked = 0
+    for i in range(len(b)):
+        code = out[i, :, 3].astype(np.int64)
+        if not lay.valid[i]:
+            assert np.all(code == otrk.FLAG_INVALID)
+            continue
+        first = np.nonzero(code)[0]
+        m_end = first[0] if first.size else g.n_tranches
+        assert m_end == lay.m_end[i], i
+        T = lay.template(i)
+        n_ok = int(m_end)
+        Phi, f, fdot, _ = T.at(t[:n_ok])
+        assert np.array_equal(out[i, :n_ok, 1], f.numpy()), i
+        assert np.array_equal(out[i, :n_ok, 2], fdot.numpy()), i
+        assert np.array_equal(out[i, :n_ok, 0], Phi.numpy()), i
+        # bin index ceil(f dT) therefore agrees bit for bit
+        checked += n_ok
+    assert checked > 10000
+
+
+def test_layout_bit_exact():
+    tfsc = lib()
+    d = small_data()
+    g = d["grid"]
+    b = d["bank"]
+    note("segment layout, rule and fixed")
+    for fixed in (0, 7):
+        seg = tfsc.segment_layout(gridspec(g), _bank(tfsc, b), nseg_fixed=fixed)
+        lay = otrk.Layout(b, g, nseg_fixed=fixed or None) if fixed else otrk.Layout(b, g)
+        assert np.array_equal(seg.nseg.cpu().numpy(), lay.nseg)
+        assert np.array_equal(seg.seg_offset.cpu().numpy(), lay.seg_offset)
+
+
+@pytest.mark.parametrize("schedule", ["thread", "wave"])
+def test_tiny_fp64_matches_oracle(schedule):
+    """Tiny workload (257 templates incl. the exact one), FP64 pixels and arithmetic: 1e-6."""
+    tfsc = lib()
+    d = tiny_data()
+    g = d["grid"]
+    note(f"tiny fp64 {schedule}")
+    ref = oracle_stat(d, want_zn=True)
+    bt = _bank(tfsc, d["bank"])
+    seg = tfsc.segment_layout(gridspec(g), bt, nseg_fixed=8)
+    res = tfsc.bank_statistic(gridspec(g), store_from_oracle(d, "f64"), bt, seg, precision="f64", schedule=schedule,
+                              want_zn=True)
+    torch.cuda.synchronize()
+    stat = res.stat.cpu().numpy()
+    assert rel(stat, ref.stat).max() < 1e-6
+    assert np.array_equal(res.flags.cpu().numpy(), ref.flags)
+    assert np.max(np.abs(res.seg_terms.cpu().numpy() - ref.seg_terms) / np.maximum(ref.seg_terms, 1.0)) < 1e-6
+    zn = res.seg_zn.cpu().numpy()
+    # (z_n, N_n) come out with the exact weight normalisation 2^-e, e = exponent of max u_k
+    sc = 2.0 ** (-np.frexp(np.max(d["u"]))[1])
+    assert np.allclose(zn[:, 2], ref.seg_zn[:, 2] * sc * sc, rtol=1e-9)
+    assert np.allclose(zn[:, 0], ref.seg_zn[:, 0] * sc, rtol=1e-6, atol=1e-9 * np.abs(ref.seg_zn[:, 0] * sc).max())
+    # the injected template ranks first
+    assert int(np.argmax(stat)) == 256
+    note(f"tiny fp64 {schedule}: max rel {rel(stat, ref.stat).max():.2e}, exact-template stat {stat[256]:.1f}")
+
+
+@pytest.mark.parametrize("schedule", ["thread", "wave"])
+@pytest.mark.parametrize("precision,pixdt,tol", [("f64", "f64", 1e-6), ("f64", "f32", 1e-5), ("f32", "f32", 1e-4)])
+def test_two_channel_gapped_matches_oracle(schedule, precision, pixdt, tol):
+    tfsc = lib()
+    d = small_data()
+    g = d["grid"]
+    note(f"2ch gapped {schedule} {precision} pixels {pixdt}")
+    ref = oracle_stat(d)
+    bt = _bank(tfsc, d["bank"])
+    seg = tfsc.segment_layout(gridspec(g), bt)
+    res = tfsc.bank_statistic(gridspec(g), store_from_oracle(d, pixdt), bt, seg, precision=precision,
+                              schedule=schedule)
+    stat = res.stat.cpu().numpy()
+    r = rel(stat, ref.stat)
+    note(f"  max rel {r.max():.2e} median {np.median(r):.2e}")
+    assert r.max() < tol
+    assert np.array_equal(res.flags.cpu().numpy(), ref.flags)
+    seg_ref = ref.seg_terms
+    assert np.max(np.abs(res.seg_terms.cpu().numpy() - seg_ref) / np.maximum(seg_ref, 1.0)) < 10 * tol
+
+
+def test_tranche_major_thread_schedule():
+    tfsc = lib()
+    d = small_data()
+    g = d["grid"]
+    note("tranche-major layout, thread schedule")
+    ref = oracle_stat(d)
+    bt = _bank(tfsc, d["bank"])
+    seg = tfsc.segment_layout(gridspec(g), bt)
+    res = tfsc.bank_statistic(gridspec(g), store_from_oracle(d, "f32", layout="tranche"), bt, seg, precision="f32",
+                              schedule="thread")
+    assert rel(res.stat.cpu().numpy(), ref.stat).max() < 1e-4
+
+
+def test_processing_order_does_not_change_results():
+    tfsc = lib()
+    d = small_data()
+    g = d["grid"]
+    bt = _bank(tfsc, d["bank"])
+    seg = tfsc.segment_layout(gridspec(g), bt)
+    store = store_from_oracle(d, "f32")
+    a = tfsc.bank_statistic(gridspec(g), store, bt, seg, precision="f32", schedule="wave")
+    perm = torch.randperm(bt.n, generator=torch.Generator().manual_seed(3)).to(torch.int32).cuda()
+    b = tfsc.bank_statistic(gridspec(g), store, bt, seg, precision="f32", schedule="wave", order=perm)
+    c = tfsc.bank_statistic(gridspec(g), store, bt, seg, precision="f32", schedule="wave", block_waves=2,
+                            groups_per_cu=3)
+    assert torch.equal(a.stat, b.stat) and torch.equal(a.stat, c.stat)
+    assert torch.equal(a.seg_terms, b.seg_terms)
+
+
+def test_empty_bank_and_errors():
+    tfsc = lib()
+    d = small_data()
+    g = d["grid"]
+    b = d["bank"].subset(np.arange(0))
+    bt = _bank(tfsc, b)
+    seg = tfsc.segment_layout(gridspec(g), bt)
+    assert seg.total == 0
+    res = tfsc.bank_statistic(gridspec(g), store_from_oracle(d, "f32"), bt, seg, precision="f32")
+    assert res.stat.numel() == 0
+    with pytest.raises(tfsc.TfscError):
+        tfsc.bank_statistic(gridspec(g), store_from_oracle(d, "f32", layout="tranche"), _bank(tfsc, d["bank"]),
+                            tfsc.segment_layout(gridspec(g), _bank(tfsc, d["bank"])), precision="f32", schedule="wave")
+    with pytest.raises(tfsc.TfscError):
+        tfsc.bank_statistic(gridspec(g), store_from_oracle(d, "f64"), _bank(tfsc, d["bank"]),
+                            tfsc.segment_layout(gridspec(g), _bank(tfsc, d["bank"])), precision="f32")
+
+
+@pytest.mark.parametrize("dtype,tol", [("f16", 2e-3), ("bf16", 2e-2)])
+def test_16bit_store_error_against_oracle(dtype, tol):
+    """16-bit pixels with a per-layer FP32 scale, FP32 arithmetic: error of Upsilon vs the FP64 oracle."""
+    tfsc = lib()
+    d = small_data()
+    g = d["grid"]
+    note(f"16-bit store {dtype}")
+    x32 = d["x"].astype(np.float32)
+    from oracle import transform as otf
+    ref_pix, u, wm = otf.transform(x32.astype(np.float64), g, d["psd"], d["mu"], d["keep"], 0.1, "rfft")
+    from oracle import cpu as ocpu
+    ref = ocpu.statistic(ref_pix, u, wm, d["bank"], g)
+    st = tfsc.transform(gridspec(g), dev(x32), dev(d["psd"]), dev(d["mu"]), dev(d["keep"]), dtype=dtype)
+    bt = _bank(tfsc, d["bank"])
+    seg = tfsc.segment_layout(gridspec(g), bt)
+    res = tfsc.bank_statistic(gridspec(g), st, bt, seg, precision="f32", schedule="wave")
+    r = rel(res.stat.cpu().numpy(), ref.stat)
+    note(f"  {dtype}: max rel {r.max():.2e} median {np.median(r):.2e} p99 {np.quantile(r, 0.99):.2e}")
+    assert r.max() < tol
+    assert np.array_equal(res.flags.cpu().numpy(), ref.flags)
