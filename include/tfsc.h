@@ -175,10 +175,13 @@ tfsc_status tfsc_segment_layout(const tfsc_grid *grid, const tfsc_bank *bank, tf
  * input).  The kernels use u_k 2^-e with e the binary exponent of
  * max_k u_k (an exact power-of-two rescaling that keeps FP32 sums in range);
  * Upsilon is unchanged by it, z_n and N_n carry factors 2^-e and 2^-2e.
- * Needs TFSC_WS_STATISTIC workspace.                                        */
+ * n_active[n] (optional, may be NULL) receives the number of active tranches
+ * with w_m != 0 each template visited (its pixel columns: 21 C pixels each,
+ * minus bins outside [1, M/2 - 1]).  Needs TFSC_WS_STATISTIC workspace.     */
 tfsc_status tfsc_bank_statistic(const tfsc_grid *grid, const tfsc_pixels *pix, const tfsc_bank *bank,
                                 const tfsc_segments *seg, const tfsc_options *opt, double *seg_terms, double *stat,
-                                double *seg_zn, int32_t *flags, void *ws, size_t ws_bytes, void *stream);
+                                double *seg_zn, int32_t *flags, int32_t *n_active, void *ws, size_t ws_bytes,
+                                void *stream);
 
 /* Vector-Jacobian product of the statistic: g_params[n][5] =
  * d(sum_n g_seg_n Upsilon_n + g_stat Upsilon)/d(ln Mc, f0, cos theta, phi, psi)

@@ -134,6 +134,7 @@ class StatResult:
     seg_terms: torch.Tensor   # [total] f64
     flags: torch.Tensor       # [n] int32
     seg_zn: torch.Tensor | None = None  # [total][3] f64
+    n_active: torch.Tensor | None = None  # [n] int32
 
 
 def _options(precision="f32", schedule="wave", block_waves=0, groups_per_cu=0, order=None) -> _lib.Options:
@@ -163,12 +164,13 @@ def transform(grid: GridSpec, x: torch.Tensor, psd0: torch.Tensor, mu: torch.Ten
     return out
 
 
-def segment_layout(grid: GridSpec, bank: BankTensors, nseg_fixed: int = 0) -> SegmentLayout:
-    """tfsc_segment_layout: N_seg per template and CSR offsets (reads the total back once)."""
+def segment_layout(grid: GridSpec, bank: BankTensors, nseg_fixed: int = 0, out: SegmentLayout | None = None,
+                   read_total: bool = True) -> SegmentLayout:
+    """tfsc_segment_layout: N_seg per template and CSR offsets (reads the total back unless told not to)."""
     L = lib()
     dev = bank.mc.device
-    seg = SegmentLayout(torch.empty(bank.n, dtype=torch.int32, device=dev),
-                        torch.empty(bank.n + 1, dtype=torch.int64, device=dev), nseg_fixed)
+    seg = out if out is not None else SegmentLayout(torch.empty(bank.n, dtype=torch.int32, device=dev),
+                                                    torch.empty(bank.n + 1, dtype=torch.int64, device=dev), nseg_fixed)
     g = grid.c()
     nb = L.tfsc_workspace_bytes(ctypes.byref(g), bank.n, None, _lib.WS_LAYOUT)
     ws = _ws(nb, dev)
@@ -176,14 +178,15 @@ def segment_layout(grid: GridSpec, bank: BankTensors, nseg_fixed: int = 0) -> Se
     bc = bank.c()
     st = L.tfsc_segment_layout(ctypes.byref(g), ctypes.byref(bc), ctypes.byref(sc), _ptr(ws), nb, _stream())
     _lib.check(st, "tfsc_segment_layout")
-    seg.total = int(seg.seg_offset[-1].item())
+    if read_total:
+        seg.total = int(seg.seg_offset[-1].item())
     return seg
 
 
 def bank_statistic(grid: GridSpec, pixels: PixelStore, bank: BankTensors, seg: SegmentLayout,
                    precision: str = "f32", schedule: str = "wave", want_zn: bool = False, block_waves: int = 0,
                    groups_per_cu: int = 0, order: torch.Tensor | None = None, out: StatResult | None = None,
-                   ws: torch.Tensor | None = None) -> StatResult:
+                   ws: torch.Tensor | None = None, want_active: bool = False) -> StatResult:
     """tfsc_bank_statistic: Upsilon, per-segment terms and flags for every template."""
     L = lib()
     dev = bank.mc.device
@@ -191,7 +194,8 @@ def bank_statistic(grid: GridSpec, pixels: PixelStore, bank: BankTensors, seg: S
         out = StatResult(torch.empty(bank.n, dtype=torch.float64, device=dev),
                          torch.empty(max(seg.total, 1), dtype=torch.float64, device=dev),
                          torch.empty(bank.n, dtype=torch.int32, device=dev),
-                         torch.empty((max(seg.total, 1), 3), dtype=torch.float64, device=dev) if want_zn else None)
+                         torch.empty((max(seg.total, 1), 3), dtype=torch.float64, device=dev) if want_zn else None,
+                         torch.empty(bank.n, dtype=torch.int32, device=dev) if want_active else None)
     g = grid.c()
     opt = _options(precision, schedule, block_waves, groups_per_cu, order)
     nb = L.tfsc_workspace_bytes(ctypes.byref(g), bank.n, ctypes.byref(opt), _lib.WS_STATISTIC)
@@ -200,7 +204,7 @@ def bank_statistic(grid: GridSpec, pixels: PixelStore, bank: BankTensors, seg: S
     pc, bc, sc = pixels.c(), bank.c(), seg.c()
     st = L.tfsc_bank_statistic(ctypes.byref(g), ctypes.byref(pc), ctypes.byref(bc), ctypes.byref(sc),
                                ctypes.byref(opt), _ptr(out.seg_terms), _ptr(out.stat), _ptr(out.seg_zn),
-                               _ptr(out.flags), _ptr(ws), ws.numel(), _stream())
+                               _ptr(out.flags), _ptr(out.n_active), _ptr(ws), ws.numel(), _stream())
     _lib.check(st, "tfsc_bank_statistic")
     return out
 

@@ -73,7 +73,7 @@ def load(path: str = LIB_PATH):
     L.tfsc_segment_layout.argtypes = [P(Grid), P(Bank), P(Segments), c_void_p, c_size_t, c_void_p]
     L.tfsc_bank_statistic.restype = ctypes.c_int
     L.tfsc_bank_statistic.argtypes = [P(Grid), P(Pixels), P(Bank), P(Segments), P(Options), c_void_p, c_void_p,
-                                      c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+                                      c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
     L.tfsc_statistic_vjp.restype = ctypes.c_int
     L.tfsc_statistic_vjp.argtypes = [P(Grid), P(Pixels), P(Bank), P(Segments), P(Options), c_void_p, c_void_p,
                                      c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]

@@ -180,7 +180,8 @@ tfsc_status tfsc_segment_layout(const tfsc_grid *grid, const tfsc_bank *bank, tf
 
 tfsc_status tfsc_bank_statistic(const tfsc_grid *grid, const tfsc_pixels *pix, const tfsc_bank *bank,
                                 const tfsc_segments *seg, const tfsc_options *opt, double *seg_terms, double *stat,
-                                double *seg_zn, int32_t *flags, void *ws, size_t ws_bytes, void *stream) {
+                                double *seg_zn, int32_t *flags, int32_t *n_active, void *ws, size_t ws_bytes,
+                                void *stream) {
     tfsc_status s;
     if ((s = check_grid(grid)) != TFSC_OK) return s;
     if ((s = check_bank(bank)) != TFSC_OK) return s;
@@ -202,6 +203,7 @@ tfsc_status tfsc_bank_statistic(const tfsc_grid *grid, const tfsc_pixels *pix, c
     L.stat = stat;
     L.seg_zn = seg_zn;
     L.flags = flags;
+    L.n_active = n_active;
     return hip_status(tfsc::launch_statistic(L, st));
 }
 

@@ -34,6 +34,7 @@ struct StatLaunch {
     const int32_t *order;
     double *seg_terms, *stat, *seg_zn;
     int32_t *flags;
+    int32_t *n_active;
     uint32_t *counter;
 };
 

@@ -163,6 +163,7 @@ struct StatArgs {
     const int32_t *order;
     double *seg_terms, *stat, *seg_zn;
     int32_t *flags;
+    int32_t *n_active;
     uint32_t *counter;
 };
 
@@ -260,6 +261,7 @@ __global__ __launch_bounds__(256) void k_stat_thread(StatArgs a) {
         close_segments(acc, ns, off, a.seg_terms, a.seg_zn, true);
         a.stat[i] = 0.0;
         a.flags[i] = flag;
+        if (a.n_active) a.n_active[i] = 0;
         return;
     }
     Track T;
@@ -267,7 +269,7 @@ __global__ __launch_bounds__(256) void k_stat_thread(StatArgs a) {
     Sky<R> S;
     sky_init(S, a.ct[i], a.phi[i], a.psi[i], a.ci[i]);
     const double u_mul = a.u_scale[0];
-    int m = 0;
+    int m = 0, n_act = 0;
     for (; m < a.Nt; ++m) {
         double tm = (double)m * a.dT, Phi, f, fdot;
         int code = track_step(T, tm, a.dT, a.df, a.fnyq, Phi, f, fdot);
@@ -279,6 +281,7 @@ __global__ __launch_bounds__(256) void k_stat_thread(StatArgs a) {
         close_segments(acc, sg, off, a.seg_terms, a.seg_zn, true);
         double wmd = a.tranche_w[m];
         if (wmd == 0.0) continue;
+        ++n_act;
         TrancheSpec<R> ts;
         int kc = tranche_setup(ts, Phi, f, fdot, a.dT);
         cx<R> P[C];
@@ -295,6 +298,7 @@ __global__ __launch_bounds__(256) void k_stat_thread(StatArgs a) {
     if (!acc.any && m > 0) flag |= kFlagAllExcluded;
     a.stat[i] = acc.total;
     a.flags[i] = flag;
+    if (a.n_active) a.n_active[i] = n_act;
 }
 
 // ------------------------------------------------------------------ WAVE schedule
@@ -337,6 +341,7 @@ __global__ __launch_bounds__(256) void k_stat_wave(StatArgs a) {
             if (writer) {
                 a.stat[i] = 0.0;
                 a.flags[i] = kFlagInvalid;
+                if (a.n_active) a.n_active[i] = 0;
             }
             continue;
         }
@@ -344,7 +349,7 @@ __global__ __launch_bounds__(256) void k_stat_wave(StatArgs a) {
         track_init(T, a.mc[i], a.eta[i], a.f0[i]);
         Sky<R> S;
         sky_init(S, a.ct[i], a.phi[i], a.psi[i], a.ci[i]);
-        int m_end = a.Nt;
+        int m_end = a.Nt, n_act = 0;
         for (int m0 = 0; m0 < m_end; m0 += 64) {
             const int m = m0 + lane;
             const bool inr = m < a.Nt;
@@ -359,6 +364,7 @@ __global__ __launch_bounds__(256) void k_stat_wave(StatArgs a) {
                 m_end = lim;
             }
             const bool active = inr && m < lim;
+            n_act += __popcll(__ballot(active && a.tranche_w[min(m, a.Nt - 1)] != 0.0));
             R zr = 0, zi = 0, nn = 0;
             if (active) {
                 const double wmd = a.tranche_w[m];
@@ -397,6 +403,7 @@ __global__ __launch_bounds__(256) void k_stat_wave(StatArgs a) {
         if (writer) {
             a.stat[i] = acc.total;
             a.flags[i] = flag;
+            if (a.n_active) a.n_active[i] = n_act;
         }
     }
 }
@@ -487,6 +494,7 @@ static StatArgs make_args(const StatLaunch &L) {
     a.stat = L.stat;
     a.seg_zn = L.seg_zn;
     a.flags = L.flags;
+    a.n_active = L.n_active;
     a.counter = L.counter;
     return a;
 }

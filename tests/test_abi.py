@@ -66,5 +66,5 @@ def test_argument_errors_return_codes(L):
                                  None, 0, None) == 5
     pix = _lib.Pixels(7, 0, None, None, None, None)
     assert L.tfsc_bank_statistic(ctypes.byref(g), ctypes.byref(pix), ctypes.byref(_lib.Bank(0)), ctypes.byref(seg),
-                                 None, None, None, None, None, None, 0, None) == 3
+                                 None, None, None, None, None, None, None, 0, None) == 3
     assert L.tfsc_track(ctypes.byref(g), ctypes.byref(bank), None, None) == 1
