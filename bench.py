@@ -43,6 +43,8 @@ def parse():
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--block-waves", type=int, default=0)
     p.add_argument("--groups-per-cu", type=int, default=0)
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="copy 256 MiB device-to-device once, so profiler byte counters can be calibrated")
     return p.parse_args()
 
 
@@ -69,6 +71,15 @@ def main():
     psd_d, mu_d = torch.from_numpy(psd).to(dev), torch.from_numpy(mu).to(dev)
     keep_d = torch.from_numpy(keep).to(dev)
     bank = tfsc.BankTensors.from_host(bank_h, dev)
+
+    if args.copy_calibration:
+        a_ = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        b_ = torch.empty_like(a_)
+        torch.cuda.synchronize()
+        b_.copy_(a_)
+        torch.cuda.synchronize()
+        log("copy calibration: 268435456 bytes read, 268435456 bytes written")
+        del a_, b_
 
     # first pass: layout with total read-back, allocations reused by every timed step
     seg = tfsc.segment_layout(grid, bank)

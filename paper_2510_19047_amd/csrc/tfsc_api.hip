@@ -75,6 +75,11 @@ tfsc_status resolve_options(const tfsc_options *o, const tfsc_pixels *p, Resolve
     return TFSC_OK;
 }
 
+size_t pixel_store_bytes(const tfsc_grid *g, const tfsc_pixels *p) {
+    const size_t b = p->dtype == TFSC_F64 ? 16 : (p->dtype == TFSC_F32 ? 8 : 4);
+    return b * (size_t)g->n_channels * (size_t)(g->tranche_len / 2 + 1) * (size_t)g->n_tranches;
+}
+
 size_t geo_bytes(int Nt) { return align_up(sizeof(double) * 18 * (size_t)Nt); }
 
 size_t ws_bytes_for(const tfsc_grid *g, int64_t n, int which) {
@@ -191,6 +196,7 @@ tfsc_status tfsc_bank_statistic(const tfsc_grid *grid, const tfsc_pixels *pix, c
     if ((s = resolve_options(opt, pix, r)) != TFSC_OK) return s;
     if (bank->n > 0 && (!seg_terms || !stat || !flags)) return TFSC_ERR_ARG;
     if (!ws || ws_bytes < ws_bytes_for(grid, bank->n, TFSC_WS_STATISTIC)) return TFSC_ERR_WORKSPACE;
+    if (r.schedule == TFSC_SCHED_WAVE && pixel_store_bytes(grid, pix) > 0xffffffffull) return TFSC_ERR_UNSUPPORTED;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (bank->n == 0) return TFSC_OK;
     hipError_t e = tfsc::launch_geometry(grid->n_tranches, (double)grid->tranche_len * grid->dt,

@@ -197,7 +197,7 @@ __device__ inline void sky_init(Sky<R> &S, double ct, double phi, double psi, do
 template <class R>
 __device__ __forceinline__ R sinc_of(R x) {
     // sin(x)/x for 0 <= x <= ~2 pi f L; series near 0
-    if (x < (R)1e-4) return (R)1 - x * x / (R)6;
+    if (x < (R)1e-4) return (R)1 - x * x * (R)(1.0 / 6.0);
     return sin_rev(x * (R)(1.0 / kTwoPi)) * rcp(x);
 }
 
@@ -205,6 +205,7 @@ __device__ __forceinline__ R sinc_of(R x) {
 template <class R>
 __device__ inline void transfer_ae(const Sky<R> &S, const double *__restrict__ geo, int m, int Nt, double f,
                                    cx<R> &TA, cx<R> &TE) {
+#pragma clang fp contract(fast)
     const double L = kArmM / kClight;
     double kp[3];
 #pragma unroll
@@ -267,20 +268,21 @@ __device__ inline void transfer_ae(const Sky<R> &S, const double *__restrict__ g
 //   h_j = i Q (e^{i phi_m} / (x - j) - e^{i phi_end} / (x - j + beta)),  Q = A dT / (2 pi).
 template <class R>
 struct TrancheSpec {
-    R x, beta, s, r6, P, Q;
+    R x, beta, s, r6, P, Q, half_inv_beta;
     cx<R> E0, E1;
     double rev0;  // phi_m in revolutions, reduced
 };
 
 template <class R>
 __device__ __forceinline__ void fresnel_fg(R av, R &f, R &g) {
+#pragma clang fp contract(fast)
     if (av > (R)6) {
         f = rcp((R)kPi * av);
         g = (R)0;
     } else {
         R a2 = av * av;
-        f = ((R)1 + (R)0.926 * av) / ((R)2 + (R)1.792 * av + (R)3.104 * a2);
-        g = (R)1 / ((R)2 + (R)4.142 * av + (R)3.492 * a2 + (R)6.670 * a2 * av);
+        f = ((R)1 + (R)0.926 * av) * rcp((R)2 + (R)1.792 * av + (R)3.104 * a2);
+        g = rcp((R)2 + (R)4.142 * av + (R)3.492 * a2 + (R)6.670 * a2 * av);
     }
 }
 
@@ -289,17 +291,22 @@ __device__ __forceinline__ R sgn(R v) {
     return v > (R)0 ? (R)1 : (v < (R)0 ? (R)-1 : (R)0);
 }
 
+// Asymptotic Fresnel on both tranche edges and no bin frequency crossed (valid when
+// x - j > r6 or x - j + beta < -r6):  h_j = i Q (e^{i phi_m}/(x - j) - e^{i phi_end}/(x - j + beta)).
 template <class R>
-__device__ __forceinline__ cx<R> tranche_spectrum_bin(const TrancheSpec<R> &ts, int j) {
-    R xj = ts.x - (R)j;
+__device__ __forceinline__ cx<R> bin_fast(const TrancheSpec<R> &ts, R xj) {
+#pragma clang fp contract(fast)
+    R a = rcp(xj), b = rcp(xj + ts.beta);
+    R re = ts.E0.re * a - ts.E1.re * b;
+    R im = ts.E0.im * a - ts.E1.im * b;
+    return {-ts.Q * im, ts.Q * re};
+}
+
+// General form, valid for every bin (both Fresnel branches, stationary-phase term).
+template <class R>
+__device__ __forceinline__ cx<R> bin_full(const TrancheSpec<R> &ts, R xj) {
+#pragma clang fp contract(fast)
     R xj1 = xj + ts.beta;
-    if (xj > ts.r6 || xj1 < -ts.r6) {
-        // fast path: asymptotic Fresnel on both edges, no stationary bin
-        R a = rcp(xj), b = rcp(xj1);
-        R re = ts.E0.re * a - ts.E1.re * b;
-        R im = ts.E0.im * a - ts.E1.im * b;
-        return {-ts.Q * im, ts.Q * re};
-    }
     R v0 = ts.s * xj, v1 = ts.s * xj1;
     R sg0 = sgn(v0), sg1 = sgn(v1);
     R f0, g0, f1, g1;
@@ -311,13 +318,20 @@ __device__ __forceinline__ cx<R> tranche_spectrum_bin(const TrancheSpec<R> &ts, 
     R ds = sg1 - sg0;
     if (ds != (R)0) {
         // bin frequency crossed inside the tranche: stationary-phase term
-        double rv = frac_rev(ts.rev0 - (double)(xj * xj / (ts.beta * (R)2)));
+        double rv = frac_rev(ts.rev0 - (double)(xj * xj * ts.half_inv_beta));
         cx<R> e = expi_rev((R)rv);
         R hh = ds * (R)0.5;
         h.re += hh * (e.re - e.im);
         h.im += hh * (e.re + e.im);
     }
     return cscale(h, ts.P);
+}
+
+template <class R>
+__device__ __forceinline__ cx<R> tranche_spectrum_bin(const TrancheSpec<R> &ts, int j) {
+    R xj = ts.x - (R)j;
+    if (xj > ts.r6 || xj + ts.beta < -ts.r6) return bin_fast(ts, xj);
+    return bin_full(ts, xj);
 }
 
 // Tranche constants from the FP64 track.  Returns k_c.  Bin index, offset and
@@ -337,14 +351,18 @@ __device__ __forceinline__ int tranche_setup(TrancheSpec<R> &ts, double Phi, dou
         double A = pow(f, 2.0 / 3.0);
         ts.P = A / sqrt(2.0 * fdot);
         ts.Q = A * dT / kTwoPi;
+        ts.r6 = 6.0 / ts.s;
+        ts.half_inv_beta = 0.5 / beta;
     } else {
         float b = (float)beta;
-        ts.s = sqrtf(2.0f * rcp(b));
+        float ib = rcp(b);
+        ts.s = sqrtf(2.0f * ib);
         float A = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf((float)f) * (2.0f / 3.0f));
         ts.P = A * __builtin_amdgcn_rsqf((float)(2.0 * fdot));
         ts.Q = A * (float)(dT / kTwoPi);
+        ts.r6 = sqrtf(18.0f * b);  // 6 / s
+        ts.half_inv_beta = 0.5f * ib;
     }
-    ts.r6 = (R)6 / ts.s;
     ts.E0 = expi_rev((R)rev0);
     ts.E1 = expi_rev((R)rev1);
     ts.rev0 = rev0;

@@ -151,6 +151,7 @@ struct StatArgs {
     int M, K, Nt, C;
     double dt, dT, df, fnyq;
     const void *pix;
+    uint32_t pix_bytes;  // size of the pixel store (WAVE schedule: < 4 GiB)
     const float *layer_scale;
     const double *inv_asd;
     const double *tranche_w;
@@ -199,6 +200,7 @@ template <int C, class R, class PixT, int LAYOUT, class U>
 __device__ __forceinline__ void tranche_bins(const StatArgs &a, const TrancheSpec<R> &ts, int kc, int m,
                                              const U *__restrict__ u_tab, U u_mul, const float *__restrict__ sc_tab,
                                              cx<R> (&P)[C], R &Q) {
+#pragma clang fp contract(fast)
     using PT = PixTraits<PixT>;
 #pragma unroll
     for (int c = 0; c < C; ++c) P[c] = {(R)0, (R)0};
@@ -211,7 +213,8 @@ __device__ __forceinline__ void tranche_bins(const StatArgs &a, const TrancheSpe
         cx<R> h = tranche_spectrum_bin(ts, j);
         R w = (R)(u_tab[k] * u_mul);
         cx<R> g = {h.re * w, h.im * w};
-        Q += g.re * g.re + g.im * g.im;
+        Q += g.re * g.re;
+        Q += g.im * g.im;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             size_t idx = LAYOUT == 0 ? ((size_t)(c * a.K + k) * a.Nt + m) : ((size_t)(c * a.Nt + m) * a.K + k);
@@ -222,8 +225,10 @@ __device__ __forceinline__ void tranche_bins(const StatArgs &a, const TrancheSpe
                 D.re *= s;
                 D.im *= s;
             }
-            P[c].re += D.re * g.re + D.im * g.im;
-            P[c].im += D.re * g.im - D.im * g.re;
+            P[c].re += D.re * g.re;
+            P[c].re += D.im * g.im;
+            P[c].im += D.re * g.im;
+            P[c].im -= D.im * g.re;
         }
     }
 }
@@ -232,6 +237,7 @@ __device__ __forceinline__ void tranche_bins(const StatArgs &a, const TrancheSpe
 template <int C, class R>
 __device__ __forceinline__ void tranche_combine(const Sky<R> &S, const StatArgs &a, int m, double f, R wm,
                                                 const cx<R> (&P)[C], R Q, R &zr, R &zi, R &nn) {
+#pragma clang fp contract(fast)
     cx<R> TA, TE;
     transfer_ae(S, a.geo, m, a.Nt, f, TA, TE);
     cx<R> z = cmul(TA, P[0]);
@@ -302,24 +308,152 @@ __global__ __launch_bounds__(256) void k_stat_thread(StatArgs a) {
 }
 
 // ------------------------------------------------------------------ WAVE schedule
+// Wave-wide sum of a float or double, result in every lane's scalar view (DPP row
+// shifts within 16-lane rows, then row broadcasts 15 and 31; lane 63 ends with the
+// total).  Called only in converged control flow.
+__device__ __forceinline__ float dpp_sum_f32(float v) {
+#pragma clang fp contract(fast)
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x111, 0xf, 0xf, true));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x112, 0xf, 0xf, true));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x114, 0xf, 0xe, true));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x118, 0xf, 0xc, true));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x142, 0xa, 0xf, true));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x143, 0xc, 0xf, true));
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
+template <int CTRL, int RM, int BM>
+__device__ __forceinline__ double dpp_add_step_f64(double v) {
+    long long bits = __builtin_bit_cast(long long, v);
+    int lo = __builtin_amdgcn_update_dpp(0, (int)(bits & 0xffffffffLL), CTRL, RM, BM, true);
+    int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, RM, BM, true);
+    long long o = ((long long)(unsigned)lo) | ((long long)hi << 32);
+    return v + __builtin_bit_cast(double, o);
+}
+
+__device__ __forceinline__ double dpp_sum_f64(double v) {
+    // the two 32-bit halves move by DPP; the adds are FP64
+    v = dpp_add_step_f64<0x111, 0xf, 0xf>(v);
+    v = dpp_add_step_f64<0x112, 0xf, 0xf>(v);
+    v = dpp_add_step_f64<0x114, 0xf, 0xe>(v);
+    v = dpp_add_step_f64<0x118, 0xf, 0xc>(v);
+    v = dpp_add_step_f64<0x142, 0xa, 0xf>(v);
+    v = dpp_add_step_f64<0x143, 0xc, 0xf>(v);
+    long long bits = __builtin_bit_cast(long long, v);
+    int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), 63);
+    int hi = __builtin_amdgcn_readlane((int)(bits >> 32), 63);
+    return __builtin_bit_cast(double, ((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+
+__device__ __forceinline__ float dpp_max_f32(float v) {
+    v = fmaxf(v, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x111, 0xf, 0xf, true)));
+    v = fmaxf(v, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x112, 0xf, 0xf, true)));
+    v = fmaxf(v, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x114, 0xf, 0xe, true)));
+    v = fmaxf(v, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x118, 0xf, 0xc, true)));
+    v = fmaxf(v, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x142, 0xa, 0xf, true)));
+    v = fmaxf(v, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x143, 0xc, 0xf, true)));
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+
 template <class R>
 __device__ __forceinline__ R wave_sum(R v) {
+    if constexpr (sizeof(R) == 4) return dpp_sum_f32(v);
+    else return dpp_sum_f64(v);
+}
+
+// Raw buffer view of the pixel store: hardware-checked, loads past the end return 0.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t pix_rsrc(const void *p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+template <class PixT>
+__device__ __forceinline__ cx<typename PixTraits<PixT>::R> buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(PixT) == 8) {
+        auto v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+        double2 d = __builtin_bit_cast(double2, v);
+        return {d.x, d.y};
+    } else if constexpr (sizeof(PixT) == 4) {
+        auto v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+        float2 f = __builtin_bit_cast(float2, v);
+        return {f.x, f.y};
+    } else {
+        uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+        if constexpr (sizeof(PixT) == 2 && PixTraits<PixT>::scaled && __is_same(PixT, __half)) {
+            __half2 h = __builtin_bit_cast(__half2, w);
+            float2 f = __half22float2(h);
+            return {f.x, f.y};
+        } else {
+            return {__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u)};
+        }
+    }
+}
+
+// Bins of one tranche for the WAVE schedule.  The 21 bins are unrolled; each bin's pixel
+// row is a scalar offset from the lane's row of bin kc - 10, the weight table is padded
+// with zeros so bins outside [1, M/2 - 1] contribute nothing (their loads are in bounds or
+// return 0), and the exact Fresnel form is used only for the bins [jA, jB] where some lane
+// of the wave may need it (a wave-uniform choice).
+template <int C, class R, class PixT>
+__device__ __forceinline__ void wave_tranche_bins(const TrancheSpec<R> &ts, int kc, int m, int Nt, int K,
+                                                  __amdgpu_buffer_rsrc_t rsrc, const R *__restrict__ u_pad,
+                                                  const float *__restrict__ sc_pad, int jA, int jB, cx<R> (&P)[C],
+                                                  R &Q) {
+#pragma clang fp contract(fast)
+    constexpr uint32_t B = sizeof(PixT) == 8 ? 16u : (sizeof(PixT) == 4 ? 8u : 4u);
+    const uint32_t voff = (uint32_t)((kc - kHalfBins) * Nt + m) * B;
+    const uint32_t row = (uint32_t)Nt * B, chan = (uint32_t)K * row;
+    const R *uk = u_pad + (kc - kHalfBins + kHalfBins);  // u_pad[k + 10] = u_k
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    for (int c = 0; c < C; ++c) P[c] = {(R)0, (R)0};
+    Q = (R)0;
+#pragma unroll 7
+    for (int jj = 0; jj < 2 * kHalfBins + 1; ++jj) {
+        const int j = jj - kHalfBins;
+        const R xj = ts.x - (R)j;
+        cx<R> h = (j >= jA && j <= jB) ? bin_full(ts, xj) : bin_fast(ts, xj);
+        const R w = uk[jj];
+        const cx<R> g = {h.re * w, h.im * w};
+        Q += g.re * g.re;
+        Q += g.im * g.im;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const auto Dl = buf_load<PixT>(rsrc, voff, (uint32_t)jj * row + (uint32_t)c * chan);
+            cx<R> D = {(R)Dl.re, (R)Dl.im};
+            if constexpr (PixTraits<PixT>::scaled) {
+                const R s = (R)sc_pad[c * (K + 2 * kHalfBins) + kc + j + kHalfBins];
+                D.re *= s;
+                D.im *= s;
+            }
+            // conj(D) g accumulated as four separate multiply-adds
+            P[c].re += D.re * g.re;
+            P[c].re += D.im * g.im;
+            P[c].im += D.re * g.im;
+            P[c].im -= D.im * g.re;
+        }
+    }
 }
 
 template <int C, class R, class PixT>
-__global__ __launch_bounds__(256) void k_stat_wave(StatArgs a) {
-    // template weights u_k (and 16-bit layer scales) staged in LDS once per block
+__global__ __launch_bounds__(256, 3) void k_stat_wave(StatArgs a) {
+    // Zero-padded template weights u_pad[k + 10] = u_k for 1 <= k <= M/2 - 1 (else 0), and
+    // the 16-bit layer scales, staged in LDS once per block.
     extern __shared__ unsigned char smem_raw[];
-    R *u_tab = reinterpret_cast<R *>(smem_raw);
-    float *sc_tab = reinterpret_cast<float *>(smem_raw + sizeof(R) * a.K);
+    const int KP = a.K + 2 * kHalfBins;
+    R *u_pad = reinterpret_cast<R *>(smem_raw);
+    float *sc_pad = reinterpret_cast<float *>(smem_raw + sizeof(R) * KP);
     const double u_mul = a.u_scale[0];
-    for (int k = threadIdx.x; k < a.K; k += blockDim.x) u_tab[k] = (R)(a.inv_asd[k] * u_mul);
+    const int kmax = a.M / 2 - 1;
+    for (int q = threadIdx.x; q < KP; q += blockDim.x) {
+        const int k = q - kHalfBins;
+        u_pad[q] = (k >= 1 && k <= kmax) ? (R)(a.inv_asd[k] * u_mul) : (R)0;
+    }
     if constexpr (PixTraits<PixT>::scaled)
-        for (int k = threadIdx.x; k < C * a.K; k += blockDim.x) sc_tab[k] = a.layer_scale[k];
+        for (int q = threadIdx.x; q < C * KP; q += blockDim.x) {
+            const int c = q / KP, k = q % KP - kHalfBins;
+            sc_pad[q] = (k >= 0 && k < a.K) ? a.layer_scale[c * a.K + k] : 0.0f;
+        }
     __syncthreads();
+    const __amdgpu_buffer_rsrc_t rsrc = pix_rsrc(a.pix, a.pix_bytes);
 
     const int lane = threadIdx.x & 63;
     for (;;) {
@@ -364,18 +498,27 @@ __global__ __launch_bounds__(256) void k_stat_wave(StatArgs a) {
                 m_end = lim;
             }
             const bool active = inr && m < lim;
-            n_act += __popcll(__ballot(active && a.tranche_w[min(m, a.Nt - 1)] != 0.0));
+            const double wmd = active ? a.tranche_w[m] : 0.0;
+            const bool work = active && wmd != 0.0;
+            n_act += __popcll(__ballot(work));
+            TrancheSpec<R> ts;
+            int kc = 0;
+            float reach = 0.0f;  // x + beta + r6 bound of the exact-form bins
+            if (work) {
+                kc = tranche_setup(ts, Phi, f, fdot, a.dT);
+                reach = (float)(ts.beta + ts.r6);
+            }
+            // Exact-form bins: x - r6 <= j <= x + beta + r6 with x in (-1, 0], so every lane's
+            // such bins lie in [floor(-1 - rmax) + 1, floor(rmax)] (margin 1e-3 for rounding).
+            const float rmax = dpp_max_f32(reach);
+            const int jA = (int)floorf(-1.0f - rmax - 1e-3f) + 1;
+            const int jB = (int)floorf(rmax + 1e-3f);
             R zr = 0, zi = 0, nn = 0;
-            if (active) {
-                const double wmd = a.tranche_w[m];
-                if (wmd != 0.0) {
-                    TrancheSpec<R> ts;
-                    int kc = tranche_setup(ts, Phi, f, fdot, a.dT);
-                    cx<R> P[C];
-                    R Q;
-                    tranche_bins<C, R, PixT, 0, R>(a, ts, kc, m, u_tab, (R)1, sc_tab, P, Q);
-                    tranche_combine<C, R>(S, a, m, f, (R)wmd, P, Q, zr, zi, nn);
-                }
+            if (work) {
+                cx<R> P[C];
+                R Q;
+                wave_tranche_bins<C, R, PixT>(ts, kc, m, a.Nt, a.K, rsrc, u_pad, sc_pad, jA, jB, P, Q);
+                tranche_combine<C, R>(S, a, m, f, (R)wmd, P, Q, zr, zi, nn);
             }
             // segmented reduction over the lanes of this chunk
             const int last = min(min(m0 + 63, lim - 1), a.Nt - 1);
@@ -385,10 +528,9 @@ __global__ __launch_bounds__(256) void k_stat_wave(StatArgs a) {
                 const int my_s = (int)(((int64_t)m * ns) / a.Nt);
                 for (int s = s_first; s <= s_last; ++s) {
                     const bool mine = active && my_s == s;
-                    R vr = mine ? zr : (R)0, vi = mine ? zi : (R)0, vn = mine ? nn : (R)0;
-                    vr = wave_sum(vr);
-                    vi = wave_sum(vi);
-                    vn = wave_sum(vn);
+                    R vr = wave_sum<R>(mine ? zr : (R)0);
+                    R vi = wave_sum<R>(mine ? zi : (R)0);
+                    R vn = wave_sum<R>(mine ? nn : (R)0);
                     close_segments(acc, s, off, a.seg_terms, a.seg_zn, writer);
                     acc.zr += (double)vr;
                     acc.zi += (double)vi;
@@ -474,6 +616,11 @@ static StatArgs make_args(const StatLaunch &L) {
     a.df = 1.0 / a.dT;
     a.fnyq = 0.5 / L.dt;
     a.pix = L.pix;
+    {
+        const size_t pb = L.pix_dtype == 0 ? 16 : (L.pix_dtype == 1 ? 8 : 4);
+        const size_t tot = pb * (size_t)L.C * (size_t)(L.M / 2 + 1) * (size_t)L.Nt;
+        a.pix_bytes = tot > 0xffffffffull ? 0xffffffffu : (uint32_t)tot;
+    }
     a.layer_scale = L.layer_scale;
     a.inv_asd = L.inv_asd;
     a.tranche_w = L.tranche_w;
@@ -512,7 +659,8 @@ static hipError_t launch_thread_t(const StatArgs &a, int layout, hipStream_t st)
 template <int C, class R, class PixT>
 static hipError_t launch_wave_t(const StatArgs &a, int n_groups, int block_waves, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, a.counter, 1);
-    size_t shmem = sizeof(R) * a.K + (PixTraits<PixT>::scaled ? sizeof(float) * C * a.K : 0);
+    const size_t KP = (size_t)a.K + 2 * kHalfBins;
+    size_t shmem = sizeof(R) * KP + (PixTraits<PixT>::scaled ? sizeof(float) * C * KP : 0);
     hipLaunchKernelGGL((k_stat_wave<C, R, PixT>), dim3(n_groups), dim3(64 * block_waves), shmem, st, a);
     return hipGetLastError();
 }
