@@ -106,8 +106,9 @@ typedef struct {
  *            TFSC_SCHED_WAVE   -- one 64-lane wavefront per template, lanes
  *                        over consecutive tranches, persistent grid pulling
  *                        templates from a device work counter; LAYER_MAJOR.
- * block_waves / groups_per_cu: launch shape of the WAVE schedule (0 = tuned
- * default); order: optional [n] permutation of template indices giving the
+ * block_waves / groups_per_cu: launch shape of the WAVE schedule, waves per
+ * block (1..4) and resident blocks per compute unit (1..64); 0 = default
+ * (4, 4); larger values return TFSC_ERR_ARG.  order: optional [n] permutation of template indices giving the
  * processing order (NULL = bank order); results are written at the
  * template's own index whatever the order.                                 */
 enum { TFSC_SCHED_THREAD = 0, TFSC_SCHED_WAVE = 1 };
@@ -183,16 +184,42 @@ tfsc_status tfsc_bank_statistic(const tfsc_grid *grid, const tfsc_pixels *pix, c
                                 double *seg_zn, int32_t *flags, int32_t *n_active, void *ws, size_t ws_bytes,
                                 void *stream);
 
-/* Vector-Jacobian product of the statistic: g_params[n][5] =
+/* Vector-Jacobian product of the statistic (gradient of Eq. (Upsilon-seg)
+ * through Eqs. (overlap-n), (inner-segment-tf), (fresnel-ft) and the
+ * response): g_params[n][5] =
  * d(sum_n g_seg_n Upsilon_n + g_stat Upsilon)/d(ln Mc, f0, cos theta, phi, psi)
- * holding the integer structure (bins, Fresnel branches, track end, N_seg)
- * fixed; the track is recomputed, nothing per pixel is stored.  seg_zn is
- * the forward's output for the same inputs; g_stat[n] and/or g_seg
- * [seg_offset[n]] (either may be NULL).  Needs TFSC_WS_VJP workspace.       */
+ * per template, eta and cos iota held fixed, and the integer structure (bins,
+ * Fresnel branches, track end, N_seg) held at the template's own values (the
+ * almost-everywhere derivative).  The track, spectra and response are
+ * recomputed with forward-mode tangents; nothing per pixel is stored.
+ * seg_zn is the forward's output (tfsc_bank_statistic) for the same inputs;
+ * g_stat[n] and/or g_seg[seg_offset[n]] may be NULL (not both).  Arithmetic
+ * is FP64 for every pixel type and either layout; opt->precision, schedule
+ * and order are ignored, block_waves and groups_per_cu set the launch.
+ * Invalid and empty templates get 0.  Needs TFSC_WS_VJP workspace.         */
 tfsc_status tfsc_statistic_vjp(const tfsc_grid *grid, const tfsc_pixels *pix, const tfsc_bank *bank,
                                const tfsc_segments *seg, const tfsc_options *opt, const double *seg_zn,
                                const double *g_stat, const double *g_seg, double *g_params, void *ws,
                                size_t ws_bytes, void *stream);
+
+/* One step of the gradient-ascent follow-up of candidates (the paper's
+ * Outlook proposes differentiable templates for follow-up): for each
+ * template, an Adam step (beta1 0.9, beta2 0.999) that increases Upsilon,
+ * applied in place to bank->mc (through ln Mc), f0, cos_theta, phi and psi.
+ * Step sizes are lr_scale times the statistic's resolution of the template:
+ * delta f0 = 0.1 / T_seg, delta ln Mc = delta f0 / ((5/3) fdot(0) T_obs),
+ * 0.05 for cos theta, phi and psi; (cos theta, phi) are reflected through a
+ * pole when cos theta leaves [-1, 1], phi is wrapped to [0, 2 pi) and psi to
+ * [0, pi).  stat[n] and g_params[n][5] are the forward's Upsilon and the
+ * VJP's gradient at the current parameters; seg->nseg gives T_seg.
+ * state[n][16] is caller-owned device memory: (Adam m[5], v[5], best
+ * Upsilon, best mc, f0, cos theta, phi, psi); step = 1 initialises it, so it
+ * needs no clearing.  Before updating, a template whose stat exceeds its best
+ * records its current parameters as the best.  lr_scale = 0 only records
+ * (use it after the last step's forward).  Invalid templates are not moved.  */
+tfsc_status tfsc_follow_up_step(const tfsc_grid *grid, tfsc_bank *bank, const tfsc_segments *seg,
+                                const double *stat, const double *g_params, double *state, double lr_scale,
+                                int step, void *stream);
 
 /* The FP64 track behind every statistic call, for inspection: out[n][Nt][4]
  * holds (Phi_m, f_m, fdot_m, code_m) at each tranche start t_m = m dT, with

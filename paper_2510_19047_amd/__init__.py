@@ -212,7 +212,10 @@ def bank_statistic(grid: GridSpec, pixels: PixelStore, bank: BankTensors, seg: S
 def statistic_vjp(grid: GridSpec, pixels: PixelStore, bank: BankTensors, seg: SegmentLayout, seg_zn: torch.Tensor,
                   g_stat: torch.Tensor | None = None, g_seg: torch.Tensor | None = None, precision: str = "f32",
                   block_waves: int = 0, groups_per_cu: int = 0, out: torch.Tensor | None = None) -> torch.Tensor:
-    """tfsc_statistic_vjp: [n][5] gradient w.r.t. (ln Mc, f0, cos theta, phi, psi)."""
+    """tfsc_statistic_vjp: [n][5] gradient w.r.t. (ln Mc, f0, cos theta, phi, psi), computed in FP64.
+
+    ``precision`` is accepted for symmetry with bank_statistic and does not change the arithmetic.
+    """
     L = lib()
     dev = bank.mc.device
     if out is None:
@@ -227,6 +230,44 @@ def statistic_vjp(grid: GridSpec, pixels: PixelStore, bank: BankTensors, seg: Se
                               ws.numel(), _stream())
     _lib.check(st, "tfsc_statistic_vjp")
     return out
+
+
+def follow_up_step(grid: GridSpec, bank: BankTensors, seg: SegmentLayout, stat: torch.Tensor,
+                   g_params: torch.Tensor, state: torch.Tensor, lr_scale: float, step: int) -> None:
+    """tfsc_follow_up_step: one Adam ascent step on bank (in place); state is [n][16] float64."""
+    L = lib()
+    g, bc, sc = grid.c(), bank.c(), seg.c()
+    st = L.tfsc_follow_up_step(ctypes.byref(g), ctypes.byref(bc), ctypes.byref(sc), _ptr(stat), _ptr(g_params),
+                               _ptr(state), float(lr_scale), int(step), _stream())
+    _lib.check(st, "tfsc_follow_up_step")
+
+
+def follow_up(grid: GridSpec, pixels: PixelStore, bank: BankTensors, steps: int = 50, lr_scale: float = 0.5,
+              nseg_fixed: int = 0, precision: str = "f32"):
+    """Gradient-ascent follow-up of a candidate set: ``steps`` rounds of statistic, VJP and Adam step.
+
+    The segment layout is fixed at the candidates' initial parameters.  Returns (initial Upsilon, best
+    Upsilon, best parameters [n][5] = (mc, f0, cos theta, phi, psi)).  ``bank`` is not modified.
+    """
+    dev = bank.mc.device
+    work = BankTensors(*(t.clone() for t in (bank.mc, bank.eta, bank.f0, bank.cos_theta, bank.phi, bank.psi,
+                                             bank.cos_iota)))
+    seg = segment_layout(grid, work, nseg_fixed)
+    state = torch.empty((work.n, 16), dtype=torch.float64, device=dev)
+    ones = torch.ones(work.n, dtype=torch.float64, device=dev)
+    gp = torch.empty((work.n, 5), dtype=torch.float64, device=dev)
+    res = None
+    first = None
+    for step in range(1, steps + 2):
+        res = bank_statistic(grid, pixels, work, seg, precision=precision, want_zn=True, out=res)
+        if first is None:
+            first = res.stat.clone()
+        if step == steps + 1:
+            follow_up_step(grid, work, seg, res.stat, gp, state, 0.0, step)  # record the last point only
+            break
+        statistic_vjp(grid, pixels, work, seg, res.seg_zn, g_stat=ones, out=gp)
+        follow_up_step(grid, work, seg, res.stat, gp, state, lr_scale, step)
+    return first, state[:, 10].clone(), state[:, 11:16].clone()
 
 
 def track(grid: GridSpec, bank: BankTensors) -> torch.Tensor:

@@ -42,7 +42,7 @@ class Options(ctypes.Structure):
 
 
 EXPORTS = ("tfsc_abi_version", "tfsc_status_string", "tfsc_workspace_bytes", "tfsc_transform",
-           "tfsc_segment_layout", "tfsc_bank_statistic", "tfsc_statistic_vjp", "tfsc_track")
+           "tfsc_segment_layout", "tfsc_bank_statistic", "tfsc_statistic_vjp", "tfsc_follow_up_step", "tfsc_track")
 
 _lib = None
 
@@ -77,6 +77,9 @@ def load(path: str = LIB_PATH):
     L.tfsc_statistic_vjp.restype = ctypes.c_int
     L.tfsc_statistic_vjp.argtypes = [P(Grid), P(Pixels), P(Bank), P(Segments), P(Options), c_void_p, c_void_p,
                                      c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+    L.tfsc_follow_up_step.restype = ctypes.c_int
+    L.tfsc_follow_up_step.argtypes = [P(Grid), P(Bank), P(Segments), c_void_p, c_void_p, c_void_p, ctypes.c_double,
+                                      ctypes.c_int, c_void_p]
     L.tfsc_track.restype = ctypes.c_int
     L.tfsc_track.argtypes = [P(Grid), P(Bank), c_void_p, c_void_p]
     _lib = L

@@ -1,4 +1,5 @@
 // C ABI of libtfsc.so: argument checks, workspace carving and launches.
+#include <math.h>
 #include <string.h>
 
 #include "../../include/tfsc.h"
@@ -66,7 +67,8 @@ tfsc_status resolve_options(const tfsc_options *o, const tfsc_pixels *p, Resolve
     r.order = o ? o->order : nullptr;
     if (r.precision != TFSC_F64 && r.precision != TFSC_F32) return TFSC_ERR_DTYPE;
     if (r.schedule != TFSC_SCHED_THREAD && r.schedule != TFSC_SCHED_WAVE) return TFSC_ERR_ARG;
-    if (r.block_waves > 16 || r.groups_per_cu > 64) return TFSC_ERR_ARG;
+    // the WAVE and VJP kernels are compiled for at most 256 threads (4 waves) per block
+    if (r.block_waves > 4 || r.groups_per_cu > 64) return TFSC_ERR_ARG;
     if (p) {
         if (r.precision == TFSC_F64 && (p->dtype == TFSC_BF16 || p->dtype == TFSC_F16)) return TFSC_ERR_DTYPE;
         if (r.precision == TFSC_F32 && p->dtype == TFSC_F64) return TFSC_ERR_DTYPE;
@@ -222,8 +224,10 @@ tfsc_status tfsc_statistic_vjp(const tfsc_grid *grid, const tfsc_pixels *pix, co
     if ((s = check_bank(bank)) != TFSC_OK) return s;
     if ((s = check_pixels(pix, bank->n > 0)) != TFSC_OK) return s;
     if (!seg || (bank->n > 0 && (!seg->nseg || !seg->seg_offset))) return TFSC_ERR_ARG;
+    // The VJP computes in FP64 for every pixel type and layout; only the launch shape is taken
+    // from the options.
     Resolved r;
-    if ((s = resolve_options(opt, pix, r)) != TFSC_OK) return s;
+    if ((s = resolve_options(opt, nullptr, r)) != TFSC_OK) return s;
     if (bank->n > 0 && (!seg_zn || !g_params || (!g_stat && !g_seg))) return TFSC_ERR_ARG;
     if (!ws || ws_bytes < ws_bytes_for(grid, bank->n, TFSC_WS_VJP)) return TFSC_ERR_WORKSPACE;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -240,6 +244,35 @@ tfsc_status tfsc_statistic_vjp(const tfsc_grid *grid, const tfsc_pixels *pix, co
     V.g_seg = g_seg;
     V.g_params = g_params;
     return hip_status(tfsc::launch_vjp(V, st));
+}
+
+tfsc_status tfsc_follow_up_step(const tfsc_grid *grid, tfsc_bank *bank, const tfsc_segments *seg,
+                                const double *stat, const double *g_params, double *state, double lr_scale,
+                                int step, void *stream) {
+    tfsc_status s;
+    if ((s = check_grid(grid)) != TFSC_OK) return s;
+    if ((s = check_bank(bank)) != TFSC_OK) return s;
+    if (step < 1 || !(lr_scale >= 0.0) || !isfinite(lr_scale)) return TFSC_ERR_ARG;
+    if (bank->n == 0) return TFSC_OK;
+    if (!seg || !seg->nseg || !stat || !g_params || !state) return TFSC_ERR_ARG;
+    tfsc::FollowLaunch L;
+    L.Nt = grid->n_tranches;
+    L.dT = (double)grid->tranche_len * grid->dt;
+    L.n = bank->n;
+    L.mc = const_cast<double *>(bank->mc);
+    L.f0 = const_cast<double *>(bank->f0);
+    L.ct = const_cast<double *>(bank->cos_theta);
+    L.phi = const_cast<double *>(bank->phi);
+    L.psi = const_cast<double *>(bank->psi);
+    L.eta = bank->eta;
+    L.ci = bank->cos_iota;
+    L.nseg = seg->nseg;
+    L.stat = stat;
+    L.g_params = g_params;
+    L.state = state;
+    L.lr_scale = lr_scale;
+    L.step = step;
+    return hip_status(tfsc::launch_follow_step(L, reinterpret_cast<hipStream_t>(stream)));
 }
 
 tfsc_status tfsc_transform(const tfsc_grid *grid, const void *x, int x_dtype, const double *psd0,

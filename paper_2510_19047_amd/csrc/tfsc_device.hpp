@@ -31,7 +31,7 @@ enum : int { kFlagInvalid = 1, kFlagEmpty = 2, kFlagBandEnd = 4, kFlagMergeEnd =
 
 // ------------------------------------------------------------------ track
 struct Track {
-    double eta, M, c8, a2, a3, a4, b2, b3, b4, tc;
+    double eta, M, c8, a2, a3, a4, b2, b3, b4, tc, th0;
 };
 
 __device__ __forceinline__ bool params_valid(double mc, double eta, double f0, double ct, double ci) {
@@ -73,6 +73,7 @@ __device__ inline void track_init(Track &T, double mc, double eta, double f0) {
     }
     double th2 = th * th, th4 = th2 * th2, th8 = th4 * th4;
     T.tc = (5.0 * T.M) / (eta * th8);
+    T.th0 = th;
 }
 
 // Phase Phi (rad, phi_c = 0), GW frequency f and its derivative at time t < t_c.

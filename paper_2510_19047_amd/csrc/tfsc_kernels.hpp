@@ -45,6 +45,19 @@ struct VjpLaunch {
     double *g_params;
 };
 
+struct FollowLaunch {
+    int Nt;
+    double dT;
+    int64_t n;
+    double *mc, *f0, *ct, *phi, *psi;  // updated in place
+    const double *eta, *ci;
+    const int32_t *nseg;
+    const double *stat, *g_params;
+    double *state;  // [n][16]
+    double lr_scale;
+    int step;
+};
+
 struct TransformLaunch {
     int M, Nt, C;
     double dt, alpha;
@@ -65,6 +78,7 @@ hipError_t launch_weight_scale(int K, const double *inv_asd, double *scale_out, 
 hipError_t launch_statistic(const StatLaunch &L, hipStream_t st);
 hipError_t launch_vjp(const VjpLaunch &L, hipStream_t st);
 hipError_t launch_transform(const TransformLaunch &L, hipStream_t st);
+hipError_t launch_follow_step(const FollowLaunch &L, hipStream_t st);
 hipError_t launch_track(int64_t n, int M, int Nt, double dt, const double *mc, const double *eta, const double *f0,
                         const double *ct, const double *ci, double *out, hipStream_t st);
 

@@ -68,3 +68,34 @@ def test_argument_errors_return_codes(L):
     assert L.tfsc_bank_statistic(ctypes.byref(g), ctypes.byref(pix), ctypes.byref(_lib.Bank(0)), ctypes.byref(seg),
                                  None, None, None, None, None, None, None, 0, None) == 3
     assert L.tfsc_track(ctypes.byref(g), ctypes.byref(bank), None, None) == 1
+
+
+def test_vjp_argument_errors(L):
+    from paper_2510_19047_amd import _lib
+    g = _grid()
+    bank = _lib.Bank(0)
+    seg = _lib.Segments(0, None, None)
+    pix = _lib.Pixels(1, 0, None, None, None, None)
+    # missing pixel weights
+    assert L.tfsc_statistic_vjp(ctypes.byref(g), ctypes.byref(pix), ctypes.byref(bank), ctypes.byref(seg), None,
+                                None, None, None, None, None, 0, None) == 1
+    # an empty bank needs no workspace beyond the declared size, but a NULL workspace is refused
+    one = (ctypes.c_double * 4)()
+    pix = _lib.Pixels(1, 0, None, None, ctypes.cast(one, ctypes.c_void_p), ctypes.cast(one, ctypes.c_void_p))
+    assert L.tfsc_statistic_vjp(ctypes.byref(g), ctypes.byref(pix), ctypes.byref(bank), ctypes.byref(seg), None,
+                                None, None, None, None, None, 0, None) == 4
+
+
+def test_launch_shape_limits(L):
+    """block_waves above 4 (256 threads, the kernels' launch bound) is refused before any launch."""
+    from paper_2510_19047_amd import _lib
+    g = _grid()
+    one = (ctypes.c_double * 4)()
+    p = ctypes.cast(one, ctypes.c_void_p)
+    pix = _lib.Pixels(1, 0, p, None, p, p)
+    seg = _lib.Segments(0, p, p)
+    bank = _lib.Bank(1, p, p, p, p, p, p, p)
+    for bw, gpc in ((5, 1), (8, 2), (1, 65)):
+        opt = _lib.Options(1, 1, bw, gpc, None)
+        assert L.tfsc_bank_statistic(ctypes.byref(g), ctypes.byref(pix), ctypes.byref(bank), ctypes.byref(seg),
+                                     ctypes.byref(opt), p, p, None, p, None, p, 1 << 30, None) == 1
