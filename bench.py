@@ -8,8 +8,10 @@ templates (Mc log-uniform in [10, 60] Msun, f0 uniform in [10, 40] mHz, isotropi
 uniform polarisation and inclination, plus 20 exact-injection templates), adaptive
 N_seg from 16 to 256.  Data and bank are seeded and synthetic.
 
-One step = tfsc_transform (data -> pixels) + tfsc_segment_layout + tfsc_bank_statistic
-over the whole bank, with inputs resident in HBM.  Prints one JSON line.
+One step = tfsc_transform (data -> pixels) + tfsc_segment_layout + tfsc_processing_order +
+tfsc_bank_statistic over the whole bank, with inputs resident in HBM.  Prints one JSON line.
+The WAVE schedule's launch shape comes from the autotuner (timed on a separate 65,536-template
+tuning bank, cached per device and workload shape).
 """
 from __future__ import annotations
 
@@ -41,8 +43,9 @@ def parse():
     p.add_argument("--plain-steps", type=int, default=2)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
-    p.add_argument("--block-waves", type=int, default=0)
+    p.add_argument("--block-waves", type=int, default=0, help="fix the launch shape (0 = autotune)")
     p.add_argument("--groups-per-cu", type=int, default=0)
+    p.add_argument("--no-order", action="store_true", help="process the bank in its own order")
     p.add_argument("--copy-calibration", action="store_true",
                    help="copy 256 MiB device-to-device once, so profiler byte counters can be calibrated")
     return p.parse_args()
@@ -95,13 +98,29 @@ def main():
     log(f"bank {n} templates, mean active tranches {n_active.mean():.0f}, segments {seg.total}, "
         f"algorithmic bytes {alg_bytes / 1e12:.3f} TB")
 
-    kw = dict(block_waves=args.block_waves, groups_per_cu=args.groups_per_cu)
+    order = None if args.no_order else tfsc.processing_order(grid, bank)
+    if args.block_waves > 0:
+        shape = (args.block_waves, args.groups_per_cu if args.groups_per_cu > 0 else 4)
+    else:
+        from paper_2510_19047_amd import batching
+        tune_h = ti.random_bank(65536, 5, mc_range=(10.0, 60.0), f0_range=(0.010, 0.040), stream=77)
+        tune = tfsc.BankTensors.from_host(tune_h, dev)
+        tune_seg = tfsc.segment_layout(grid, tune)
+        shape = batching.autotune(grid, pix_chosen, tune, tune_seg, precision="f32",
+                                  order=None if args.no_order else tfsc.processing_order(grid, tune))
+        del tune, tune_seg
+    kw = dict(block_waves=shape[0], groups_per_cu=shape[1])
+    log(f"launch shape: {shape[0]} waves per block, {shape[1]} blocks per CU; "
+        f"order: {'bank order' if order is None else 'by f0 bin (device counting sort)'}")
 
     def step(store_dtype, layout, schedule, pix_out, res_out):
         tfsc.transform(grid, x_d, psd_d, mu_d, keep_d, dtype=store_dtype, layout=layout, out=pix_out)
         tfsc.segment_layout(grid, bank, out=seg, read_total=False)
-        return tfsc.bank_statistic(grid, pix_out, bank, seg, precision="f32", schedule=schedule, out=res_out,
-                                   **(kw if schedule == "wave" else {}))
+        if schedule == "wave":
+            o = None if order is None else tfsc.processing_order(grid, bank, out=order)
+            return tfsc.bank_statistic(grid, pix_out, bank, seg, precision="f32", schedule=schedule, out=res_out,
+                                       order=o, **kw)
+        return tfsc.bank_statistic(grid, pix_out, bank, seg, precision="f32", schedule=schedule, out=res_out)
 
     # ---------------- chosen form: wave-per-template schedule
     res_c = tfsc.StatResult(torch.empty(n, dtype=torch.float64, device=dev),
@@ -127,7 +146,8 @@ def main():
     ks = []
     for i in range(max(args.steps, 3)):
         ev[0].record(st)
-        tfsc.bank_statistic(grid, pix_chosen, bank, seg, precision="f32", schedule="wave", out=res_c, **kw)
+        tfsc.bank_statistic(grid, pix_chosen, bank, seg, precision="f32", schedule="wave", out=res_c, order=order,
+                            **kw)
         ev[1].record(st)
         torch.cuda.synchronize()
         ks.append(ev[0].elapsed_time(ev[1]))
@@ -178,7 +198,9 @@ def main():
             "n_templates": n,
             "pixel_store": args.chosen_store,
             "schedule": "wave-per-template persistent",
-            "step": "transform + segment layout + bank statistic",
+            "launch_shape": {"block_waves": kw["block_waves"], "groups_per_cu": kw["groups_per_cu"]},
+            "order": "bank" if order is None else "f0 bin",
+            "step": "transform + segment layout + processing order + bank statistic",
         },
         "roofline": {
             "bound": "hbm",

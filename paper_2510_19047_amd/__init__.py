@@ -232,6 +232,20 @@ def statistic_vjp(grid: GridSpec, pixels: PixelStore, bank: BankTensors, seg: Se
     return out
 
 
+def processing_order(grid: GridSpec, bank: BankTensors, out: torch.Tensor | None = None) -> torch.Tensor:
+    """tfsc_processing_order: an int32 permutation grouping templates by the frequency bin of f0."""
+    L = lib()
+    dev = bank.mc.device
+    if out is None:
+        out = torch.empty(max(bank.n, 1), dtype=torch.int32, device=dev)
+    g, bc = grid.c(), bank.c()
+    nb = L.tfsc_workspace_bytes(ctypes.byref(g), bank.n, None, _lib.WS_ORDER)
+    ws = _ws(nb, dev)
+    _lib.check(L.tfsc_processing_order(ctypes.byref(g), ctypes.byref(bc), _ptr(out), _ptr(ws), nb, _stream()),
+               "tfsc_processing_order")
+    return out[: bank.n]
+
+
 def follow_up_step(grid: GridSpec, bank: BankTensors, seg: SegmentLayout, stat: torch.Tensor,
                    g_params: torch.Tensor, state: torch.Tensor, lr_scale: float, step: int) -> None:
     """tfsc_follow_up_step: one Adam ascent step on bank (in place); state is [n][16] float64."""

@@ -13,7 +13,7 @@ TFSC_OK = 0
 F64, F32, BF16, F16 = 0, 1, 2, 3
 LAYER_MAJOR, TRANCHE_MAJOR = 0, 1
 SCHED_THREAD, SCHED_WAVE = 0, 1
-WS_LAYOUT, WS_STATISTIC, WS_VJP, WS_TRANSFORM = 0, 1, 2, 3
+WS_LAYOUT, WS_STATISTIC, WS_VJP, WS_TRANSFORM, WS_ORDER = 0, 1, 2, 3, 4
 FLAG_INVALID, FLAG_EMPTY, FLAG_BAND_END, FLAG_MERGE_END, FLAG_ALL_EXCLUDED = 1, 2, 4, 8, 16
 
 
@@ -42,7 +42,7 @@ class Options(ctypes.Structure):
 
 
 EXPORTS = ("tfsc_abi_version", "tfsc_status_string", "tfsc_workspace_bytes", "tfsc_transform",
-           "tfsc_segment_layout", "tfsc_bank_statistic", "tfsc_statistic_vjp", "tfsc_follow_up_step", "tfsc_track")
+           "tfsc_segment_layout", "tfsc_bank_statistic", "tfsc_statistic_vjp", "tfsc_follow_up_step", "tfsc_processing_order", "tfsc_track")
 
 _lib = None
 
@@ -80,6 +80,8 @@ def load(path: str = LIB_PATH):
     L.tfsc_follow_up_step.restype = ctypes.c_int
     L.tfsc_follow_up_step.argtypes = [P(Grid), P(Bank), P(Segments), c_void_p, c_void_p, c_void_p, ctypes.c_double,
                                       ctypes.c_int, c_void_p]
+    L.tfsc_processing_order.restype = ctypes.c_int
+    L.tfsc_processing_order.argtypes = [P(Grid), P(Bank), c_void_p, c_void_p, c_size_t, c_void_p]
     L.tfsc_track.restype = ctypes.c_int
     L.tfsc_track.argtypes = [P(Grid), P(Bank), c_void_p, c_void_p]
     _lib = L

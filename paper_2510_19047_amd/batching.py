@@ -1,0 +1,123 @@
+"""Batching around the statistic: launch-shape autotuning and HIP-graph replay over noise realisations.
+
+Paper Sec. "Hardware acceleration and computational cost": the method evaluates large batches of
+parameter sets per launch.  Here that is one persistent launch over the whole bank, with
+
+* ``autotune``: the WAVE schedule's launch shape (waves per block, resident blocks per compute unit)
+  chosen by timing candidates with HIP events on a tuning bank, cached in a JSON file keyed by the
+  device and the workload's shape;
+* ``RealisationGraph``: the sequence transform(r) -> bank_statistic(r) for R noise realisations of
+  the same grid, captured once into a HIP graph (torch.cuda.CUDAGraph) and replayed.  Every kernel
+  in it is a launch (work counters are cleared by a fill kernel, never by a memset node).
+
+Nothing here computes any part of the statistic: the work is done by libtfsc.so.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import torch
+
+from . import (BankTensors, GridSpec, PixelStore, SegmentLayout, StatResult, bank_statistic, transform)
+
+CANDIDATES = ((4, 4), (4, 3), (4, 2), (2, 8), (2, 6), (2, 4), (1, 12), (1, 8))
+
+
+def _cache_path(path: str | None) -> str:
+    if path:
+        return path
+    env = os.environ.get("TFSC_TUNE_CACHE")
+    if env:
+        return env
+    return os.path.join(os.path.expanduser("~"), ".cache", "tfsc", "launch_shapes.json")
+
+
+def _key(grid: GridSpec, pixels: PixelStore, precision: str) -> str:
+    name = torch.cuda.get_device_name(torch.cuda.current_device())
+    return f"{name}|C{grid.n_channels}|M{grid.tranche_len}|Nt{grid.n_tranches}|{pixels.dtype}|{precision}"
+
+
+def autotune(grid: GridSpec, pixels: PixelStore, bank: BankTensors, seg: SegmentLayout, precision: str = "f32",
+             order: torch.Tensor | None = None, candidates=CANDIDATES, reps: int = 2, cache: str | None = None,
+             refresh: bool = False) -> tuple[int, int]:
+    """(block_waves, groups_per_cu) with the shortest WAVE statistic launch on ``bank`` (a tuning bank).
+
+    The result is cached under the device name and workload shape; ``refresh`` re-times it.
+    """
+    path = _cache_path(cache)
+    key = _key(grid, pixels, precision)
+    table = {}
+    if os.path.exists(path):
+        try:
+            with open(path) as fh:
+                table = json.load(fh)
+        except (OSError, ValueError):
+            table = {}
+    if key in table and not refresh:
+        bw, gpc = table[key]["shape"]
+        return int(bw), int(gpc)
+    res = bank_statistic(grid, pixels, bank, seg, precision=precision, schedule="wave", order=order)
+    ws = torch.empty(1 << 22, dtype=torch.uint8, device=bank.mc.device)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    timings = {}
+    for bw, gpc in candidates:
+        ts = []
+        for _ in range(reps):
+            ev[0].record()
+            bank_statistic(grid, pixels, bank, seg, precision=precision, schedule="wave", order=order, out=res,
+                           ws=ws, block_waves=bw, groups_per_cu=gpc)
+            ev[1].record()
+            torch.cuda.synchronize()
+            ts.append(ev[0].elapsed_time(ev[1]))
+        timings[f"{bw}x{gpc}"] = min(ts)
+    best = min(candidates, key=lambda c: timings[f"{c[0]}x{c[1]}"])
+    table[key] = {"shape": list(best), "ms": timings, "tuning_templates": bank.n}
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        with open(path, "w") as fh:
+            json.dump(table, fh, indent=1)
+    except OSError:
+        pass  # a read-only home only loses the cache
+    return int(best[0]), int(best[1])
+
+
+class RealisationGraph:
+    """transform(r) -> bank_statistic(r) for R realisations, captured into one HIP graph.
+
+    xs: [R][C][N] device time series (f32 or f64).  The pixel stores, results and workspace are
+    allocated once (eager warm-up) and reused by every replay; ``results[r]`` holds realisation r's
+    output after ``replay()``.
+    """
+
+    def __init__(self, grid: GridSpec, xs: torch.Tensor, psd0: torch.Tensor, mu: torch.Tensor, keep: torch.Tensor,
+                 bank: BankTensors, seg: SegmentLayout, store: str = "f32", precision: str = "f32",
+                 order: torch.Tensor | None = None, block_waves: int = 0, groups_per_cu: int = 0):
+        self.grid, self.xs, self.psd0, self.mu, self.keep = grid, xs, psd0, mu, keep
+        self.bank, self.seg, self.store, self.precision, self.order = bank, seg, store, precision, order
+        self.shape = dict(block_waves=block_waves, groups_per_cu=groups_per_cu)
+        R = xs.shape[0]
+        dev = bank.mc.device
+        self.stores = [transform(grid, xs[r], psd0, mu, keep, dtype=store) for r in range(R)]
+        self.ws = torch.empty(1 << 22, dtype=torch.uint8, device=dev)
+        self.results = [bank_statistic(grid, self.stores[r], bank, seg, precision=precision, schedule="wave",
+                                       order=order, ws=self.ws, **self.shape) for r in range(R)]
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._enqueue()
+
+    def _enqueue(self):
+        for r in range(self.xs.shape[0]):
+            transform(self.grid, self.xs[r], self.psd0, self.mu, self.keep, dtype=self.store, out=self.stores[r])
+            bank_statistic(self.grid, self.stores[r], self.bank, self.seg, precision=self.precision,
+                           schedule="wave", order=self.order, out=self.results[r], ws=self.ws, **self.shape)
+
+    def replay(self) -> list[StatResult]:
+        self.graph.replay()
+        return self.results
+
+    def eager(self) -> list[StatResult]:
+        """The same work launched directly (for comparison with the graph)."""
+        self._enqueue()
+        return self.results

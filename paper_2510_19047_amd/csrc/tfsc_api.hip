@@ -91,6 +91,8 @@ size_t ws_bytes_for(const tfsc_grid *g, int64_t n, int which) {
         case TFSC_WS_STATISTIC:
         case TFSC_WS_VJP:
             return geo_bytes(g->n_tranches) + kAlign;
+        case TFSC_WS_ORDER:
+            return align_up(sizeof(uint32_t) * 2 * (size_t)(g->tranche_len / 2 + 2));
         case TFSC_WS_TRANSFORM: {
             size_t K = (size_t)g->tranche_len / 2 + 1;
             return align_up(sizeof(float) * 2 * (size_t)g->n_channels * K * (size_t)g->n_tranches) +
@@ -134,7 +136,7 @@ tfsc::StatLaunch stat_launch(const tfsc_grid *grid, const tfsc_pixels *pix, cons
     L.order = r.order;
     char *tail = reinterpret_cast<char *>(ws) + geo_bytes(grid->n_tranches);
     L.counter = reinterpret_cast<uint32_t *>(tail);
-    L.u_scale = reinterpret_cast<const double *>(tail + 8);
+    L.u_scale = reinterpret_cast<const double *>(tail + tfsc::kTailScale);
     return L;
 }
 
@@ -244,6 +246,27 @@ tfsc_status tfsc_statistic_vjp(const tfsc_grid *grid, const tfsc_pixels *pix, co
     V.g_seg = g_seg;
     V.g_params = g_params;
     return hip_status(tfsc::launch_vjp(V, st));
+}
+
+tfsc_status tfsc_processing_order(const tfsc_grid *grid, const tfsc_bank *bank, int32_t *order, void *ws,
+                                  size_t ws_bytes, void *stream) {
+    tfsc_status s;
+    if ((s = check_grid(grid)) != TFSC_OK) return s;
+    if ((s = check_bank(bank)) != TFSC_OK) return s;
+    if (bank->n > 0 && !order) return TFSC_ERR_ARG;
+    if (!ws || ws_bytes < ws_bytes_for(grid, bank->n, TFSC_WS_ORDER)) return TFSC_ERR_WORKSPACE;
+    tfsc::OrderLaunch L;
+    L.M = grid->tranche_len;
+    L.dt = grid->dt;
+    L.n = bank->n;
+    L.mc = bank->mc;
+    L.eta = bank->eta;
+    L.f0 = bank->f0;
+    L.ct = bank->cos_theta;
+    L.ci = bank->cos_iota;
+    L.order = order;
+    L.ws = reinterpret_cast<uint32_t *>(ws);
+    return hip_status(tfsc::launch_order(L, reinterpret_cast<hipStream_t>(stream)));
 }
 
 tfsc_status tfsc_follow_up_step(const tfsc_grid *grid, tfsc_bank *bank, const tfsc_segments *seg,

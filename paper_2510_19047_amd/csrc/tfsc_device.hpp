@@ -32,6 +32,7 @@ enum : int { kFlagInvalid = 1, kFlagEmpty = 2, kFlagBandEnd = 4, kFlagMergeEnd =
 // ------------------------------------------------------------------ track
 struct Track {
     double eta, M, c8, a2, a3, a4, b2, b3, b4, tc, th0;
+    double i5M, ic8, i40M, m2ieta;  // 1/(5M), 1/c8, 1/(40M), -2/eta
 };
 
 __device__ __forceinline__ bool params_valid(double mc, double eta, double f0, double ct, double ci) {
@@ -74,25 +75,32 @@ __device__ inline void track_init(Track &T, double mc, double eta, double f0) {
     double th2 = th * th, th4 = th2 * th2, th8 = th4 * th4;
     T.tc = (5.0 * T.M) / (eta * th8);
     T.th0 = th;
+    T.i5M = 1.0 / (5.0 * T.M);
+    T.ic8 = 1.0 / T.c8;
+    T.i40M = 1.0 / (40.0 * T.M);
+    T.m2ieta = -2.0 / eta;
 }
 
 // Phase Phi (rad, phi_c = 0), GW frequency f and its derivative at time t < t_c.
+// One division per call (theta = 1/s); the per-template divisors enter as their
+// reciprocals, and theta^-5 = s^5.
 __device__ inline void track_at(const Track &T, double t, double &Phi, double &f, double &fdot) {
     double tau = T.tc - t;
-    double q = (T.eta * tau) / (5.0 * T.M);
+    double q = (T.eta * tau) * T.i5M;
     double s = sqrt(sqrt(sqrt(q)));
     double th = 1.0 / s;
     double th2 = th * th, th3 = th2 * th, th4 = th2 * th2;
     double Pf = ((1.0 + T.a2 * th2) + T.a3 * th3) + T.a4 * th4;
-    f = (th3 / T.c8) * Pf;
+    f = (th3 * T.ic8) * Pf;
     double dPf = ((3.0 + (5.0 * T.a2) * th2) + (6.0 * T.a3) * th3) + (7.0 * T.a4) * th4;
-    double dfdth = (th2 / T.c8) * dPf;
+    double dfdth = (th2 * T.ic8) * dPf;
     double th8 = th4 * th4, th9 = th8 * th;
-    double dthdt = (T.eta * th9) / (40.0 * T.M);
+    double dthdt = (T.eta * th9) * T.i40M;
     fdot = dfdth * dthdt;
     double Pp = ((1.0 + T.b2 * th2) + T.b3 * th3) + T.b4 * th4;
-    double thm5 = 1.0 / (th4 * th);
-    Phi = -((2.0 * thm5) * Pp) / T.eta;
+    double s2 = s * s;
+    double thm5 = (s2 * s2) * s;
+    Phi = (T.m2ieta * thm5) * Pp;
 }
 
 // Track end (paper Appendix A compactness + band edge + merger): returns 0 if
@@ -161,9 +169,10 @@ __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // ------------------------------------------------------------------ response
-// Per-tranche geometry table (FP64, structure of arrays, row stride Nt):
-// rows 0..8 spacecraft positions p_i (light-seconds), rows 9..17 unit arm
-// vectors n_01, n_12, n_20 (from the first spacecraft to the second).
+// Per-tranche geometry table (FP64, structure of arrays, row stride Nt, so the 64
+// lanes of a wave on consecutive tranches read 512 contiguous bytes per row): rows
+// 0..8 spacecraft positions p_i (light-seconds), rows 9..17 unit arm vectors
+// n_01, n_12, n_20 (from the first spacecraft to the second).
 constexpr int kGeoRows = 18;
 
 template <class R>
@@ -202,27 +211,32 @@ __device__ __forceinline__ R sinc_of(R x) {
     return sin_rev(x * (R)(1.0 / kTwoPi)) * rcp(x);
 }
 
-// T_A, T_E at tranche m (time t_m) and frequency f.  geo: table above.
+__device__ __forceinline__ void load_geo(const double *__restrict__ geo, int m, int Nt, double g[kGeoRows]) {
+#pragma unroll
+    for (int r = 0; r < kGeoRows; ++r) g[r] = geo[(size_t)r * Nt + m];
+}
+
+// T_A, T_E at tranche m (time t_m) and frequency f.  geo: the table above; each value is
+// read where it is used, which keeps register pressure down.
 template <class R>
 __device__ inline void transfer_ae(const Sky<R> &S, const double *__restrict__ geo, int m, int Nt, double f,
                                    cx<R> &TA, cx<R> &TE) {
 #pragma clang fp contract(fast)
     const double L = kArmM / kClight;
+    const double *g = geo + m;  // value r of tranche m at g[r * Nt]
     double kp[3];
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        double px = geo[(3 * i + 0) * (size_t)Nt + m], py = geo[(3 * i + 1) * (size_t)Nt + m],
-               pz = geo[(3 * i + 2) * (size_t)Nt + m];
-        kp[i] = S.kd[0] * px + S.kd[1] * py + S.kd[2] * pz;
-    }
+    for (int i = 0; i < 3; ++i)
+        kp[i] = S.kd[0] * g[(size_t)(3 * i) * Nt] + S.kd[1] * g[(size_t)(3 * i + 1) * Nt] +
+                S.kd[2] * g[(size_t)(3 * i + 2) * Nt];
     const R pfL = (R)(kPi * f * L);
     cx<R> Gd[3], Gr[3];  // arm a: direction (s -> r) and reverse
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int s = a, r = (a + 1) % 3;
-        R n0 = (R)geo[(9 + 3 * a + 0) * (size_t)Nt + m];
-        R n1 = (R)geo[(9 + 3 * a + 1) * (size_t)Nt + m];
-        R n2 = (R)geo[(9 + 3 * a + 2) * (size_t)Nt + m];
+        R n0 = (R)g[(size_t)(9 + 3 * a + 0) * Nt];
+        R n1 = (R)g[(size_t)(9 + 3 * a + 1) * Nt];
+        R n2 = (R)g[(size_t)(9 + 3 * a + 2) * Nt];
         R kn = S.k[0] * n0 + S.k[1] * n1 + S.k[2] * n2;
         R nu = S.u[0] * n0 + S.u[1] * n1 + S.u[2] * n2;
         R nv = S.v[0] * n0 + S.v[1] * n1 + S.v[2] * n2;
@@ -297,7 +311,17 @@ __device__ __forceinline__ R sgn(R v) {
 template <class R>
 __device__ __forceinline__ cx<R> bin_fast(const TrancheSpec<R> &ts, R xj) {
 #pragma clang fp contract(fast)
-    R a = rcp(xj), b = rcp(xj + ts.beta);
+    const R xj1 = xj + ts.beta;
+    R a, b;
+    if constexpr (sizeof(R) == 4) {
+        // one hardware reciprocal for both: 1/xj = xj1 r, 1/xj1 = xj r with r = 1/(xj xj1)
+        const R r = rcp(xj * xj1);
+        a = xj1 * r;
+        b = xj * r;
+    } else {
+        a = rcp(xj);
+        b = rcp(xj1);
+    }
     R re = ts.E0.re * a - ts.E1.re * b;
     R im = ts.E0.im * a - ts.E1.im * b;
     return {-ts.Q * im, ts.Q * re};

@@ -6,6 +6,10 @@
 
 namespace tfsc {
 
+// Layout of the statistic workspace's tail: the WAVE schedule's uint32 work counter at
+// +0, the FP64 weight scale at +kTailScale.
+constexpr int kTailScale = 64;
+
 struct LayoutLaunch {
     int64_t n;
     const double *mc, *eta, *f0, *ct, *ci;
@@ -45,6 +49,15 @@ struct VjpLaunch {
     double *g_params;
 };
 
+struct OrderLaunch {
+    int M;
+    double dt;
+    int64_t n;
+    const double *mc, *eta, *f0, *ct, *ci;
+    int32_t *order;
+    uint32_t *ws;  // 2 (M/2 + 2) counters
+};
+
 struct FollowLaunch {
     int Nt;
     double dT;
@@ -79,6 +92,7 @@ hipError_t launch_statistic(const StatLaunch &L, hipStream_t st);
 hipError_t launch_vjp(const VjpLaunch &L, hipStream_t st);
 hipError_t launch_transform(const TransformLaunch &L, hipStream_t st);
 hipError_t launch_follow_step(const FollowLaunch &L, hipStream_t st);
+hipError_t launch_order(const OrderLaunch &L, hipStream_t st);
 hipError_t launch_track(int64_t n, int M, int Nt, double dt, const double *mc, const double *eta, const double *f0,
                         const double *ct, const double *ci, double *out, hipStream_t st);
 

@@ -82,6 +82,76 @@ __global__ void k_layout_offsets(int64_t n, const int32_t *__restrict__ nseg, co
     if (i == 0) seg_offset[0] = 0;
 }
 
+// ------------------------------------------------------------------ processing order
+__global__ void k_zero_u32(uint32_t *p, int n);
+
+// Counting sort of the bank by the frequency bin of f0 (invalid rows last): bucket
+// histogram, exclusive scan, scatter.  Within a bucket the order follows the atomics.
+__device__ __forceinline__ int order_bucket(double f0, double dT, int K, bool ok) {
+    if (!ok) return K;
+    const double b = floor(f0 * dT);
+    return b < 0.0 ? 0 : (b > (double)(K - 1) ? K - 1 : (int)b);
+}
+
+__global__ void k_order_hist(int64_t n, const double *__restrict__ mc, const double *__restrict__ eta,
+                             const double *__restrict__ f0, const double *__restrict__ ct,
+                             const double *__restrict__ ci, double dT, int K, uint32_t *__restrict__ count) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const bool ok = params_valid(mc[i], eta[i], f0[i], ct[i], ci[i]);
+    atomicAdd(count + order_bucket(f0[i], dT, K, ok), 1u);
+}
+
+// exclusive scan of count[0..nb) into cursor[0..nb), one block of 1024 threads
+__global__ void k_order_scan(int nb, const uint32_t *__restrict__ count, uint32_t *__restrict__ cursor) {
+    __shared__ uint32_t sh[1024];
+    __shared__ uint32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int base = 0; base < nb; base += 1024) {
+        const int idx = base + threadIdx.x;
+        const uint32_t v = idx < nb ? count[idx] : 0u;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const uint32_t t = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0u;
+            __syncthreads();
+            sh[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (idx < nb) cursor[idx] = carry + sh[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += sh[1023];
+        __syncthreads();
+    }
+}
+
+__global__ void k_order_scatter(int64_t n, const double *__restrict__ mc, const double *__restrict__ eta,
+                                const double *__restrict__ f0, const double *__restrict__ ct,
+                                const double *__restrict__ ci, double dT, int K, uint32_t *__restrict__ cursor,
+                                int32_t *__restrict__ order) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const bool ok = params_valid(mc[i], eta[i], f0[i], ct[i], ci[i]);
+    const uint32_t pos = atomicAdd(cursor + order_bucket(f0[i], dT, K, ok), 1u);
+    order[pos] = (int32_t)i;
+}
+
+hipError_t launch_order(const OrderLaunch &L, hipStream_t st) {
+    if (L.n == 0) return hipSuccess;
+    const int K = L.M / 2 + 1, nb = K + 1;
+    const double dT = (double)L.M * L.dt;
+    uint32_t *count = L.ws, *cursor = L.ws + nb;
+    const unsigned blocks = (unsigned)((L.n + 255) / 256);
+    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, count, nb);
+    hipLaunchKernelGGL(k_order_hist, dim3(blocks), dim3(256), 0, st, L.n, L.mc, L.eta, L.f0, L.ct, L.ci, dT, K,
+                       count);
+    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, st, nb, count, cursor);
+    hipLaunchKernelGGL(k_order_scatter, dim3(blocks), dim3(256), 0, st, L.n, L.mc, L.eta, L.f0, L.ct, L.ci, dT, K,
+                       cursor, L.order);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ geometry
 // Rigid analytic orbits (first order in e = L / (2 sqrt 3 R)) at t_m = m dT.
 __global__ void k_geometry(int Nt, double dT, double *__restrict__ geo) {
@@ -104,7 +174,7 @@ __global__ void k_geometry(int Nt, double dT, double *__restrict__ geo) {
         p[i][2] = -sqrt(3.0) * e * R * c1;
     }
     for (int i = 0; i < 3; ++i)
-        for (int x = 0; x < 3; ++x) geo[(3 * i + x) * (size_t)Nt + m] = p[i][x];
+        for (int x = 0; x < 3; ++x) geo[(size_t)(3 * i + x) * Nt + m] = p[i][x];
     for (int a2 = 0; a2 < 3; ++a2) {
         int s = a2, r = (a2 + 1) % 3;
         double d[3], nn = 0.0;
@@ -113,7 +183,7 @@ __global__ void k_geometry(int Nt, double dT, double *__restrict__ geo) {
             nn += d[x] * d[x];
         }
         nn = sqrt(nn);
-        for (int x = 0; x < 3; ++x) geo[(9 + 3 * a2 + x) * (size_t)Nt + m] = d[x] / nn;
+        for (int x = 0; x < 3; ++x) geo[(size_t)(9 + 3 * a2 + x) * Nt + m] = d[x] / nn;
     }
 }
 
@@ -194,6 +264,36 @@ __device__ __forceinline__ void close_segments(SegAcc<double> &acc, int upto, in
         ++acc.cur;
     }
 }
+
+// Segment boundaries b_s = ceil(s Nt / N_seg) stepped without division: tranche m lies in
+// segment s = floor(m N_seg / Nt) exactly when b_s <= m < b_{s+1}.  The state (s Nt =
+// qs N_seg + rs) advances by (q, r) = divmod(Nt, N_seg) per segment.
+struct SegWalk {
+    int s, lo, hi;      // current segment and its tranche range [lo, hi)
+    int q, r, ns;       // divmod(Nt, N_seg), N_seg
+    int qs, rs;         // (s + 1) Nt = qs N_seg + rs
+    __device__ __forceinline__ void init(int Nt, int nseg) {
+        ns = nseg;
+        q = Nt / nseg;
+        r = Nt - q * nseg;
+        s = 0;
+        lo = 0;
+        qs = q;
+        rs = r;
+        hi = qs + (rs > 0 ? 1 : 0);
+    }
+    __device__ __forceinline__ void step() {
+        ++s;
+        lo = hi;
+        qs += q;
+        rs += r;
+        if (rs >= ns) {
+            qs += 1;
+            rs -= ns;
+        }
+        hi = qs + (rs > 0 ? 1 : 0);
+    }
+};
 
 // Sum over the 21 bins of tranche m: P_c = sum conj(D_ck) h_k u_k, Q = sum |h_k u_k|^2.
 template <int C, class R, class PixT, int LAYOUT, class U>
@@ -457,13 +557,14 @@ __global__ __launch_bounds__(256, 3) void k_stat_wave(StatArgs a) {
 
     const int lane = threadIdx.x & 63;
     for (;;) {
-        // Work fetch in converged code: every lane joins one atomic (lane 0 adds 1, the
-        // others 0) and readfirstlane makes the item a wave-uniform scalar, so no
-        // cross-lane broadcast depends on reconvergence after a lane-0-only branch.
+        // Work fetch in converged code: every lane joins one atomic on a uniform address
+        // (lane 0 adds 1, the others 0), which the compiler turns into a single atomic per
+        // wave, and readfirstlane makes the item a wave-uniform scalar, so no cross-lane
+        // broadcast depends on reconvergence after a lane-0-only branch.
         const uint32_t mine = atomicAdd(a.counter, lane == 0 ? 1u : 0u);
-        const uint32_t item = __builtin_amdgcn_readfirstlane(mine);
-        if ((int64_t)item >= a.n) break;
-        const int64_t i = a.order ? (int64_t)__builtin_amdgcn_readfirstlane(a.order[item]) : (int64_t)item;
+        const int64_t item = (int64_t)__builtin_amdgcn_readfirstlane(mine);
+        if (item >= a.n) break;
+        const int64_t i = a.order ? (int64_t)__builtin_amdgcn_readfirstlane(a.order[item]) : item;
         if (i < 0 || i >= a.n) continue;  // malformed processing order: skip rather than fault
         const int ns = a.nseg[i];
         const int64_t off = a.seg_offset[i];
@@ -484,6 +585,8 @@ __global__ __launch_bounds__(256, 3) void k_stat_wave(StatArgs a) {
         Sky<R> S;
         sky_init(S, a.ct[i], a.phi[i], a.psi[i], a.ci[i]);
         int m_end = a.Nt, n_act = 0;
+        SegWalk sw;
+        sw.init(a.Nt, ns);
         for (int m0 = 0; m0 < m_end; m0 += 64) {
             const int m = m0 + lane;
             const bool inr = m < a.Nt;
@@ -523,18 +626,18 @@ __global__ __launch_bounds__(256, 3) void k_stat_wave(StatArgs a) {
             // segmented reduction over the lanes of this chunk
             const int last = min(min(m0 + 63, lim - 1), a.Nt - 1);
             if (last >= m0) {
-                const int s_first = (int)(((int64_t)m0 * ns) / a.Nt);
-                const int s_last = (int)(((int64_t)last * ns) / a.Nt);
-                const int my_s = (int)(((int64_t)m * ns) / a.Nt);
-                for (int s = s_first; s <= s_last; ++s) {
-                    const bool mine = active && my_s == s;
+                while (sw.hi <= m0) sw.step();
+                for (;;) {
+                    const bool mine = active && m >= sw.lo && m < sw.hi;
                     R vr = wave_sum<R>(mine ? zr : (R)0);
                     R vi = wave_sum<R>(mine ? zi : (R)0);
                     R vn = wave_sum<R>(mine ? nn : (R)0);
-                    close_segments(acc, s, off, a.seg_terms, a.seg_zn, writer);
+                    close_segments(acc, sw.s, off, a.seg_terms, a.seg_zn, writer);
                     acc.zr += (double)vr;
                     acc.zi += (double)vi;
                     acc.N += (double)vn;
+                    if (sw.hi > last) break;
+                    sw.step();
                 }
             }
             if (viol) break;

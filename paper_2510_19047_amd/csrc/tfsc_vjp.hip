@@ -297,26 +297,24 @@ __device__ inline void sky_dual(SkyD &S, double ct, double phi, double psi, doub
     S.ci = ci;
 }
 
-__device__ inline void transfer_ae_dual(const SkyD &S, const double *__restrict__ geo, int m, int Nt, double f,
-                                        CDn<4> &TA, CDn<4> &TE) {
+__device__ inline void transfer_ae_dual(const SkyD &S, const double (&g)[kGeoRows], double f, CDn<4> &TA,
+                                        CDn<4> &TE) {
     const double L = kArmM / kClight;
     Dn<4> F = dconst<4>(f);
     F.d[0] = 1.0;
     Dn<4> kp[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        const double px = geo[(3 * i + 0) * (size_t)Nt + m], py = geo[(3 * i + 1) * (size_t)Nt + m],
-                     pz = geo[(3 * i + 2) * (size_t)Nt + m];
-        kp[i] = S.k[0] * px + S.k[1] * py + S.k[2] * pz;
+        kp[i] = S.k[0] * g[3 * i] + S.k[1] * g[3 * i + 1] + S.k[2] * g[3 * i + 2];
     }
     const Dn<4> pfL = F * (kPi * L);
     CDn<4> Gd[3], Gr[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int s = a, r = (a + 1) % 3;
-        const double n0 = geo[(9 + 3 * a + 0) * (size_t)Nt + m];
-        const double n1 = geo[(9 + 3 * a + 1) * (size_t)Nt + m];
-        const double n2 = geo[(9 + 3 * a + 2) * (size_t)Nt + m];
+        const double n0 = g[9 + 3 * a + 0];
+        const double n1 = g[9 + 3 * a + 1];
+        const double n2 = g[9 + 3 * a + 2];
         Dn<4> kn = S.k[0] * n0 + S.k[1] * n1 + S.k[2] * n2;
         Dn<4> nu = S.u[0] * n0 + S.u[1] * n1 + S.u[2] * n2;
         Dn<4> nv = S.v[0] * n0 + S.v[1] * n1 + S.v[2] * n2;
@@ -563,7 +561,9 @@ __global__ __launch_bounds__(256) void k_vjp_wave(VjpArgs a) {
                             Vi[p] *= w2;
                         }
                         CDn<4> Tc[2];
-                        transfer_ae_dual(S, a.geo, m, a.Nt, f, Tc[0], Tc[1]);
+                        double gm[kGeoRows];
+                        load_geo(a.geo, m, a.Nt, gm);
+                        transfer_ae_dual(S, gm, f, Tc[0], Tc[1]);
 #pragma unroll
                         for (int c = 0; c < C; ++c) {
                             const double tr = Tc[c].re.v, ti = Tc[c].im.v;

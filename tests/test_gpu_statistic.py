@@ -172,3 +172,25 @@ def test_16bit_store_error_against_oracle(dtype, tol):
     note(f"  {dtype}: max rel {r.max():.2e} median {np.median(r):.2e} p99 {np.quantile(r, 0.99):.2e}")
     assert r.max() < tol
     assert np.array_equal(res.flags.cpu().numpy(), ref.flags)
+
+
+def test_device_processing_order():
+    """tfsc_processing_order: a permutation sorted by the f0 bin (invalid last); results do not depend on it."""
+    tfsc = lib()
+    d = small_data()
+    g = d["grid"]
+    b = d["bank"]
+    note("device processing order")
+    bt = _bank(tfsc, b)
+    order = tfsc.processing_order(gridspec(g), bt).cpu().numpy()
+    assert np.array_equal(np.sort(order), np.arange(len(b)))
+    valid = otrk.params_valid(b.mc, b.eta, b.f0, b.cos_theta, b.cos_iota)
+    K = g.tranche_len // 2 + 1
+    key = np.where(valid, np.clip(np.floor(b.f0 * g.tranche_dur), 0, K - 1), K)
+    assert np.all(np.diff(key[order]) >= 0)
+    seg = tfsc.segment_layout(gridspec(g), bt)
+    store = store_from_oracle(d, "f32")
+    a = tfsc.bank_statistic(gridspec(g), store, bt, seg, precision="f32", schedule="wave")
+    c = tfsc.bank_statistic(gridspec(g), store, bt, seg, precision="f32", schedule="wave",
+                            order=torch.from_numpy(order).cuda())
+    assert torch.equal(a.stat, c.stat) and torch.equal(a.flags, c.flags)
