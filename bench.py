@@ -208,7 +208,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(n, args.chosen_store, "bank" if order is None else "f0 bin",
+                                        (kw["block_waves"], kw["groups_per_cu"])),
             "kernel": "k_stat_wave",
             "kernel_ms": round(k_ms, 3),
             "alg_bytes_per_launch": alg_bytes,
@@ -229,6 +230,33 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, x, psd, mu, keep, bank_h, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def measured_traffic(n, store, order, shape):
+    """Calibrated bytes beyond L2 per k_stat_wave launch from the committed rocprofv3 counter runs.
+
+    Only valid while the kernel source and the configuration are the ones that were profiled;
+    otherwise None.
+    """
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(root, "profiles", "k_stat_wave_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#") and ":" in line:
+                k, v = line.split(":", 1)
+                rec[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in ("tfsc_stat.hip", "tfsc_device.hpp", "tfsc_kernels.hpp"):
+        with open(os.path.join(root, "paper_2510_19047_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    same = (rec.get("source_sha256") == h.hexdigest() and rec.get("n_templates") == str(n)
+            and rec.get("pixel_store") == store and rec.get("order") == order
+            and rec.get("launch_shape") == f"{shape[0]}x{shape[1]}")
+    return float(rec["traffic_bytes"]) if same else None
 
 
 def cpu_baseline(g, x, psd, mu, keep, bank_h, seconds):
