@@ -100,12 +100,36 @@ def lisa_like_psd_ae(f):
     return 8.0 * np.sin(w * L) ** 2 * ((2.0 + c1) * s_oms + 2.0 * (3.0 + 2.0 * c1 + c2) * s_acc)
 
 
-def psd_on_bins(grid: GridSpec) -> np.ndarray:
-    """S0(f_k) at the tranche bins f_k = k / (M dt), k = 0..M/2.  Bin 0 copies bin 1."""
+def psd_on_bins(grid: GridSpec, alpha: float = 0.1, reach: int = 32, oversample: int = 16) -> np.ndarray:
+    """Whitening PSD S0_k at the tranche bins f_k = k / (M dt), k = 0..M/2 (bin 0 copies bin 1).
+
+    S0_k is the analytic PSD averaged over the spectral window of one tranche (Tukey(alpha), M
+    samples): S0_k = sum_nu S(f_k + nu) K(nu) / sum_nu K(nu), K = |W(nu)|^2 on a grid of step
+    1/(oversample M dt) over +-reach bins.  This is the expected periodogram of the noise at bin k,
+    so the whitened pixels have unit variance also at the TDI null f = 1/(2L), whose width is far
+    below one bin (there the PSD at the bin centre is 1e3 times below the tranche's average power).
+    Frequencies below 0 and above Nyquist are folded back; the lowest bins (far below the band of
+    any template here) see only the window's main lobe and near sidelobes.
+    """
+    M, dT = grid.tranche_len, grid.tranche_dur
+    if alpha <= 0.0:
+        w = np.ones(M)
+    else:
+        from scipy.signal.windows import tukey
+        w = tukey(M, alpha)
+    n_fine = oversample * M
+    K = np.abs(np.fft.fft(w, n=n_fine)) ** 2
+    q = np.arange(-reach * oversample, reach * oversample + 1)
+    Kq = K[q % n_fine]
+    Kq = Kq / Kq.sum()
+    nu = q / (oversample * dT)
+    fnyq = 0.5 / grid.dt
     k = np.arange(grid.n_bins, dtype=np.float64)
-    f = k / grid.tranche_dur
-    out = np.empty(grid.n_bins)
-    out[1:] = lisa_like_psd_ae(f[1:])
+    f = k[:, None] / dT + nu[None, :]
+    f = np.abs(f)
+    f = np.where(f > fnyq, 2.0 * fnyq - f, f)
+    f = np.maximum(f, 1.0 / (oversample * dT))
+    out = (lisa_like_psd_ae(f) * Kq[None, :]).sum(axis=1)
     out[0] = out[1]
     return out
 
