@@ -46,6 +46,12 @@ def parse():
     p.add_argument("--block-waves", type=int, default=0, help="fix the launch shape (0 = autotune)")
     p.add_argument("--groups-per-cu", type=int, default=0)
     p.add_argument("--no-order", action="store_true", help="process the bank in its own order")
+    p.add_argument("--batching", action="store_true",
+                   help="also time the batching workload: 4M wide-range templates over 16 noise realisations "
+                        "replayed from one HIP graph (adds about a minute)")
+    p.add_argument("--follow-up", action="store_true",
+                   help="also run the differentiation workload: 50 Adam steps on the top 65,536 templates of "
+                        "the batching bank (implies --batching)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="copy 256 MiB device-to-device once, so profiler byte counters can be calibrated")
     return p.parse_args()
@@ -179,6 +185,8 @@ def main():
     sc, sp = res_c.stat.cpu().numpy(), res_p.stat.cpu().numpy()
     rel_cp = float(np.max(np.abs(sc - sp) / np.maximum(np.abs(sp), 1.0)))
 
+    traffic, traffic_shape = measured_traffic(n, args.chosen_store, "bank" if order is None else "f0 bin",
+                                              (kw["block_waves"], kw["groups_per_cu"]))
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -208,8 +216,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(n, args.chosen_store, "bank" if order is None else "f0 bin",
-                                        (kw["block_waves"], kw["groups_per_cu"])),
+            "traffic": traffic,
+            "traffic_launch_shape": traffic_shape,
             "kernel": "k_stat_wave",
             "kernel_ms": round(k_ms, 3),
             "alg_bytes_per_launch": alg_bytes,
@@ -227,16 +235,68 @@ def main():
     }
 
     # ---------------- CPU baseline: the plain-C oracle on host cores, bounded sample
+    if args.batching or args.follow_up:
+        del res, res_c, res_p, pix_plain
+        torch.cuda.empty_cache()
+        out["batching"] = batching_run(args, tfsc, ti, grid, g, psd_d, mu_d, keep_d, kw)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, x, psd, mu, keep, bank_h, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
+def batching_run(args, tfsc, ti, grid, g, psd_d, mu_d, keep_d, kw):
+    """4M wide-range templates x 16 realisations in one HIP graph; optionally the Adam follow-up."""
+    import torch
+    from paper_2510_19047_amd import batching
+    dev = psd_d.device
+    R = 16
+    log("batching: 4M-template bank and 16 noise realisations")
+    bank_h = ti.batching_bank()
+    bank = tfsc.BankTensors.from_host(bank_h, dev)
+    seg = tfsc.segment_layout(grid, bank)
+    order = tfsc.processing_order(grid, bank)
+    keepm = ti.sample_keep_mask(g)[None, :]
+    xs = torch.empty((R, g.n_channels, g.n_samples), dtype=torch.float32, device=dev)
+    for r in range(R):
+        xs[r] = torch.from_numpy((ti.noise(g, realisation=r) * keepm).astype(np.float32)).to(dev)
+    rg = batching.RealisationGraph(grid, xs, psd_d, mu_d, keep_d, bank, seg, store="f32", precision="f32",
+                                   order=order, **kw)
+    rg.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rg.replay()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    evals = bank.n * R
+    log(f"batching: one replay {wall * 1e3:.1f} ms, {evals / wall / 1e6:.3f} M template-realisations/s")
+    rec = {"templates": bank.n, "realisations": R, "ms_per_replay": round(wall * 1e3, 2),
+           "template_realisations_per_s": round(evals / wall, 1), "graph": "transform + statistic x 16"}
+    if args.follow_up:
+        stat0 = rg.results[0].stat
+        top = torch.topk(torch.nan_to_num(stat0, nan=-1.0), 65536).indices
+        sub = tfsc.BankTensors(*(getattr(bank, k)[top].contiguous() for k in tfsc.BankTensors.FIELDS))
+        store0 = rg.stores[0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        first, best, _ = tfsc.follow_up(grid, store0, sub, steps=50, lr_scale=0.5, precision="f32")
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        gain = (best - first).cpu().numpy()
+        log(f"follow-up: 50 Adam steps on 65536 templates in {wall:.2f} s; gain median {np.median(gain):.2f}, "
+            f"p90 {np.quantile(gain, 0.9):.2f}")
+        rec["follow_up"] = {"templates": 65536, "steps": 50, "wall_s": round(wall, 3),
+                            "gain_median": round(float(np.median(gain)), 3),
+                            "gain_p90": round(float(np.quantile(gain, 0.9)), 3),
+                            "start_median": round(float(first.median().item()), 3)}
+    return rec
+
+
 def measured_traffic(n, store, order, shape):
     """Calibrated bytes beyond L2 per k_stat_wave launch from the committed rocprofv3 counter runs.
 
-    Only valid while the kernel source and the configuration are the ones that were profiled;
-    otherwise None.
+    Only valid while the kernel source, the bank, the store and the processing order are the ones
+    that were profiled; otherwise None.  The launch shape the counters were taken with is returned
+    beside it (the autotuner's choice can differ between boxes by timings within noise).
     """
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
@@ -254,9 +314,8 @@ def measured_traffic(n, store, order, shape):
         with open(os.path.join(root, "paper_2510_19047_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     same = (rec.get("source_sha256") == h.hexdigest() and rec.get("n_templates") == str(n)
-            and rec.get("pixel_store") == store and rec.get("order") == order
-            and rec.get("launch_shape") == f"{shape[0]}x{shape[1]}")
-    return float(rec["traffic_bytes"]) if same else None
+            and rec.get("pixel_store") == store and rec.get("order") == order)
+    return (float(rec["traffic_bytes"]), rec.get("launch_shape")) if same else (None, None)
 
 
 def cpu_baseline(g, x, psd, mu, keep, bank_h, seconds):
