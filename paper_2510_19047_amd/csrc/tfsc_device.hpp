@@ -260,13 +260,16 @@ __device__ inline void transfer_ae(const Sky<R> &S, const double *__restrict__ g
     cx<R> D = expi_rev((R)(-rl));
     const double rf = rl > 0.25 ? 0.5 - rl : (rl < -0.25 ? -0.5 - rl : rl);
     const R s2 = sin_rev_accurate((R)rf);
-    cx<R> om = {(R)-2 * s2 * D.im, (R)2 * s2 * D.re};
-    cx<R> TX = cmul(om, csub(cadd(G20, cmul(D, G02)), cadd(G10, cmul(D, G01))));
-    cx<R> TY = cmul(om, csub(cadd(G01, cmul(D, G10)), cadd(G21, cmul(D, G12))));
-    cx<R> TZ = cmul(om, csub(cadd(G12, cmul(D, G21)), cadd(G02, cmul(D, G20))));
+    // X = (1 - D^2)[(G20 - G10) + D (G02 - G01)] and cyclic; the common factor 1 - D^2 and the
+    // 1/sqrt2, 1/sqrt6 of A and E are applied once to the combinations.
+    const cx<R> Xp = cadd(csub(G20, G10), cmul(D, csub(G02, G01)));
+    const cx<R> Yp = cadd(csub(G01, G21), cmul(D, csub(G10, G12)));
+    const cx<R> Zp = cadd(csub(G12, G02), cmul(D, csub(G21, G20)));
     const R is2 = (R)0.70710678118654752440, is6 = (R)0.40824829046386301637;
-    TA = cscale(csub(TZ, TX), is2);
-    TE = cscale(cadd(csub(TX, cscale(TY, (R)2)), TZ), is6);
+    const cx<R> oma = {(R)-2 * is2 * s2 * D.im, (R)2 * is2 * s2 * D.re};
+    const cx<R> ome = {(R)-2 * is6 * s2 * D.im, (R)2 * is6 * s2 * D.re};
+    TA = cmul(oma, csub(Zp, Xp));
+    TE = cmul(ome, cadd(csub(Xp, cscale(Yp, (R)2)), Zp));
 }
 
 // ------------------------------------------------------------------ tranche spectrum

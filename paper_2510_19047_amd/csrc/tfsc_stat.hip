@@ -533,8 +533,54 @@ __device__ __forceinline__ void wave_tranche_bins(const TrancheSpec<R> &ts, int 
     }
 }
 
+// Per-template constants are the same in every lane of a wave; stating that with
+// readfirstlane lets the compiler keep them in scalar registers instead of 64-lane
+// vector registers, which the tranche loop needs for occupancy.
+__device__ __forceinline__ double wave_uniform(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ float wave_uniform(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(uint32_t, v)));
+}
+
+__device__ __forceinline__ void wave_uniform(Track &T) {
+    T.eta = wave_uniform(T.eta);
+    T.M = wave_uniform(T.M);
+    T.c8 = wave_uniform(T.c8);
+    T.a2 = wave_uniform(T.a2);
+    T.a3 = wave_uniform(T.a3);
+    T.a4 = wave_uniform(T.a4);
+    T.b2 = wave_uniform(T.b2);
+    T.b3 = wave_uniform(T.b3);
+    T.b4 = wave_uniform(T.b4);
+    T.tc = wave_uniform(T.tc);
+    T.th0 = wave_uniform(T.th0);
+    T.i5M = wave_uniform(T.i5M);
+    T.ic8 = wave_uniform(T.ic8);
+    T.i40M = wave_uniform(T.i40M);
+    T.m2ieta = wave_uniform(T.m2ieta);
+}
+
+template <class R>
+__device__ __forceinline__ void wave_uniform(Sky<R> &S) {
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        S.k[q] = wave_uniform(S.k[q]);
+        S.u[q] = wave_uniform(S.u[q]);
+        S.v[q] = wave_uniform(S.v[q]);
+        S.kd[q] = wave_uniform(S.kd[q]);
+    }
+    S.c2 = wave_uniform(S.c2);
+    S.s2 = wave_uniform(S.s2);
+    S.ap = wave_uniform(S.ap);
+    S.ci = wave_uniform(S.ci);
+}
+
 template <int C, class R, class PixT>
-__global__ __launch_bounds__(256, 3) void k_stat_wave(StatArgs a) {
+__global__ __launch_bounds__(256, 4) void k_stat_wave(StatArgs a) {
     // Zero-padded template weights u_pad[k + 10] = u_k for 1 <= k <= M/2 - 1 (else 0), and
     // the 16-bit layer scales, staged in LDS once per block.
     extern __shared__ unsigned char smem_raw[];
@@ -582,8 +628,10 @@ __global__ __launch_bounds__(256, 3) void k_stat_wave(StatArgs a) {
         }
         Track T;
         track_init(T, a.mc[i], a.eta[i], a.f0[i]);
+        wave_uniform(T);
         Sky<R> S;
         sky_init(S, a.ct[i], a.phi[i], a.psi[i], a.ci[i]);
+        wave_uniform(S);
         int m_end = a.Nt, n_act = 0;
         SegWalk sw;
         sw.init(a.Nt, ns);

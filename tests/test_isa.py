@@ -2,7 +2,7 @@
 
 * the work fetch issues one atomic per wave (the compiler's atomic optimizer pattern: v_mbcnt to
   elect one lane), not 64 lane atomics on one address, which serialise;
-* no register spills to scratch memory in the FP32-arithmetic instantiations.
+* at most a few registers spilled to scratch in the FP32-arithmetic instantiations.
 """
 import os
 import re
@@ -49,14 +49,15 @@ def test_wave_kernel_fetch_is_one_atomic_per_wave(asm):
     assert found >= 4
 
 
-def test_wave_kernel_has_no_scratch(asm):
-    """The FP32-arithmetic instantiations (every pixel store) keep everything in registers; the FP64
-    validation path may spill."""
+def test_wave_kernel_scratch_is_small(asm):
+    """The FP32-arithmetic instantiations (every pixel store) spill at most a few registers at the
+    four-waves-per-SIMD launch bound (measured faster than three waves without spills); the FP64
+    validation path may spill more."""
     n = 0
     for name, body in _kernels(asm, "k_stat_wave"):
         if not re.match(r"_ZN4tfsc11k_stat_waveILi[12]Ef", name):
             continue
         n += 1
         size = int(re.search(r"; ScratchSize: (\d+)", body).group(1))
-        assert size == 0, (name, size)
+        assert size <= 64, (name, size)
     assert n >= 4
