@@ -355,6 +355,36 @@ __device__ __forceinline__ cx<R> bin_full(const TrancheSpec<R> &ts, R xj) {
     return cscale(h, ts.P);
 }
 
+// h_j w for a bin in the asymptotic region, with the weight w folded into the reciprocals.
+template <class R>
+__device__ __forceinline__ cx<R> bin_fast_weighted(const TrancheSpec<R> &ts, R xj, R w) {
+#pragma clang fp contract(fast)
+    const R xj1 = xj + ts.beta;
+    const R qw = ts.Q * w;
+    R a, b;
+    if constexpr (sizeof(R) == 4) {
+        const R r = rcp(xj * xj1) * qw;
+        a = xj1 * r;
+        b = xj * r;
+    } else {
+        a = qw / xj;
+        b = qw / xj1;
+    }
+    const R re = ts.E0.re * a - ts.E1.re * b;
+    const R im = ts.E0.im * a - ts.E1.im * b;
+    return {-im, re};
+}
+
+// h_j w for bin k_c + j: asymptotic form where both Fresnel arguments exceed 6 and no bin
+// frequency is crossed, the general form otherwise.
+template <class R>
+__device__ __forceinline__ cx<R> tranche_bin_weighted(const TrancheSpec<R> &ts, int j, R w) {
+    R xj = ts.x - (R)j;
+    if (xj > ts.r6 || xj + ts.beta < -ts.r6) return bin_fast_weighted(ts, xj, w);
+    const cx<R> h = bin_full(ts, xj);
+    return {h.re * w, h.im * w};
+}
+
 template <class R>
 __device__ __forceinline__ cx<R> tranche_spectrum_bin(const TrancheSpec<R> &ts, int j) {
     R xj = ts.x - (R)j;

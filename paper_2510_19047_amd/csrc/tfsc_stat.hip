@@ -310,9 +310,7 @@ __device__ __forceinline__ void tranche_bins(const StatArgs &a, const TrancheSpe
     for (int j = -kHalfBins; j <= kHalfBins; ++j) {
         int k = kc + j;
         if (k < 1 || k > kmax) continue;
-        cx<R> h = tranche_spectrum_bin(ts, j);
-        R w = (R)(u_tab[k] * u_mul);
-        cx<R> g = {h.re * w, h.im * w};
+        const cx<R> g = tranche_bin_weighted(ts, j, (R)(u_tab[k] * u_mul));
         Q += g.re * g.re;
         Q += g.im * g.im;
 #pragma unroll
@@ -510,9 +508,14 @@ __device__ __forceinline__ void wave_tranche_bins(const TrancheSpec<R> &ts, int 
     for (int jj = 0; jj < 2 * kHalfBins + 1; ++jj) {
         const int j = jj - kHalfBins;
         const R xj = ts.x - (R)j;
-        cx<R> h = (j >= jA && j <= jB) ? bin_full(ts, xj) : bin_fast(ts, xj);
         const R w = uk[jj];
-        const cx<R> g = {h.re * w, h.im * w};
+        cx<R> g;
+        if (j >= jA && j <= jB) {
+            const cx<R> h = bin_full(ts, xj);
+            g = {h.re * w, h.im * w};
+        } else {
+            g = bin_fast_weighted(ts, xj, w);
+        }
         Q += g.re * g.re;
         Q += g.im * g.im;
 #pragma unroll
