@@ -284,17 +284,29 @@ __device__ inline void transfer_ae(const Sky<R> &S, const double *__restrict__ g
 // the paper's f, g (rational for |z| <= 6, f = 1/(pi |z|), g = 0 above).  When
 // both |v| > 6 and no bin frequency is crossed this is
 //   h_j = i Q (e^{i phi_m} / (x - j) - e^{i phi_end} / (x - j + beta)),  Q = A dT / (2 pi).
+//
+// The paper's Fresnel forms jump at |z| = 6 (by up to ~5e-4), so which branch a bin edge
+// takes is an integer decision and is made in FP64 for every precision: |v0| <= 6 exactly
+// for j in [j0lo, j0hi] and |v1| <= 6 for j in [j1lo, j1hi] (computed from FP64 x, beta
+// and r6 = 6 / s).  A bin is in the asymptotic-only region exactly when j < j0lo or
+// j > j1hi.
 template <class R>
 struct TrancheSpec {
-    R x, beta, s, r6, P, Q, half_inv_beta;
+    R x, beta, s, P, Q, half_inv_beta;
     cx<R> E0, E1;
     double rev0;  // phi_m in revolutions, reduced
+    int j0lo, j0hi, j1lo, j1hi;
 };
 
 template <class R>
-__device__ __forceinline__ void fresnel_fg(R av, R &f, R &g) {
+__device__ __forceinline__ bool bin_is_fast(const TrancheSpec<R> &ts, int j) {
+    return j < ts.j0lo || j > ts.j1hi;
+}
+
+template <class R>
+__device__ __forceinline__ void fresnel_fg(R av, bool rational, R &f, R &g) {
 #pragma clang fp contract(fast)
-    if (av > (R)6) {
+    if (!rational) {
         f = rcp((R)kPi * av);
         g = (R)0;
     } else {
@@ -309,8 +321,8 @@ __device__ __forceinline__ R sgn(R v) {
     return v > (R)0 ? (R)1 : (v < (R)0 ? (R)-1 : (R)0);
 }
 
-// Asymptotic Fresnel on both tranche edges and no bin frequency crossed (valid when
-// x - j > r6 or x - j + beta < -r6):  h_j = i Q (e^{i phi_m}/(x - j) - e^{i phi_end}/(x - j + beta)).
+// Asymptotic Fresnel on both tranche edges and no bin frequency crossed (bin_is_fast):
+// h_j = i Q (e^{i phi_m}/(x - j) - e^{i phi_end}/(x - j + beta)).
 template <class R>
 __device__ __forceinline__ cx<R> bin_fast(const TrancheSpec<R> &ts, R xj) {
 #pragma clang fp contract(fast)
@@ -330,16 +342,16 @@ __device__ __forceinline__ cx<R> bin_fast(const TrancheSpec<R> &ts, R xj) {
     return {-ts.Q * im, ts.Q * re};
 }
 
-// General form, valid for every bin (both Fresnel branches, stationary-phase term).
+// General form, valid for every bin j (both Fresnel branches, stationary-phase term).
 template <class R>
-__device__ __forceinline__ cx<R> bin_full(const TrancheSpec<R> &ts, R xj) {
+__device__ __forceinline__ cx<R> bin_full(const TrancheSpec<R> &ts, R xj, int j) {
 #pragma clang fp contract(fast)
     R xj1 = xj + ts.beta;
     R v0 = ts.s * xj, v1 = ts.s * xj1;
     R sg0 = sgn(v0), sg1 = sgn(v1);
     R f0, g0, f1, g1;
-    fresnel_fg(fabs(v0), f0, g0);
-    fresnel_fg(fabs(v1), f1, g1);
+    fresnel_fg(fabs(v0), j >= ts.j0lo && j <= ts.j0hi, f0, g0);
+    fresnel_fg(fabs(v1), j >= ts.j1lo && j <= ts.j1hi, f1, g1);
     cx<R> t0 = cmul(cx<R>{sg0 * g0, sg0 * f0}, ts.E0);
     cx<R> t1 = cmul(cx<R>{sg1 * g1, sg1 * f1}, ts.E1);
     cx<R> h = csub(t0, t1);
@@ -380,16 +392,16 @@ __device__ __forceinline__ cx<R> bin_fast_weighted(const TrancheSpec<R> &ts, R x
 template <class R>
 __device__ __forceinline__ cx<R> tranche_bin_weighted(const TrancheSpec<R> &ts, int j, R w) {
     R xj = ts.x - (R)j;
-    if (xj > ts.r6 || xj + ts.beta < -ts.r6) return bin_fast_weighted(ts, xj, w);
-    const cx<R> h = bin_full(ts, xj);
+    if (bin_is_fast(ts, j)) return bin_fast_weighted(ts, xj, w);
+    const cx<R> h = bin_full(ts, xj, j);
     return {h.re * w, h.im * w};
 }
 
 template <class R>
 __device__ __forceinline__ cx<R> tranche_spectrum_bin(const TrancheSpec<R> &ts, int j) {
     R xj = ts.x - (R)j;
-    if (xj > ts.r6 || xj + ts.beta < -ts.r6) return bin_fast(ts, xj);
-    return bin_full(ts, xj);
+    if (bin_is_fast(ts, j)) return bin_fast(ts, xj);
+    return bin_full(ts, xj, j);
 }
 
 // Tranche constants from the FP64 track.  Returns k_c.  Bin index, offset and
@@ -404,12 +416,19 @@ __device__ __forceinline__ int tranche_setup(TrancheSpec<R> &ts, double Phi, dou
     double rev1 = frac_rev(rev0 + x + 0.5 * beta);
     ts.x = (R)x;
     ts.beta = (R)beta;
+    {
+        // rational-branch bin ranges of the two edges, decided in FP64 (|v| <= 6 is rational)
+        const double r6 = 6.0 / sqrt(2.0 / beta);
+        ts.j0lo = (int)ceil(x - r6);
+        ts.j0hi = (int)floor(x + r6);
+        ts.j1lo = (int)ceil((x + beta) - r6);
+        ts.j1hi = (int)floor((x + beta) + r6);
+    }
     if constexpr (sizeof(R) == 8) {
         ts.s = sqrt(2.0 / beta);
         double A = pow(f, 2.0 / 3.0);
         ts.P = A / sqrt(2.0 * fdot);
         ts.Q = A * dT / kTwoPi;
-        ts.r6 = 6.0 / ts.s;
         ts.half_inv_beta = 0.5 / beta;
     } else {
         float b = (float)beta;
@@ -418,7 +437,6 @@ __device__ __forceinline__ int tranche_setup(TrancheSpec<R> &ts, double Phi, dou
         float A = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf((float)f) * (2.0f / 3.0f));
         ts.P = A * __builtin_amdgcn_rsqf((float)(2.0 * fdot));
         ts.Q = A * (float)(dT / kTwoPi);
-        ts.r6 = sqrtf(18.0f * b);  // 6 / s
         ts.half_inv_beta = 0.5f * ib;
     }
     ts.E0 = expi_rev((R)rev0);

@@ -511,7 +511,7 @@ __device__ __forceinline__ void wave_tranche_bins(const TrancheSpec<R> &ts, int 
         const R w = uk[jj];
         cx<R> g;
         if (j >= jA && j <= jB) {
-            const cx<R> h = bin_full(ts, xj);
+            const cx<R> h = bin_full(ts, xj, j);
             g = {h.re * w, h.im * w};
         } else {
             g = bin_fast_weighted(ts, xj, w);
@@ -657,16 +657,15 @@ __global__ __launch_bounds__(256, 4) void k_stat_wave(StatArgs a) {
             n_act += __popcll(__ballot(work));
             TrancheSpec<R> ts;
             int kc = 0;
-            float reach = 0.0f;  // x + beta + r6 bound of the exact-form bins
+            float nlo = -1e9f, hi = -1e9f;  // -(first) and last bin that is not asymptotic-only
             if (work) {
                 kc = tranche_setup(ts, Phi, f, fdot, a.dT);
-                reach = (float)(ts.beta + ts.r6);
+                nlo = (float)(-ts.j0lo);
+                hi = (float)ts.j1hi;
             }
-            // Exact-form bins: x - r6 <= j <= x + beta + r6 with x in (-1, 0], so every lane's
-            // such bins lie in [floor(-1 - rmax) + 1, floor(rmax)] (margin 1e-3 for rounding).
-            const float rmax = dpp_max_f32(reach);
-            const int jA = (int)floorf(-1.0f - rmax - 1e-3f) + 1;
-            const int jB = (int)floorf(rmax + 1e-3f);
+            // The wave takes the general form on the union [jA, jB] of the lanes' such bins.
+            const int jA = -(int)dpp_max_f32(nlo);
+            const int jB = (int)dpp_max_f32(hi);
             R zr = 0, zi = 0, nn = 0;
             if (work) {
                 cx<R> P[C];

@@ -32,21 +32,25 @@ def full_data():
     return dict(grid=g, x=x, psd=psd, mu=mu, keep=keep, pix=pix, u=u, wm=wm, bank=bank)
 
 
-@pytest.mark.parametrize("precision,source", [("f32", "gpu"), ("f32", "oracle"), ("f64", "oracle")])
-def test_full_size_sampled_parity(precision, source):
+@pytest.mark.parametrize("precision,source,schedule", [("f32", "gpu", "wave"), ("f32", "oracle", "wave"),
+                                                       ("f64", "oracle", "wave"), ("f32", "gpu", "thread"),
+                                                       ("f64", "oracle", "thread")])
+def test_full_size_sampled_parity(precision, source, schedule):
     tfsc = lib()
     d = full_data()
     g = d["grid"]
     bt = tfsc.BankTensors.from_host(d["bank"])
     seg = tfsc.segment_layout(gridspec(g), bt)
+    layout = "layer" if schedule == "wave" else "tranche"
     if source == "gpu":
-        note(f"full size: GPU transform (f32) -> wave statistic ({precision})")
-        st = tfsc.transform(gridspec(g), dev(d["x"]), dev(d["psd"]), dev(d["mu"]), dev(d["keep"]), dtype="f32")
+        note(f"full size: GPU transform (f32, {layout}) -> {schedule} statistic ({precision})")
+        st = tfsc.transform(gridspec(g), dev(d["x"]), dev(d["psd"]), dev(d["mu"]), dev(d["keep"]), dtype="f32",
+                            layout=layout)
     else:
-        note(f"full size: oracle pixels stored {precision} -> wave statistic ({precision})")
-        st = tfsc.PixelStore.from_complex(dev(d["pix"]), dev(d["u"]), dev(d["wm"]), dtype=precision)
+        note(f"full size: oracle pixels stored {precision} ({layout}) -> {schedule} statistic ({precision})")
+        st = tfsc.PixelStore.from_complex(dev(d["pix"]), dev(d["u"]), dev(d["wm"]), dtype=precision, layout=layout)
     tol = 1e-4 if precision == "f32" else 1e-6
-    res = tfsc.bank_statistic(gridspec(g), st, bt, seg, precision=precision, schedule="wave")
+    res = tfsc.bank_statistic(gridspec(g), st, bt, seg, precision=precision, schedule=schedule)
     stat = res.stat.cpu().numpy()
     flags = res.flags.cpu().numpy()
     sample = np.concatenate([np.arange(20), np.arange(20, len(d["bank"]), 16)])
@@ -63,3 +67,35 @@ def test_full_size_sampled_parity(precision, source):
     seg_off = seg.seg_offset.cpu().numpy()
     assert np.array_equal(np.diff(seg_off)[sample], ref.nseg)
     assert set(np.unique(np.diff(seg_off))) <= {16, 32, 64, 128, 256}
+
+
+def test_whole_bank_fp32_forms_against_fp64_path():
+    """All 1,000,020 templates: both FP32 forms against the FP64 path (itself within 2e-9 of the oracle
+    on the sampled templates above), in the bench's configuration."""
+    tfsc = lib()
+    g = ti.FULL
+    note("whole bank: FP32 wave and thread forms vs the FP64 path")
+    x = ti.noise(g) * ti.sample_keep_mask(g)[None, :]
+    psd, mu, keep = ti.psd_on_bins(g), ti.tranche_psd_scale(g), ti.tranche_keep(g)
+    bank_h = ti.full_bank(1_000_000)
+    bt = tfsc.BankTensors.from_host(bank_h)
+    grid = gridspec(g)
+    seg = tfsc.segment_layout(grid, bt)
+    order = tfsc.processing_order(grid, bt)
+    st64 = tfsc.transform(grid, dev(x), dev(psd), dev(mu), dev(keep), dtype="f64")
+    ref = tfsc.bank_statistic(grid, st64, bt, seg, precision="f64", schedule="wave", order=order).stat
+    ref = ref.cpu().numpy()
+    del st64
+    x32 = dev(x.astype(np.float32))
+    for schedule, layout in (("wave", "layer"), ("thread", "tranche")):
+        st = tfsc.transform(grid, x32, dev(psd), dev(mu), dev(keep), dtype="f32", layout=layout)
+        s = tfsc.bank_statistic(grid, st, bt, seg, precision="f32", schedule=schedule,
+                                order=order if schedule == "wave" else None).stat.cpu().numpy()
+        r = rel(s, ref)
+        w = np.argsort(r)[-3:]
+        note(f"  {schedule}: max rel {r.max():.2e}  p99.99 {np.quantile(r, 0.9999):.2e}  median {np.median(r):.2e}")
+        for i in w:
+            note(f"    worst: idx {i} rel {r[i]:.2e} stat {s[i]:.3f} fp64 {ref[i]:.3f} mc {bank_h.mc[i]:.2f} "
+                 f"f0 {bank_h.f0[i]:.5f}")
+        assert r.max() < 1e-4
+        del st
