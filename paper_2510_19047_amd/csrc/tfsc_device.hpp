@@ -418,7 +418,7 @@ __device__ __forceinline__ int tranche_setup(TrancheSpec<R> &ts, double Phi, dou
     ts.beta = (R)beta;
     {
         // rational-branch bin ranges of the two edges, decided in FP64 (|v| <= 6 is rational)
-        const double r6 = 6.0 / sqrt(2.0 / beta);
+        const double r6 = sqrt(18.0 * beta);  // 6 / s with s = sqrt(2 / beta)
         ts.j0lo = (int)ceil(x - r6);
         ts.j0hi = (int)floor(x + r6);
         ts.j1lo = (int)ceil((x + beta) - r6);
