@@ -82,7 +82,7 @@ size_t pixel_store_bytes(const tfsc_grid *g, const tfsc_pixels *p) {
     return b * (size_t)g->n_channels * (size_t)(g->tranche_len / 2 + 1) * (size_t)g->n_tranches;
 }
 
-size_t geo_bytes(int Nt) { return align_up(sizeof(double) * 18 * (size_t)Nt); }
+size_t geo_bytes(int Nt) { return tfsc::geo64_bytes(Nt) + tfsc::geo32_bytes(Nt); }
 
 size_t ws_bytes_for(const tfsc_grid *g, int64_t n, int which) {
     switch (which) {

@@ -206,9 +206,41 @@ __device__ inline void sky_init(Sky<R> &S, double ct, double phi, double psi, do
 
 template <class R>
 __device__ __forceinline__ R sinc_of(R x) {
-    // sin(x)/x for 0 <= x <= ~2 pi f L; series near 0
-    if (x < (R)1e-4) return (R)1 - x * x * (R)(1.0 / 6.0);
-    return sin_rev(x * (R)(1.0 / kTwoPi)) * rcp(x);
+    // sin(x)/x for 0 <= x <= ~2 pi f L; series near 0 (a select, not a branch: the
+    // unselected quotient may be inf or nan at x = 0)
+    const R q = sin_rev(x * (R)(1.0 / kTwoPi)) * rcp(x);
+    const R ser = (R)1 - x * x * (R)(1.0 / 6.0);
+    return x < (R)1e-4 ? ser : q;
+}
+
+// Buffer views of the geometry tables: the FP64 table (rows of Nt doubles) and, for the FP32
+// arithmetic, the FP32 copy of the arm-vector rows 9..17 (rows of Nt floats).  A value is
+// read with the lane's tranche as vector offset and the row as scalar offset, so no vector
+// address arithmetic is spent on it.
+struct GeoView {
+    __amdgpu_buffer_rsrc_t g64, g32;
+    uint32_t row64, row32;  // bytes per row
+};
+
+__device__ __forceinline__ GeoView geo_view(const double *geo, const float *geo32, int Nt) {
+    GeoView v;
+    v.row64 = (uint32_t)Nt * 8u;
+    v.row32 = (uint32_t)Nt * 4u;
+    v.g64 = __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(geo), (short)0, (int)(v.row64 * kGeoRows), 0x00020000);
+    v.g32 = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(geo32), (short)0, (int)(v.row32 * 9u), 0x00020000);
+    return v;
+}
+
+__device__ __forceinline__ double geo_d(const GeoView &v, int m, int r) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(v.g64, (uint32_t)m * 8u, (uint32_t)r * v.row64, 0));
+}
+
+template <class R>
+__device__ __forceinline__ R geo_arm(const GeoView &v, int m, int q) {  // arm-vector value q = 0..8
+    if constexpr (sizeof(R) == 4)
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(v.g32, (uint32_t)m * 4u, (uint32_t)q * v.row32, 0));
+    else
+        return geo_d(v, m, 9 + q);
 }
 
 __device__ __forceinline__ void load_geo(const double *__restrict__ geo, int m, int Nt, double g[kGeoRows]) {
@@ -216,27 +248,24 @@ __device__ __forceinline__ void load_geo(const double *__restrict__ geo, int m, 
     for (int r = 0; r < kGeoRows; ++r) g[r] = geo[(size_t)r * Nt + m];
 }
 
-// T_A, T_E at tranche m (time t_m) and frequency f.  geo: the table above; each value is
-// read where it is used, which keeps register pressure down.
+// T_A, T_E at tranche m (time t_m) and frequency f from the geometry tables; each value
+// is read where it is used, which keeps register pressure down.
 template <class R>
-__device__ inline void transfer_ae(const Sky<R> &S, const double *__restrict__ geo, int m, int Nt, double f,
-                                   cx<R> &TA, cx<R> &TE) {
+__device__ inline void transfer_ae(const Sky<R> &S, const GeoView &gv, int m, double f, cx<R> &TA, cx<R> &TE) {
 #pragma clang fp contract(fast)
     const double L = kArmM / kClight;
-    const double *g = geo + m;  // value r of tranche m at g[r * Nt]
     double kp[3];
 #pragma unroll
     for (int i = 0; i < 3; ++i)
-        kp[i] = S.kd[0] * g[(size_t)(3 * i) * Nt] + S.kd[1] * g[(size_t)(3 * i + 1) * Nt] +
-                S.kd[2] * g[(size_t)(3 * i + 2) * Nt];
+        kp[i] = S.kd[0] * geo_d(gv, m, 3 * i) + S.kd[1] * geo_d(gv, m, 3 * i + 1) + S.kd[2] * geo_d(gv, m, 3 * i + 2);
     const R pfL = (R)(kPi * f * L);
     cx<R> Gd[3], Gr[3];  // arm a: direction (s -> r) and reverse
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int s = a, r = (a + 1) % 3;
-        R n0 = (R)g[(size_t)(9 + 3 * a + 0) * Nt];
-        R n1 = (R)g[(size_t)(9 + 3 * a + 1) * Nt];
-        R n2 = (R)g[(size_t)(9 + 3 * a + 2) * Nt];
+        R n0 = geo_arm<R>(gv, m, 3 * a + 0);
+        R n1 = geo_arm<R>(gv, m, 3 * a + 1);
+        R n2 = geo_arm<R>(gv, m, 3 * a + 2);
         R kn = S.k[0] * n0 + S.k[1] * n1 + S.k[2] * n2;
         R nu = S.u[0] * n0 + S.u[1] * n1 + S.u[2] * n2;
         R nv = S.v[0] * n0 + S.v[1] * n1 + S.v[2] * n2;

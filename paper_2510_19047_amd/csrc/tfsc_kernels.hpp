@@ -10,6 +10,14 @@ namespace tfsc {
 // +0, the FP64 weight scale at +kTailScale.
 constexpr int kTailScale = 64;
 
+// Geometry tables in the statistic workspace: 18 FP64 rows of Nt values, then (256-byte
+// aligned) the FP32 copy of the 9 arm-vector rows.
+inline size_t geo64_bytes(int Nt) { return (sizeof(double) * 18 * (size_t)Nt + 255) / 256 * 256; }
+inline size_t geo32_bytes(int Nt) { return (sizeof(float) * 9 * (size_t)Nt + 255) / 256 * 256; }
+inline float *geo32_of(const double *geo, int Nt) {
+    return reinterpret_cast<float *>(reinterpret_cast<char *>(const_cast<double *>(geo)) + geo64_bytes(Nt));
+}
+
 struct LayoutLaunch {
     int64_t n;
     const double *mc, *eta, *f0, *ct, *ci;

@@ -154,7 +154,7 @@ hipError_t launch_order(const OrderLaunch &L, hipStream_t st) {
 
 // ------------------------------------------------------------------ geometry
 // Rigid analytic orbits (first order in e = L / (2 sqrt 3 R)) at t_m = m dT.
-__global__ void k_geometry(int Nt, double dT, double *__restrict__ geo) {
+__global__ void k_geometry(int Nt, double dT, double *__restrict__ geo, float *__restrict__ geo32) {
     int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= Nt) return;
     const double L = kArmM / kClight, R = kAuM / kClight;
@@ -183,7 +183,10 @@ __global__ void k_geometry(int Nt, double dT, double *__restrict__ geo) {
             nn += d[x] * d[x];
         }
         nn = sqrt(nn);
-        for (int x = 0; x < 3; ++x) geo[(size_t)(9 + 3 * a2 + x) * Nt + m] = d[x] / nn;
+        for (int x = 0; x < 3; ++x) {
+            geo[(size_t)(9 + 3 * a2 + x) * Nt + m] = d[x] / nn;
+            geo32[(size_t)(3 * a2 + x) * Nt + m] = (float)(d[x] / nn);
+        }
     }
 }
 
@@ -226,6 +229,7 @@ struct StatArgs {
     const double *inv_asd;
     const double *tranche_w;
     const double *geo;
+    const float *geo32;
     const double *u_scale;  // [1], see k_weight_scale
     int64_t n;
     const double *mc, *eta, *f0, *ct, *phi, *psi, *ci;
@@ -333,11 +337,11 @@ __device__ __forceinline__ void tranche_bins(const StatArgs &a, const TrancheSpe
 
 // Tranche contribution z_m = w_m sum_c T_c P_c, N_m = w_m^2 (sum_c |T_c|^2) Q.
 template <int C, class R>
-__device__ __forceinline__ void tranche_combine(const Sky<R> &S, const StatArgs &a, int m, double f, R wm,
+__device__ __forceinline__ void tranche_combine(const Sky<R> &S, const GeoView &gv, int m, double f, R wm,
                                                 const cx<R> (&P)[C], R Q, R &zr, R &zi, R &nn) {
 #pragma clang fp contract(fast)
     cx<R> TA, TE;
-    transfer_ae(S, a.geo, m, a.Nt, f, TA, TE);
+    transfer_ae(S, gv, m, f, TA, TE);
     cx<R> z = cmul(TA, P[0]);
     R tt = TA.re * TA.re + TA.im * TA.im;
     if constexpr (C == 2) {
@@ -372,6 +376,7 @@ __global__ __launch_bounds__(256) void k_stat_thread(StatArgs a) {
     track_init(T, a.mc[i], a.eta[i], a.f0[i]);
     Sky<R> S;
     sky_init(S, a.ct[i], a.phi[i], a.psi[i], a.ci[i]);
+    const GeoView gv = geo_view(a.geo, a.geo32, a.Nt);
     const double u_mul = a.u_scale[0];
     int m = 0, n_act = 0;
     for (; m < a.Nt; ++m) {
@@ -392,7 +397,7 @@ __global__ __launch_bounds__(256) void k_stat_thread(StatArgs a) {
         R Q;
         tranche_bins<C, R, PixT, LAYOUT, double>(a, ts, kc, m, a.inv_asd, u_mul, a.layer_scale, P, Q);
         R zr, zi, nn;
-        tranche_combine<C, R>(S, a, m, f, (R)wmd, P, Q, zr, zi, nn);
+        tranche_combine<C, R>(S, gv, m, f, (R)wmd, P, Q, zr, zi, nn);
         acc.zr += zr;
         acc.zi += zi;
         acc.N += nn;
@@ -603,6 +608,7 @@ __global__ __launch_bounds__(256, 4) void k_stat_wave(StatArgs a) {
         }
     __syncthreads();
     const __amdgpu_buffer_rsrc_t rsrc = pix_rsrc(a.pix, a.pix_bytes);
+    const GeoView gv = geo_view(a.geo, a.geo32, a.Nt);
 
     const int lane = threadIdx.x & 63;
     for (;;) {
@@ -671,7 +677,7 @@ __global__ __launch_bounds__(256, 4) void k_stat_wave(StatArgs a) {
                 cx<R> P[C];
                 R Q;
                 wave_tranche_bins<C, R, PixT>(ts, kc, m, a.Nt, a.K, rsrc, u_pad, sc_pad, jA, jB, P, Q);
-                tranche_combine<C, R>(S, a, m, f, (R)wmd, P, Q, zr, zi, nn);
+                tranche_combine<C, R>(S, gv, m, f, (R)wmd, P, Q, zr, zi, nn);
             }
             // segmented reduction over the lanes of this chunk
             const int last = min(min(m0 + 63, lim - 1), a.Nt - 1);
@@ -754,7 +760,7 @@ hipError_t launch_layout(const LayoutLaunch &L, hipStream_t st) {
 }
 
 hipError_t launch_geometry(int Nt, double dT, double *geo, hipStream_t st) {
-    hipLaunchKernelGGL(k_geometry, dim3((Nt + 127) / 128), dim3(128), 0, st, Nt, dT, geo);
+    hipLaunchKernelGGL(k_geometry, dim3((Nt + 127) / 128), dim3(128), 0, st, Nt, dT, geo, geo32_of(geo, Nt));
     return hipGetLastError();
 }
 
@@ -778,6 +784,7 @@ static StatArgs make_args(const StatLaunch &L) {
     a.inv_asd = L.inv_asd;
     a.tranche_w = L.tranche_w;
     a.geo = L.geo;
+    a.geo32 = geo32_of(L.geo, L.Nt);
     a.u_scale = L.u_scale;
     a.n = L.n;
     a.mc = L.mc;
