@@ -464,6 +464,40 @@ __device__ __forceinline__ R wave_sum(R v) {
     else return dpp_sum_f64(v);
 }
 
+template <int CTRL, int RM, int BM>
+__device__ __forceinline__ float dpp_f32(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, RM, BM, true));
+}
+
+template <int CTRL, int RM, int BM>
+__device__ __forceinline__ void dpp_step3(float &a, float &b, float &c) {
+    const float ta = dpp_f32<CTRL, RM, BM>(a), tb = dpp_f32<CTRL, RM, BM>(b), tc = dpp_f32<CTRL, RM, BM>(c);
+    a += ta;
+    b += tb;
+    c += tc;
+}
+
+// Three wave sums at once: the three independent DPP moves of each step fill each other's
+// data-hazard slots.
+template <class R>
+__device__ __forceinline__ void wave_sum3(R &a, R &b, R &c) {
+    if constexpr (sizeof(R) == 4) {
+        dpp_step3<0x111, 0xf, 0xf>(a, b, c);
+        dpp_step3<0x112, 0xf, 0xf>(a, b, c);
+        dpp_step3<0x114, 0xf, 0xe>(a, b, c);
+        dpp_step3<0x118, 0xf, 0xc>(a, b, c);
+        dpp_step3<0x142, 0xa, 0xf>(a, b, c);
+        dpp_step3<0x143, 0xc, 0xf>(a, b, c);
+        a = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, a), 63));
+        b = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, b), 63));
+        c = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, c), 63));
+    } else {
+        a = dpp_sum_f64(a);
+        b = dpp_sum_f64(b);
+        c = dpp_sum_f64(c);
+    }
+}
+
 // Raw buffer view of the pixel store: hardware-checked, loads past the end return 0.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t pix_rsrc(const void *p, uint32_t bytes) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
@@ -685,9 +719,8 @@ __global__ __launch_bounds__(256, 4) void k_stat_wave(StatArgs a) {
                 while (sw.hi <= m0) sw.step();
                 for (;;) {
                     const bool mine = active && m >= sw.lo && m < sw.hi;
-                    R vr = wave_sum<R>(mine ? zr : (R)0);
-                    R vi = wave_sum<R>(mine ? zi : (R)0);
-                    R vn = wave_sum<R>(mine ? nn : (R)0);
+                    R vr = mine ? zr : (R)0, vi = mine ? zi : (R)0, vn = mine ? nn : (R)0;
+                    wave_sum3<R>(vr, vi, vn);
                     close_segments(acc, sw.s, off, a.seg_terms, a.seg_zn, writer);
                     acc.zr += (double)vr;
                     acc.zi += (double)vi;
