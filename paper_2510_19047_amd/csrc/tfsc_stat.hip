@@ -10,6 +10,8 @@
 //           grid pulls templates from a device counter.
 //
 // No kernel allocates; all scratch lives in the caller's workspace.
+#include <limits.h>
+
 #include "tfsc_device.hpp"
 #include "tfsc_kernels.hpp"
 
@@ -458,6 +460,27 @@ __device__ __forceinline__ float dpp_max_f32(float v) {
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
 
+template <int CTRL, int RM, int BM>
+__device__ __forceinline__ void dpp_max_step2(int &a, int &b) {
+    const int ta = __builtin_amdgcn_update_dpp(INT_MIN, a, CTRL, RM, BM, false);
+    const int tb = __builtin_amdgcn_update_dpp(INT_MIN, b, CTRL, RM, BM, false);
+    a = max(a, ta);
+    b = max(b, tb);
+}
+
+// Wave-wide maxima of two ints (lane 63 holds both after the row shifts and broadcasts),
+// interleaved so the two DPP moves of each step fill each other's hazard slots.
+__device__ __forceinline__ void wave_max2_i32(int &a, int &b) {
+    dpp_max_step2<0x111, 0xf, 0xf>(a, b);
+    dpp_max_step2<0x112, 0xf, 0xf>(a, b);
+    dpp_max_step2<0x114, 0xf, 0xe>(a, b);
+    dpp_max_step2<0x118, 0xf, 0xc>(a, b);
+    dpp_max_step2<0x142, 0xa, 0xf>(a, b);
+    dpp_max_step2<0x143, 0xc, 0xf>(a, b);
+    a = __builtin_amdgcn_readlane(a, 63);
+    b = __builtin_amdgcn_readlane(b, 63);
+}
+
 template <class R>
 __device__ __forceinline__ R wave_sum(R v) {
     if constexpr (sizeof(R) == 4) return dpp_sum_f32(v);
@@ -681,6 +704,7 @@ __global__ __launch_bounds__(256, 4) void k_stat_wave(StatArgs a) {
         for (int m0 = 0; m0 < m_end; m0 += 64) {
             const int m = m0 + lane;
             const bool inr = m < a.Nt;
+            const double wm_raw = inr ? a.tranche_w[m] : 0.0;  // issued before the track is evaluated
             double Phi = 0.0, f = 0.0, fdot = 0.0;
             int code = inr ? track_step(T, (double)m * a.dT, a.dT, a.df, a.fnyq, Phi, f, fdot) : 0;
             const uint64_t viol = __ballot(code != 0);
@@ -692,20 +716,21 @@ __global__ __launch_bounds__(256, 4) void k_stat_wave(StatArgs a) {
                 m_end = lim;
             }
             const bool active = inr && m < lim;
-            const double wmd = active ? a.tranche_w[m] : 0.0;
+            const double wmd = active ? wm_raw : 0.0;
             const bool work = active && wmd != 0.0;
             n_act += __popcll(__ballot(work));
             TrancheSpec<R> ts;
             int kc = 0;
-            float nlo = -1e9f, hi = -1e9f;  // -(first) and last bin that is not asymptotic-only
+            int nlo = INT_MIN, hi = INT_MIN;  // -(first) and last bin that is not asymptotic-only
             if (work) {
                 kc = tranche_setup(ts, Phi, f, fdot, a.dT);
-                nlo = (float)(-ts.j0lo);
-                hi = (float)ts.j1hi;
+                nlo = -ts.j0lo;
+                hi = ts.j1hi;
             }
             // The wave takes the general form on the union [jA, jB] of the lanes' such bins.
-            const int jA = -(int)dpp_max_f32(nlo);
-            const int jB = (int)dpp_max_f32(hi);
+            wave_max2_i32(nlo, hi);
+            const int jA = -nlo;
+            const int jB = hi;
             R zr = 0, zi = 0, nn = 0;
             if (work) {
                 cx<R> P[C];
