@@ -40,6 +40,8 @@ def parse():
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--templates", type=int, default=1_000_000)
     p.add_argument("--chosen-store", default="f32", choices=["f32", "f16", "bf16"])
+    p.add_argument("--chosen-layout", default="layer_ci", choices=["layer_ci", "layer"],
+                   help="pixel layout of the chosen form (channels of a cell adjacent, or one block per channel)")
     p.add_argument("--plain-steps", type=int, default=2)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -92,7 +94,7 @@ def main():
 
     # first pass: layout with total read-back, allocations reused by every timed step
     seg = tfsc.segment_layout(grid, bank)
-    pix_chosen = tfsc.transform(grid, x_d, psd_d, mu_d, keep_d, dtype=args.chosen_store, layout="layer")
+    pix_chosen = tfsc.transform(grid, x_d, psd_d, mu_d, keep_d, dtype=args.chosen_store, layout=args.chosen_layout)
     pix_plain = tfsc.transform(grid, x_d, psd_d, mu_d, keep_d, dtype="f32", layout="tranche")
     res = tfsc.bank_statistic(grid, pix_chosen, bank, seg, precision="f32", schedule="wave", want_active=True)
     torch.cuda.synchronize()
@@ -133,13 +135,13 @@ def main():
                             torch.empty(seg.total, dtype=torch.float64, device=dev),
                             torch.empty(n, dtype=torch.int32, device=dev))
     for i in range(args.warmup):
-        step(args.chosen_store, "layer", "wave", pix_chosen, res_c)
+        step(args.chosen_store, args.chosen_layout, "wave", pix_chosen, res_c)
         torch.cuda.synchronize()
         log(f"warmup {i + 1}/{args.warmup} done")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
-        step(args.chosen_store, "layer", "wave", pix_chosen, res_c)
+        step(args.chosen_store, args.chosen_layout, "wave", pix_chosen, res_c)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = 1e3 * wall / args.steps
@@ -185,8 +187,8 @@ def main():
     sc, sp = res_c.stat.cpu().numpy(), res_p.stat.cpu().numpy()
     rel_cp = float(np.max(np.abs(sc - sp) / np.maximum(np.abs(sp), 1.0)))
 
-    traffic, traffic_shape = measured_traffic(n, args.chosen_store, "bank" if order is None else "f0 bin",
-                                              (kw["block_waves"], kw["groups_per_cu"]))
+    traffic, traffic_shape = measured_traffic(n, args.chosen_store, args.chosen_layout,
+                                              "bank" if order is None else "f0 bin")
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -205,6 +207,7 @@ def main():
                         f"{n} non-spinning 2PN templates, adaptive Nseg 16-256",
             "n_templates": n,
             "pixel_store": args.chosen_store,
+            "pixel_layout": args.chosen_layout,
             "schedule": "wave-per-template persistent",
             "launch_shape": {"block_waves": kw["block_waves"], "groups_per_cu": kw["groups_per_cu"]},
             "order": "bank" if order is None else "f0 bin",
@@ -223,7 +226,8 @@ def main():
             "alg_bytes_per_launch": alg_bytes,
         },
         "forms": {
-            "chosen": {"templates_per_s": round(value, 1), "kernel_ms": round(k_ms, 3), "store": args.chosen_store,
+            "chosen": {"templates_per_s": round(value, 1), "kernel_ms": round(k_ms, 3),
+                       "store": f"{args.chosen_store} {args.chosen_layout}",
                        "arith": "f32 (track f64)"},
             "plain": {"templates_per_s": round(plain_value, 1), "ms_per_step": round(plain_ms, 3),
                       "kernel_ms": round(plain_k_ms, 3), "store": "f32 tranche-major", "arith": "f32 (track f64)",
@@ -259,7 +263,8 @@ def batching_run(args, tfsc, ti, grid, g, psd_d, mu_d, keep_d, kw):
     xs = torch.empty((R, g.n_channels, g.n_samples), dtype=torch.float32, device=dev)
     for r in range(R):
         xs[r] = torch.from_numpy((ti.noise(g, realisation=r) * keepm).astype(np.float32)).to(dev)
-    rg = batching.RealisationGraph(grid, xs, psd_d, mu_d, keep_d, bank, seg, store="f32", precision="f32",
+    rg = batching.RealisationGraph(grid, xs, psd_d, mu_d, keep_d, bank, seg, store="f32", layout=args.chosen_layout,
+                                   precision="f32",
                                    order=order, **kw)
     rg.replay()
     torch.cuda.synchronize()
@@ -291,10 +296,10 @@ def batching_run(args, tfsc, ti, grid, g, psd_d, mu_d, keep_d, kw):
     return rec
 
 
-def measured_traffic(n, store, order, shape):
+def measured_traffic(n, store, layout, order):
     """Calibrated bytes beyond L2 per k_stat_wave launch from the committed rocprofv3 counter runs.
 
-    Only valid while the kernel source, the bank, the store and the processing order are the ones
+    Only valid while the kernel source, the bank, the store, its layout and the processing order are the ones
     that were profiled; otherwise None.  The launch shape the counters were taken with is returned
     beside it (the autotuner's choice can differ between boxes by timings within noise).
     """
@@ -302,7 +307,7 @@ def measured_traffic(n, store, order, shape):
     root = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(root, "profiles", "k_stat_wave_traffic.txt")
     if not os.path.exists(path):
-        return None
+        return None, None
     rec = {}
     with open(path) as fh:
         for line in fh:
@@ -314,7 +319,8 @@ def measured_traffic(n, store, order, shape):
         with open(os.path.join(root, "paper_2510_19047_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     same = (rec.get("source_sha256") == h.hexdigest() and rec.get("n_templates") == str(n)
-            and rec.get("pixel_store") == store and rec.get("order") == order)
+            and rec.get("pixel_store") == store and rec.get("pixel_layout", "layer") == layout
+            and rec.get("order") == order)
     return (float(rec["traffic_bytes"]), rec.get("launch_shape")) if same else (None, None)
 
 

@@ -40,9 +40,11 @@ typedef enum {
 typedef enum { TFSC_F64 = 0, TFSC_F32 = 1, TFSC_BF16 = 2, TFSC_F16 = 3 } tfsc_dtype;
 
 /* Pixel store layouts (complex values stored as interleaved (re, im)):
- *   LAYER_MAJOR   [C][K][Nt]  -- tranches contiguous within one frequency layer
- *   TRANCHE_MAJOR [C][Nt][K]  -- bins contiguous within one tranche          */
-typedef enum { TFSC_LAYER_MAJOR = 0, TFSC_TRANCHE_MAJOR = 1 } tfsc_layout;
+ *   LAYER_MAJOR    [C][K][Nt]  -- tranches contiguous within one frequency layer
+ *   TRANCHE_MAJOR  [C][Nt][K]  -- bins contiguous within one tranche
+ *   LAYER_MAJOR_CI [K][Nt][C]  -- as LAYER_MAJOR with the C channels of a pixel
+ *                                 adjacent, so one load fetches all channels   */
+typedef enum { TFSC_LAYER_MAJOR = 0, TFSC_TRANCHE_MAJOR = 1, TFSC_LAYER_MAJOR_CI = 2 } tfsc_layout;
 
 /* Sampling grid.  C = 1 (TDI A) or 2 (A, E); M even, 64 <= M <= 4096 and a
  * power of two (the transform's FFT); K = M/2 + 1 bins per tranche;
@@ -105,7 +107,8 @@ typedef struct {
  *                        tranches (the paper's mapping); any layout.
  *            TFSC_SCHED_WAVE   -- one 64-lane wavefront per template, lanes
  *                        over consecutive tranches, persistent grid pulling
- *                        templates from a device work counter; LAYER_MAJOR.
+ *                        templates from a device work counter; LAYER_MAJOR
+ *                        or LAYER_MAJOR_CI.
  * block_waves / groups_per_cu: launch shape of the WAVE schedule, waves per
  * block (1..4) and resident blocks per compute unit (1..64); 0 = default
  * (4, 4); larger values return TFSC_ERR_ARG.  order: optional [n] permutation of template indices giving the

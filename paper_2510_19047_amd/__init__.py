@@ -20,7 +20,7 @@ __all__ = ["GridSpec", "PixelStore", "BankTensors", "SegmentLayout", "StatResult
 
 _DTYPE = {"f64": _lib.F64, "f32": _lib.F32, "bf16": _lib.BF16, "f16": _lib.F16}
 _TORCH_STORE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
-_LAYOUT = {"layer": _lib.LAYER_MAJOR, "tranche": _lib.TRANCHE_MAJOR}
+_LAYOUT = {"layer": _lib.LAYER_MAJOR, "tranche": _lib.TRANCHE_MAJOR, "layer_ci": _lib.LAYER_MAJOR_CI}
 _SCHED = {"thread": _lib.SCHED_THREAD, "wave": _lib.SCHED_WAVE}
 _PREC = {"f64": _lib.F64, "f32": _lib.F32}
 
@@ -67,7 +67,7 @@ class GridSpec:
 @dataclass
 class PixelStore:
     """Whitened TF pixels plus template weights (see tfsc_pixels)."""
-    pix: torch.Tensor                 # [C][K][Nt][2] (layer) or [C][Nt][K][2] (tranche), store dtype
+    pix: torch.Tensor                 # [C][K][Nt][2] (layer), [C][Nt][K][2] (tranche) or [K][Nt][C][2] (layer_ci)
     inv_asd: torch.Tensor             # [K] f64
     tranche_w: torch.Tensor           # [Nt] f64
     dtype: str = "f32"
@@ -84,7 +84,9 @@ class PixelStore:
         """Wrap complex [C][K][Nt] pixels (already whitened) as a store of FP64 or FP32 values."""
         if dtype not in ("f64", "f32"):
             raise TfscError("from_complex stores f64 or f32; 16-bit stores come from transform()")
-        p = pix if layout == "layer" else pix.transpose(1, 2)
+        if layout not in _LAYOUT:
+            raise TfscError(f"unknown pixel layout {layout!r}")
+        p = {"layer": pix, "tranche": pix.transpose(1, 2), "layer_ci": pix.permute(1, 2, 0)}[layout]
         real = torch.view_as_real(p.contiguous().to(torch.complex128 if dtype == "f64" else torch.complex64))
         return PixelStore(real.contiguous(), inv_asd.to(torch.float64).contiguous(),
                           tranche_w.to(torch.float64).contiguous(), dtype, layout)
@@ -148,7 +150,9 @@ def transform(grid: GridSpec, x: torch.Tensor, psd0: torch.Tensor, mu: torch.Ten
     dev = x.device
     K, Nt, C = grid.n_bins, grid.n_tranches, grid.n_channels
     if out is None:
-        shape = (C, K, Nt, 2) if layout == "layer" else (C, Nt, K, 2)
+        if layout not in _LAYOUT:
+            raise TfscError(f"unknown pixel layout {layout!r}")
+        shape = {"layer": (C, K, Nt, 2), "tranche": (C, Nt, K, 2), "layer_ci": (K, Nt, C, 2)}[layout]
         out = PixelStore(torch.empty(shape, dtype=_TORCH_STORE[dtype], device=dev),
                          torch.empty(K, dtype=torch.float64, device=dev), torch.empty(Nt, dtype=torch.float64, device=dev),
                          dtype, layout,

@@ -11,7 +11,7 @@ c_int32, c_int64, c_double, c_void_p, c_size_t = ctypes.c_int32, ctypes.c_int64,
 
 TFSC_OK = 0
 F64, F32, BF16, F16 = 0, 1, 2, 3
-LAYER_MAJOR, TRANCHE_MAJOR = 0, 1
+LAYER_MAJOR, TRANCHE_MAJOR, LAYER_MAJOR_CI = 0, 1, 2
 SCHED_THREAD, SCHED_WAVE = 0, 1
 WS_LAYOUT, WS_STATISTIC, WS_VJP, WS_TRANSFORM, WS_ORDER = 0, 1, 2, 3, 4
 FLAG_INVALID, FLAG_EMPTY, FLAG_BAND_END, FLAG_MERGE_END, FLAG_ALL_EXCLUDED = 1, 2, 4, 8, 16

@@ -85,20 +85,22 @@ def autotune(grid: GridSpec, pixels: PixelStore, bank: BankTensors, seg: Segment
 class RealisationGraph:
     """transform(r) -> bank_statistic(r) for R realisations, captured into one HIP graph.
 
-    xs: [R][C][N] device time series (f32 or f64).  The pixel stores, results and workspace are
+    xs: [R][C][N] device time series (f32 or f64).  The pixel stores (``layout``: "layer_ci" or
+    "layer", the two the WAVE schedule reads), results and workspace are
     allocated once (eager warm-up) and reused by every replay; ``results[r]`` holds realisation r's
     output after ``replay()``.
     """
 
     def __init__(self, grid: GridSpec, xs: torch.Tensor, psd0: torch.Tensor, mu: torch.Tensor, keep: torch.Tensor,
                  bank: BankTensors, seg: SegmentLayout, store: str = "f32", precision: str = "f32",
-                 order: torch.Tensor | None = None, block_waves: int = 0, groups_per_cu: int = 0):
+                 order: torch.Tensor | None = None, block_waves: int = 0, groups_per_cu: int = 0,
+                 layout: str = "layer_ci"):
         self.grid, self.xs, self.psd0, self.mu, self.keep = grid, xs, psd0, mu, keep
         self.bank, self.seg, self.store, self.precision, self.order = bank, seg, store, precision, order
         self.shape = dict(block_waves=block_waves, groups_per_cu=groups_per_cu)
         R = xs.shape[0]
         dev = bank.mc.device
-        self.stores = [transform(grid, xs[r], psd0, mu, keep, dtype=store) for r in range(R)]
+        self.stores = [transform(grid, xs[r], psd0, mu, keep, dtype=store, layout=layout) for r in range(R)]
         self.ws = torch.empty(1 << 22, dtype=torch.uint8, device=dev)
         self.results = [bank_statistic(grid, self.stores[r], bank, seg, precision=precision, schedule="wave",
                                        order=order, ws=self.ws, **self.shape) for r in range(R)]

@@ -47,7 +47,8 @@ tfsc_status check_bank(const tfsc_bank *b) {
 tfsc_status check_pixels(const tfsc_pixels *p, bool need_data) {
     if (!p) return TFSC_ERR_ARG;
     if (p->dtype < TFSC_F64 || p->dtype > TFSC_F16) return TFSC_ERR_DTYPE;
-    if (p->layout != TFSC_LAYER_MAJOR && p->layout != TFSC_TRANCHE_MAJOR) return TFSC_ERR_ARG;
+    if (p->layout != TFSC_LAYER_MAJOR && p->layout != TFSC_TRANCHE_MAJOR && p->layout != TFSC_LAYER_MAJOR_CI)
+        return TFSC_ERR_ARG;
     if (need_data && !p->pix) return TFSC_ERR_ARG;
     if (!p->inv_asd || !p->tranche_w) return TFSC_ERR_ARG;
     if ((p->dtype == TFSC_BF16 || p->dtype == TFSC_F16) && !p->layer_scale) return TFSC_ERR_ARG;
@@ -72,7 +73,7 @@ tfsc_status resolve_options(const tfsc_options *o, const tfsc_pixels *p, Resolve
     if (p) {
         if (r.precision == TFSC_F64 && (p->dtype == TFSC_BF16 || p->dtype == TFSC_F16)) return TFSC_ERR_DTYPE;
         if (r.precision == TFSC_F32 && p->dtype == TFSC_F64) return TFSC_ERR_DTYPE;
-        if (r.schedule == TFSC_SCHED_WAVE && p->layout != TFSC_LAYER_MAJOR) return TFSC_ERR_UNSUPPORTED;
+        if (r.schedule == TFSC_SCHED_WAVE && p->layout == TFSC_TRANCHE_MAJOR) return TFSC_ERR_UNSUPPORTED;
     }
     return TFSC_OK;
 }

@@ -321,7 +321,9 @@ __device__ __forceinline__ void tranche_bins(const StatArgs &a, const TrancheSpe
         Q += g.im * g.im;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            size_t idx = LAYOUT == 0 ? ((size_t)(c * a.K + k) * a.Nt + m) : ((size_t)(c * a.Nt + m) * a.K + k);
+            size_t idx = LAYOUT == 0   ? ((size_t)(c * a.K + k) * a.Nt + m)
+                         : LAYOUT == 1 ? ((size_t)(c * a.Nt + m) * a.K + k)
+                                       : ((size_t)k * a.Nt + m) * C + c;
             const auto Dl = PT::load(a.pix, idx);
             cx<R> D = {(R)Dl.re, (R)Dl.im};
             if constexpr (PT::scaled) {
@@ -548,53 +550,128 @@ __device__ __forceinline__ cx<typename PixTraits<PixT>::R> buf_load(__amdgpu_buf
     }
 }
 
-// Bins of one tranche for the WAVE schedule.  The 21 bins are unrolled; each bin's pixel
-// row is a scalar offset from the lane's row of bin kc - 10, the weight table is padded
-// with zeros so bins outside [1, M/2 - 1] contribute nothing (their loads are in bounds or
-// return 0), and the exact Fresnel form is used only for the bins [jA, jB] where some lane
-// of the wave may need it (a wave-uniform choice).
+// The C channel pixels of one bin: LAYER_MAJOR holds channel c at the scalar offset c * chan
+// from channel 0, LAYER_MAJOR_CI holds the C pixels of a bin side by side, fetched with one
+// wide load (two for FP64 pairs).
+template <int C, class PixT, int LAYOUT>
+__device__ __forceinline__ void bin_pixels(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff, uint32_t chan,
+                                           cx<typename PixTraits<PixT>::R> (&D)[C]) {
+    if constexpr (LAYOUT == 2 && C == 2) {
+        if constexpr (sizeof(PixT) == 8) {
+            const double2 d0 = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+            const double2 d1 = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff + 16u, 0));
+            D[0] = {d0.x, d0.y};
+            D[1] = {d1.x, d1.y};
+        } else if constexpr (sizeof(PixT) == 4) {
+            const float4 q = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+            D[0] = {q.x, q.y};
+            D[1] = {q.z, q.w};
+        } else {
+            const auto w = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+            const uint32_t w0 = (uint32_t)w[0], w1 = (uint32_t)w[1];
+            if constexpr (__is_same(PixT, __half)) {
+                const float2 f0 = __half22float2(__builtin_bit_cast(__half2, w0));
+                const float2 f1 = __half22float2(__builtin_bit_cast(__half2, w1));
+                D[0] = {f0.x, f0.y};
+                D[1] = {f1.x, f1.y};
+            } else {
+                D[0] = {__uint_as_float(w0 << 16), __uint_as_float(w0 & 0xffff0000u)};
+                D[1] = {__uint_as_float(w1 << 16), __uint_as_float(w1 & 0xffff0000u)};
+            }
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < C; ++c) D[c] = buf_load<PixT>(r, voff, soff + (uint32_t)c * chan);
+    }
+}
+
+// One bin's contribution: g = weighted template bin (exact Fresnel form on the wave's band
+// [jA, jB], asymptotic form elsewhere), Q += |g|^2, P_c += conj(D_c) g.
 template <int C, class R, class PixT>
+__device__ __forceinline__ void bin_accumulate(const TrancheSpec<R> &ts, int jj, R w, int jA, int jB,
+                                               const cx<typename PixTraits<PixT>::R> (&Dl)[C],
+                                               const float *__restrict__ sc_bin, int KP, cx<R> (&P)[C], R &Q) {
+#pragma clang fp contract(fast)
+    const int j = jj - kHalfBins;
+    const R xj = ts.x - (R)j;
+    cx<R> g;
+    if (j >= jA && j <= jB) {
+        const cx<R> h = bin_full(ts, xj, j);
+        g = {h.re * w, h.im * w};
+    } else {
+        g = bin_fast_weighted(ts, xj, w);
+    }
+    Q += g.re * g.re;
+    Q += g.im * g.im;
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        cx<R> D = {(R)Dl[c].re, (R)Dl[c].im};
+        if constexpr (PixTraits<PixT>::scaled) {
+            const R s = (R)sc_bin[c * KP];
+            D.re *= s;
+            D.im *= s;
+        }
+        // conj(D) g accumulated as four separate multiply-adds
+        P[c].re += D.re * g.re;
+        P[c].re += D.im * g.im;
+        P[c].im += D.re * g.im;
+        P[c].im -= D.im * g.re;
+    }
+}
+
+// Bins of one tranche for the WAVE schedule.  The 21 bins are unrolled; each bin's pixel
+// row is a scalar offset from the lane's row of bin kc - 10, and the weight table is padded
+// with zeros so bins outside [1, M/2 - 1] contribute nothing.  The band-end rule keeps
+// kc + 10 <= M/2, so every row read lies in the store; a lane with kc < 10 would need a
+// row below 0, and a wave holding such a lane takes wave_tranche_bins_low instead.  The
+// exact Fresnel form is used only for the bins [jA, jB] where some lane of the wave may
+// need it (a wave-uniform choice).
+template <int C, class R, class PixT, int LAYOUT>
 __device__ __forceinline__ void wave_tranche_bins(const TrancheSpec<R> &ts, int kc, int m, int Nt, int K,
                                                   __amdgpu_buffer_rsrc_t rsrc, const R *__restrict__ u_pad,
                                                   const float *__restrict__ sc_pad, int jA, int jB, cx<R> (&P)[C],
                                                   R &Q) {
-#pragma clang fp contract(fast)
     constexpr uint32_t B = sizeof(PixT) == 8 ? 16u : (sizeof(PixT) == 4 ? 8u : 4u);
-    const uint32_t voff = (uint32_t)((kc - kHalfBins) * Nt + m) * B;
-    const uint32_t row = (uint32_t)Nt * B, chan = (uint32_t)K * row;
-    const R *uk = u_pad + (kc - kHalfBins + kHalfBins);  // u_pad[k + 10] = u_k
+    constexpr uint32_t BP = LAYOUT == 2 ? (uint32_t)C * B : B;  // bytes per (bin, tranche) cell
+    const uint32_t voff = (uint32_t)((kc - kHalfBins) * Nt + m) * BP;
+    const uint32_t row = (uint32_t)Nt * BP, chan = (uint32_t)K * row;
+    const int KP = K + 2 * kHalfBins;
+    const R *uk = u_pad + kc;  // uk[jj] = u_pad[kc + jj] = u_{kc + jj - 10}
+    const float *sk = sc_pad + kc;
 #pragma unroll
     for (int c = 0; c < C; ++c) P[c] = {(R)0, (R)0};
     Q = (R)0;
 #pragma unroll 7
     for (int jj = 0; jj < 2 * kHalfBins + 1; ++jj) {
-        const int j = jj - kHalfBins;
-        const R xj = ts.x - (R)j;
-        const R w = uk[jj];
-        cx<R> g;
-        if (j >= jA && j <= jB) {
-            const cx<R> h = bin_full(ts, xj, j);
-            g = {h.re * w, h.im * w};
-        } else {
-            g = bin_fast_weighted(ts, xj, w);
-        }
-        Q += g.re * g.re;
-        Q += g.im * g.im;
+        cx<typename PixTraits<PixT>::R> Dl[C];
+        bin_pixels<C, PixT, LAYOUT>(rsrc, voff, (uint32_t)jj * row, chan, Dl);
+        bin_accumulate<C, R, PixT>(ts, jj, uk[jj], jA, jB, Dl, sk + jj, KP, P, Q);
+    }
+}
+
+// As wave_tranche_bins for a wave with some lane below bin 10: each bin's row is a per-lane
+// offset, clamped at row 0 (rows below 0 have weight 0, so the clamped load adds nothing).
+// Same arithmetic in the same order, so a lane's result does not depend on its wave.
+template <int C, class R, class PixT, int LAYOUT>
+__device__ __forceinline__ void wave_tranche_bins_low(const TrancheSpec<R> &ts, int kc, int m, int Nt, int K,
+                                                   __amdgpu_buffer_rsrc_t rsrc, const R *__restrict__ u_pad,
+                                                   const float *__restrict__ sc_pad, int jA, int jB, cx<R> (&P)[C],
+                                                   R &Q) {
+    constexpr uint32_t B = sizeof(PixT) == 8 ? 16u : (sizeof(PixT) == 4 ? 8u : 4u);
+    constexpr uint32_t BP = LAYOUT == 2 ? (uint32_t)C * B : B;
+    const uint32_t chan = (uint32_t)K * (uint32_t)Nt * BP;
+    const int KP = K + 2 * kHalfBins;
+    const R *uk = u_pad + kc;
+    const float *sk = sc_pad + kc;
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const auto Dl = buf_load<PixT>(rsrc, voff, (uint32_t)jj * row + (uint32_t)c * chan);
-            cx<R> D = {(R)Dl.re, (R)Dl.im};
-            if constexpr (PixTraits<PixT>::scaled) {
-                const R s = (R)sc_pad[c * (K + 2 * kHalfBins) + kc + j + kHalfBins];
-                D.re *= s;
-                D.im *= s;
-            }
-            // conj(D) g accumulated as four separate multiply-adds
-            P[c].re += D.re * g.re;
-            P[c].re += D.im * g.im;
-            P[c].im += D.re * g.im;
-            P[c].im -= D.im * g.re;
-        }
+    for (int c = 0; c < C; ++c) P[c] = {(R)0, (R)0};
+    Q = (R)0;
+#pragma unroll 1
+    for (int jj = 0; jj < 2 * kHalfBins + 1; ++jj) {
+        const int k = max(kc - kHalfBins + jj, 0);
+        cx<typename PixTraits<PixT>::R> Dl[C];
+        bin_pixels<C, PixT, LAYOUT>(rsrc, (uint32_t)(k * Nt + m) * BP, 0u, chan, Dl);
+        bin_accumulate<C, R, PixT>(ts, jj, uk[jj], jA, jB, Dl, sk + jj, KP, P, Q);
     }
 }
 
@@ -644,7 +721,7 @@ __device__ __forceinline__ void wave_uniform(Sky<R> &S) {
     S.ci = wave_uniform(S.ci);
 }
 
-template <int C, class R, class PixT>
+template <int C, class R, class PixT, int LAYOUT>
 __global__ __launch_bounds__(256, 4) void k_stat_wave(StatArgs a) {
     // Zero-padded template weights u_pad[k + 10] = u_k for 1 <= k <= M/2 - 1 (else 0), and
     // the 16-bit layer scales, staged in LDS once per block.
@@ -732,10 +809,14 @@ __global__ __launch_bounds__(256, 4) void k_stat_wave(StatArgs a) {
             const int jA = -nlo;
             const int jB = hi;
             R zr = 0, zi = 0, nn = 0;
+            const bool low = __ballot(work && kc < kHalfBins) != 0;
             if (work) {
                 cx<R> P[C];
                 R Q;
-                wave_tranche_bins<C, R, PixT>(ts, kc, m, a.Nt, a.K, rsrc, u_pad, sc_pad, jA, jB, P, Q);
+                if (low)
+                    wave_tranche_bins_low<C, R, PixT, LAYOUT>(ts, kc, m, a.Nt, a.K, rsrc, u_pad, sc_pad, jA, jB, P, Q);
+                else
+                    wave_tranche_bins<C, R, PixT, LAYOUT>(ts, kc, m, a.Nt, a.K, rsrc, u_pad, sc_pad, jA, jB, P, Q);
                 tranche_combine<C, R>(S, gv, m, f, (R)wmd, P, Q, zr, zi, nn);
             }
             // segmented reduction over the lanes of this chunk
@@ -869,17 +950,22 @@ static hipError_t launch_thread_t(const StatArgs &a, int layout, hipStream_t st)
     dim3 grid((unsigned)((a.n + 255) / 256)), block(256);
     if (layout == 0)
         hipLaunchKernelGGL((k_stat_thread<C, R, PixT, 0>), grid, block, 0, st, a);
-    else
+    else if (layout == 1)
         hipLaunchKernelGGL((k_stat_thread<C, R, PixT, 1>), grid, block, 0, st, a);
+    else
+        hipLaunchKernelGGL((k_stat_thread<C, R, PixT, 2>), grid, block, 0, st, a);
     return hipGetLastError();
 }
 
 template <int C, class R, class PixT>
-static hipError_t launch_wave_t(const StatArgs &a, int n_groups, int block_waves, hipStream_t st) {
+static hipError_t launch_wave_t(const StatArgs &a, int layout, int n_groups, int block_waves, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, a.counter, 1);
     const size_t KP = (size_t)a.K + 2 * kHalfBins;
     size_t shmem = sizeof(R) * KP + (PixTraits<PixT>::scaled ? sizeof(float) * C * KP : 0);
-    hipLaunchKernelGGL((k_stat_wave<C, R, PixT>), dim3(n_groups), dim3(64 * block_waves), shmem, st, a);
+    if (layout == 2)
+        hipLaunchKernelGGL((k_stat_wave<C, R, PixT, 2>), dim3(n_groups), dim3(64 * block_waves), shmem, st, a);
+    else
+        hipLaunchKernelGGL((k_stat_wave<C, R, PixT, 0>), dim3(n_groups), dim3(64 * block_waves), shmem, st, a);
     return hipGetLastError();
 }
 
@@ -889,23 +975,23 @@ static hipError_t dispatch_pix(const StatLaunch &L, const StatArgs &a, hipStream
         case 0:
             if constexpr (sizeof(R) == 8) {
                 return L.schedule == 0 ? launch_thread_t<C, R, double>(a, L.layout, st)
-                                       : launch_wave_t<C, R, double>(a, L.n_groups, L.block_waves, st);
+                                       : launch_wave_t<C, R, double>(a, L.layout, L.n_groups, L.block_waves, st);
             } else {
                 return hipErrorInvalidValue;
             }
         case 1:
             return L.schedule == 0 ? launch_thread_t<C, R, float>(a, L.layout, st)
-                                   : launch_wave_t<C, R, float>(a, L.n_groups, L.block_waves, st);
+                                   : launch_wave_t<C, R, float>(a, L.layout, L.n_groups, L.block_waves, st);
         case 2:
             if constexpr (sizeof(R) == 4)
                 return L.schedule == 0 ? launch_thread_t<C, R, __hip_bfloat16>(a, L.layout, st)
-                                       : launch_wave_t<C, R, __hip_bfloat16>(a, L.n_groups, L.block_waves, st);
+                                       : launch_wave_t<C, R, __hip_bfloat16>(a, L.layout, L.n_groups, L.block_waves, st);
             else
                 return hipErrorInvalidValue;
         case 3:
             if constexpr (sizeof(R) == 4)
                 return L.schedule == 0 ? launch_thread_t<C, R, __half>(a, L.layout, st)
-                                       : launch_wave_t<C, R, __half>(a, L.n_groups, L.block_waves, st);
+                                       : launch_wave_t<C, R, __half>(a, L.layout, L.n_groups, L.block_waves, st);
             else
                 return hipErrorInvalidValue;
     }

@@ -6,8 +6,8 @@
 // windowed into LDS, transformed by a radix-2 Stockham FFT (natural order in
 // and out, twiddles from a per-block LDS table), whitened, and parked in an
 // LDS tile [K][TB]; the tile is then written so that the TB tranches of a
-// frequency layer are contiguous (LAYER_MAJOR) or the K bins of a tranche are
-// contiguous (TRANCHE_MAJOR).  16-bit stores go through an FP32 staging
+// frequency layer are contiguous (LAYER_MAJOR, or LAYER_MAJOR_CI with the channels of a
+// pixel adjacent) or the K bins of a tranche are contiguous (TRANCHE_MAJOR).  16-bit stores go through an FP32 staging
 // buffer and a second pass that applies a per-layer scale.
 #include "tfsc_device.hpp"
 #include "tfsc_kernels.hpp"
@@ -87,12 +87,13 @@ __global__ __launch_bounds__(256) void k_transform(TransformLaunch L, double w2)
     }
     // write out the tile
     const int ntb = min(TB, Nt - m0);
-    if (L.out_layout == 0) {
+    if (L.out_layout == 0 || L.out_layout == 2) {
         for (int e = threadIdx.x; e < K * TB; e += blockDim.x) {
             const int k = e / TB, tt = e % TB;
             if (tt >= ntb) continue;
             cx<R> v = tile[e];
-            size_t idx = ((size_t)c * K + k) * Nt + (m0 + tt);
+            size_t idx = L.out_layout == 0 ? ((size_t)c * K + k) * Nt + (m0 + tt)
+                                           : ((size_t)k * Nt + (m0 + tt)) * L.C + c;
             reinterpret_cast<OutT *>(L.pix)[2 * idx] = (OutT)v.re;
             reinterpret_cast<OutT *>(L.pix)[2 * idx + 1] = (OutT)v.im;
         }
@@ -143,7 +144,8 @@ __global__ void k_quantize(int C, int K, int Nt, int layout, const float *__rest
     if (blockIdx.x == 0 && threadIdx.x == 0) layer_scale[layer] = scale;
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < Nt; t += gridDim.x * blockDim.x) {
         const float *src = st + ((size_t)layer * Nt + t) * 2;
-        size_t idx = layout == 0 ? ((size_t)layer * Nt + t) : (((size_t)c * Nt + t) * K + k);
+        size_t idx = layout == 0 ? ((size_t)layer * Nt + t)
+                                 : (layout == 1 ? (((size_t)c * Nt + t) * K + k) : (((size_t)k * Nt + t) * C + c));
         out[2 * idx] = to_q<Q>(src[0] * inv);
         out[2 * idx + 1] = to_q<Q>(src[1] * inv);
     }
@@ -175,7 +177,7 @@ static hipError_t run_fft(const TransformLaunch &L, TransformLaunch Lw, double w
     size_t shmem = sizeof(cx<R>) * (2 * (size_t)M + M / 2 + (size_t)K * TB) + sizeof(R) * M;
     static bool attr_set = false;
     if (!attr_set) {
-        hipFuncSetAttribute(reinterpret_cast<const void *>(&k_transform<R, XT, OutT, TB>),
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_transform<R, XT, OutT, TB>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         attr_set = true;
     }

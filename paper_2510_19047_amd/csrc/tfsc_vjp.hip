@@ -432,7 +432,7 @@ struct VjpArgs {
     int M, K, Nt, C;
     double dT, df, fnyq;
     const void *pix;
-    int layout;  // 0 layer-major, 1 tranche-major
+    int layout;  // 0 layer-major, 1 tranche-major, 2 layer-major with interleaved channels
     const float *layer_scale;
     const double *inv_asd, *tranche_w, *geo, *u_scale;
     int64_t n;
@@ -534,7 +534,8 @@ __global__ __launch_bounds__(256) void k_vjp_wave(VjpArgs a) {
 #pragma unroll
                             for (int c = 0; c < C; ++c) {
                                 const size_t idx = a.layout == 0 ? ((size_t)c * a.K + k) * a.Nt + m
-                                                                 : ((size_t)c * a.Nt + m) * a.K + k;
+                                                   : (a.layout == 1 ? ((size_t)c * a.Nt + m) * a.K + k
+                                                                    : ((size_t)k * a.Nt + m) * C + c);
                                 cx<typename PixTraits<PixT>::R> dv = PixTraits<PixT>::load(a.pix, idx);
                                 double dr = (double)dv.re, di = (double)dv.im;
                                 if constexpr (PixTraits<PixT>::scaled) {

@@ -32,16 +32,17 @@ def full_data():
     return dict(grid=g, x=x, psd=psd, mu=mu, keep=keep, pix=pix, u=u, wm=wm, bank=bank)
 
 
-@pytest.mark.parametrize("precision,source,schedule", [("f32", "gpu", "wave"), ("f32", "oracle", "wave"),
-                                                       ("f64", "oracle", "wave"), ("f32", "gpu", "thread"),
-                                                       ("f64", "oracle", "thread")])
-def test_full_size_sampled_parity(precision, source, schedule):
+@pytest.mark.parametrize("precision,source,schedule,layout", [("f32", "gpu", "wave", "layer_ci"),
+                                                              ("f32", "oracle", "wave", "layer"),
+                                                              ("f64", "oracle", "wave", "layer_ci"),
+                                                              ("f32", "gpu", "thread", "tranche"),
+                                                              ("f64", "oracle", "thread", "tranche")])
+def test_full_size_sampled_parity(precision, source, schedule, layout):
     tfsc = lib()
     d = full_data()
     g = d["grid"]
     bt = tfsc.BankTensors.from_host(d["bank"])
     seg = tfsc.segment_layout(gridspec(g), bt)
-    layout = "layer" if schedule == "wave" else "tranche"
     if source == "gpu":
         note(f"full size: GPU transform (f32, {layout}) -> {schedule} statistic ({precision})")
         st = tfsc.transform(gridspec(g), dev(d["x"]), dev(d["psd"]), dev(d["mu"]), dev(d["keep"]), dtype="f32",
@@ -87,7 +88,7 @@ def test_whole_bank_fp32_forms_against_fp64_path():
     ref = ref.cpu().numpy()
     del st64
     x32 = dev(x.astype(np.float32))
-    for schedule, layout in (("wave", "layer"), ("thread", "tranche")):
+    for schedule, layout in (("wave", "layer_ci"), ("thread", "tranche")):
         st = tfsc.transform(grid, x32, dev(psd), dev(mu), dev(keep), dtype="f32", layout=layout)
         s = tfsc.bank_statistic(grid, st, bt, seg, precision="f32", schedule=schedule,
                                 order=order if schedule == "wave" else None).stat.cpu().numpy()

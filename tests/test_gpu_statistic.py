@@ -1,4 +1,6 @@
 """GPU parity of the statistic path against the FP64 oracle (HIP through the C ABI)."""
+import functools
+
 import numpy as np
 import pytest
 import torch
@@ -118,6 +120,80 @@ def test_tranche_major_thread_schedule():
     assert rel(res.stat.cpu().numpy(), ref.stat).max() < 1e-4
 
 
+@pytest.mark.parametrize("schedule", ["thread", "wave"])
+@pytest.mark.parametrize("precision,pixdt", [("f64", "f64"), ("f64", "f32"), ("f32", "f32")])
+def test_channel_interleaved_layout_equals_layer_major(schedule, precision, pixdt):
+    """LAYER_MAJOR_CI holds the pixels of LAYER_MAJOR with the channels of a (bin, tranche) cell
+    adjacent; the arithmetic and its order do not change, so every output is the same bit for bit."""
+    tfsc = lib()
+    d = small_data()
+    g = d["grid"]
+    note(f"channel-interleaved store, {schedule} {precision} pixels {pixdt}")
+    bt = _bank(tfsc, d["bank"])
+    seg = tfsc.segment_layout(gridspec(g), bt)
+    a = tfsc.bank_statistic(gridspec(g), store_from_oracle(d, pixdt), bt, seg, precision=precision,
+                            schedule=schedule)
+    ci = store_from_oracle(d, pixdt, layout="layer_ci")
+    assert tuple(ci.pix.shape) == (g.tranche_len // 2 + 1, g.n_tranches, g.n_channels, 2)
+    b = tfsc.bank_statistic(gridspec(g), ci, bt, seg, precision=precision, schedule=schedule)
+    assert torch.equal(a.stat, b.stat) and torch.equal(a.flags, b.flags) and torch.equal(a.seg_terms, b.seg_terms)
+    ref = oracle_stat(d)
+    assert rel(b.stat.cpu().numpy(), ref.stat).max() < (1e-4 if precision == "f32" else 1e-5)
+
+
+def _low_bank():
+    """Templates starting at 2-15 frequency bins, so the 21-bin window of the first tranches reaches
+    below the DC bin; the chirp carries most of them across bin 10 within the observation."""
+    return ti.random_bank(256, 7, mc_range=(5.0, 100.0), f0_range=(0.0008, 0.006), eta=None, stream=31)
+
+
+@functools.lru_cache(maxsize=1)
+def _low_reference():
+    """Oracle values for the low bank, and 30-digit values (with the float64 phase rounding that every
+    float64 track shares) for its four templates of smallest chirp rate.  At such small beta = fdot dT^2
+    the float64 oracle's literal Fresnel form loses digits (1.9e-6 relative against the 30-digit value
+    for these templates), so the FP64 path is judged against the 30-digit values there."""
+    from oracle import o2_mp
+    d = small_data()
+    b = _low_bank()
+    ref = oracle_stat(d, bank=b)
+    chirp = b.mc ** (5.0 / 3.0) * b.f0 ** (11.0 / 3.0)
+    idx = np.argsort(chirp)[:4]
+    mp = np.array([o2_mp.statistic(d["pix"], d["u"], d["wm"], b, d["grid"], int(i), dps=30, float64_phase=True)
+                   for i in idx])
+    return ref, idx, mp
+
+
+@pytest.mark.parametrize("layout", ["layer", "layer_ci"])
+@pytest.mark.parametrize("precision,pixdt,tol", [("f64", "f64", 1e-6), ("f32", "f32", 1e-4)])
+def test_low_frequency_templates_match_oracle(layout, precision, pixdt, tol):
+    """The WAVE schedule's path for waves with a lane below bin 10, and the thread schedule, against
+    the oracle: FP32 at 1e-4; FP64 at 1e-6 against the 30-digit values of the smallest-beta templates
+    and at 3e-6 against the float64 oracle elsewhere (the oracle's own loss at small beta)."""
+    tfsc = lib()
+    d = small_data()
+    g = d["grid"]
+    b = _low_bank()
+    assert np.sum(b.f0 * g.tranche_dur < 9.0) > 64
+    note(f"low-frequency templates, {layout} {precision}")
+    ref, idx, mp = _low_reference()
+    bt = _bank(tfsc, b)
+    seg = tfsc.segment_layout(gridspec(g), bt)
+    st = store_from_oracle(d, pixdt, layout=layout)
+    tol_oracle = tol if precision == "f32" else 3e-6
+    for schedule in ("thread", "wave"):
+        res = tfsc.bank_statistic(gridspec(g), st, bt, seg, precision=precision, schedule=schedule)
+        s = res.stat.cpu().numpy()
+        r = rel(s, ref.stat)
+        r_mp = rel(s[idx], mp)
+        note(f"  {schedule}: max rel {r.max():.2e} vs oracle; smallest-beta templates {r_mp.max():.2e} vs 30 digits "
+             f"(oracle {rel(ref.stat[idx], mp).max():.2e})")
+        assert r.max() < tol_oracle, schedule
+        assert r_mp.max() < tol, schedule
+        assert np.array_equal(res.flags.cpu().numpy(), ref.flags)
+        assert np.max(np.abs(res.seg_terms.cpu().numpy() - ref.seg_terms) / np.maximum(ref.seg_terms, 1.0)) < 10 * tol_oracle
+
+
 def test_processing_order_does_not_change_results():
     tfsc = lib()
     d = small_data()
@@ -152,19 +228,20 @@ def test_empty_bank_and_errors():
                             tfsc.segment_layout(gridspec(g), _bank(tfsc, d["bank"])), precision="f32")
 
 
+@pytest.mark.parametrize("layout", ["layer", "layer_ci"])
 @pytest.mark.parametrize("dtype,tol", [("f16", 2e-3), ("bf16", 2e-2)])
-def test_16bit_store_error_against_oracle(dtype, tol):
+def test_16bit_store_error_against_oracle(dtype, tol, layout):
     """16-bit pixels with a per-layer FP32 scale, FP32 arithmetic: error of Upsilon vs the FP64 oracle."""
     tfsc = lib()
     d = small_data()
     g = d["grid"]
-    note(f"16-bit store {dtype}")
+    note(f"16-bit store {dtype} {layout}")
     x32 = d["x"].astype(np.float32)
     from oracle import transform as otf
     ref_pix, u, wm = otf.transform(x32.astype(np.float64), g, d["psd"], d["mu"], d["keep"], 0.1, "rfft")
     from oracle import cpu as ocpu
     ref = ocpu.statistic(ref_pix, u, wm, d["bank"], g)
-    st = tfsc.transform(gridspec(g), dev(x32), dev(d["psd"]), dev(d["mu"]), dev(d["keep"]), dtype=dtype)
+    st = tfsc.transform(gridspec(g), dev(x32), dev(d["psd"]), dev(d["mu"]), dev(d["keep"]), dtype=dtype, layout=layout)
     bt = _bank(tfsc, d["bank"])
     seg = tfsc.segment_layout(gridspec(g), bt)
     res = tfsc.bank_statistic(gridspec(g), st, bt, seg, precision="f32", schedule="wave")

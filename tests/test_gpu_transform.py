@@ -13,6 +13,8 @@ def _complex(store):
     z = torch.view_as_complex(p.contiguous().to(torch.float64 if p.dtype == torch.float64 else torch.float32))
     if store.layout == "tranche":
         z = z.transpose(1, 2)
+    elif store.layout == "layer_ci":
+        z = z.permute(2, 0, 1)
     z = z.to(torch.complex128)
     if store.layer_scale is not None:
         z = z * store.layer_scale.to(torch.float64)[:, :, None]
@@ -34,7 +36,7 @@ def test_tiny_fp64_transform():
     assert np.array_equal(st.tranche_w.cpu().numpy(), d["wm"])
 
 
-@pytest.mark.parametrize("layout", ["layer", "tranche"])
+@pytest.mark.parametrize("layout", ["layer", "tranche", "layer_ci"])
 def test_two_channel_fp32_transform(layout):
     tfsc = lib()
     d = small_data()
@@ -53,15 +55,17 @@ def test_two_channel_fp32_transform(layout):
     assert np.all(z[:, :, d["keep"] == 0] == 0)
 
 
+@pytest.mark.parametrize("layout", ["layer", "layer_ci"])
 @pytest.mark.parametrize("dtype,bits", [("f16", 11), ("bf16", 8)])
-def test_16bit_store_with_layer_scale(dtype, bits):
+def test_16bit_store_with_layer_scale(dtype, bits, layout):
     tfsc = lib()
     d = small_data()
     g = d["grid"]
-    note(f"transform {dtype}")
+    note(f"transform {dtype} {layout}")
     x32 = d["x"].astype(np.float32)
     ref32 = tfsc.transform(gridspec(g), dev(x32), dev(d["psd"]), dev(d["mu"]), dev(d["keep"]), dtype="f32")
-    st = tfsc.transform(gridspec(g), dev(x32), dev(d["psd"]), dev(d["mu"]), dev(d["keep"]), dtype=dtype)
+    st = tfsc.transform(gridspec(g), dev(x32), dev(d["psd"]), dev(d["mu"]), dev(d["keep"]), dtype=dtype,
+                        layout=layout)
     z, r = _complex(st), _complex(ref32)
     sc = st.layer_scale.cpu().numpy()
     comp = np.maximum(np.abs(r.real).max(axis=2), np.abs(r.imag).max(axis=2))

@@ -162,6 +162,23 @@ def test_vjp_reduced_precision_pixels(dtype, tol):
     assert cell.max() < tol
 
 
+def test_vjp_channel_interleaved_store_equals_layer_major():
+    """The VJP reads LAYER_MAJOR_CI pixels at the same values as LAYER_MAJOR ones: same gradients bit for bit."""
+    tfsc = lib()
+    d = small_data()
+    g = d["grid"]
+    note("vjp channel-interleaved store")
+    bt = tfsc.BankTensors.from_host(d["bank"])
+    seg = tfsc.segment_layout(gridspec(g), bt)
+    out = []
+    for layout in ("layer", "layer_ci"):
+        store = store_from_oracle(d, "f32", layout=layout)
+        res = tfsc.bank_statistic(gridspec(g), store, bt, seg, precision="f32", schedule="wave", want_zn=True)
+        out.append(tfsc.statistic_vjp(gridspec(g), store, bt, seg, res.seg_zn,
+                                      g_stat=torch.ones(bt.n, dtype=torch.float64, device="cuda")))
+    assert torch.equal(out[0], out[1])
+
+
 def test_autograd_function_uses_the_vjp():
     """TFSCStatistic.backward returns the C-ABI VJP; one gradient-ascent step on the tiny data raises Upsilon."""
     tfsc = lib()
