@@ -585,47 +585,100 @@ __device__ __forceinline__ void bin_pixels(__amdgpu_buffer_rsrc_t r, uint32_t vo
     }
 }
 
-// One bin's contribution: g = weighted template bin (exact Fresnel form on the wave's band
-// [jA, jB], asymptotic form elsewhere), Q += |g|^2, P_c += conj(D_c) g.
-template <int C, class R, class PixT>
-__device__ __forceinline__ void bin_accumulate(const TrancheSpec<R> &ts, int jj, R w, int jA, int jB,
-                                               const cx<typename PixTraits<PixT>::R> (&Dl)[C],
-                                               const float *__restrict__ sc_bin, int KP, cx<R> (&P)[C], R &Q) {
-#pragma clang fp contract(fast)
-    const int j = jj - kHalfBins;
-    const R xj = ts.x - (R)j;
-    cx<R> g;
-    if (j >= jA && j <= jB) {
-        const cx<R> h = bin_full(ts, xj, j);
-        g = {h.re * w, h.im * w};
-    } else {
-        g = bin_fast_weighted(ts, xj, w);
+// Tranche sums of the WAVE schedule.  A bin on the wave's band [jA, jB] adds its exact
+// weighted value g directly: P_c += conj(D_c) g, Q += |g|^2.  Every other bin takes the
+// asymptotic form g = i Q w (E0 / (x - j) - E1 / (x - j + beta)), written with
+//   r = w / ((x - j)(x - j + beta)),  b = (x - j) r = w / (x - j + beta)
+// as g = beta r E0' + b Delta',  E0' = i Q E0,  Delta' = i Q (E0 - E1).
+// The bin then adds only real multiples of conj(D_c) and the products r^2, b^2, r b; the
+// tranche constants are applied once at the end (finish).  beta r carries the difference of
+// the two edge terms without cancellation, and outside the band the two parts of g are
+// never close to opposite, so |g|^2 summed from the three products keeps FP32 precision.
+template <int C, class R>
+struct BinSums {
+    cx<R> P[C];          // band bins: sum conj(D_c) g
+    R Q;                 // band bins: sum |g|^2
+    cx<R> Ar[C], Ab[C];  // asymptotic bins: sum r conj(D_c), sum b conj(D_c)
+    R Srr, Sbb, Srb;     // asymptotic bins: sum r^2, b^2, r b
+
+    __device__ __forceinline__ void zero() {
+#pragma unroll
+        for (int c = 0; c < C; ++c) P[c] = Ar[c] = Ab[c] = {(R)0, (R)0};
+        Q = Srr = Sbb = Srb = (R)0;
     }
-    Q += g.re * g.re;
-    Q += g.im * g.im;
+
+    // P_c and Q of the whole tranche
+    __device__ __forceinline__ void finish(const TrancheSpec<R> &ts, cx<R> (&Pc)[C], R &Qc) const {
+#pragma clang fp contract(fast)
+        const R qb = ts.Q * ts.beta;
+        const cx<R> e0 = {-qb * ts.E0.im, qb * ts.E0.re};  // beta E0'
+        const cx<R> dl = {-ts.Q * (ts.E0.im - ts.E1.im), ts.Q * (ts.E0.re - ts.E1.re)};
+#pragma unroll
+        for (int c = 0; c < C; ++c) Pc[c] = cadd(P[c], cadd(cmul(e0, Ar[c]), cmul(dl, Ab[c])));
+        const R n0 = e0.re * e0.re + e0.im * e0.im;
+        const R n1 = dl.re * dl.re + dl.im * dl.im;
+        const R x01 = e0.re * dl.re + e0.im * dl.im;
+        Qc = Q + n0 * Srr + n1 * Sbb + (R)2 * x01 * Srb;
+    }
+};
+
+template <int C, class R, class PixT>
+__device__ __forceinline__ void bin_accumulate(const TrancheSpec<R> &ts, int j, R xj, R w, int jA, int jB,
+                                               const cx<typename PixTraits<PixT>::R> (&Dl)[C],
+                                               const float *__restrict__ sc_bin, int KP, BinSums<C, R> &acc) {
+#pragma clang fp contract(fast)
+    cx<R> D[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        cx<R> D = {(R)Dl[c].re, (R)Dl[c].im};
+        D[c] = {(R)Dl[c].re, (R)Dl[c].im};
         if constexpr (PixTraits<PixT>::scaled) {
             const R s = (R)sc_bin[c * KP];
-            D.re *= s;
-            D.im *= s;
+            D[c].re *= s;
+            D[c].im *= s;
         }
-        // conj(D) g accumulated as four separate multiply-adds
-        P[c].re += D.re * g.re;
-        P[c].re += D.im * g.im;
-        P[c].im += D.re * g.im;
-        P[c].im -= D.im * g.re;
+    }
+    if (j >= jA && j <= jB) {
+        const cx<R> h = bin_full(ts, xj, j);
+        const cx<R> g = {h.re * w, h.im * w};
+        acc.Q += g.re * g.re;
+        acc.Q += g.im * g.im;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            // conj(D) g accumulated as four separate multiply-adds
+            acc.P[c].re += D[c].re * g.re;
+            acc.P[c].re += D[c].im * g.im;
+            acc.P[c].im += D[c].re * g.im;
+            acc.P[c].im -= D[c].im * g.re;
+        }
+    } else {
+        const R xj1 = xj + ts.beta;
+        R r;
+        if constexpr (sizeof(R) == 4)
+            r = rcp(xj * xj1) * w;
+        else
+            r = w / (xj * xj1);
+        const R b = xj * r;
+        acc.Srr += r * r;
+        acc.Sbb += b * b;
+        acc.Srb += r * b;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            acc.Ar[c].re += r * D[c].re;
+            acc.Ar[c].im -= r * D[c].im;
+            acc.Ab[c].re += b * D[c].re;
+            acc.Ab[c].im -= b * D[c].im;
+        }
     }
 }
 
-// Bins of one tranche for the WAVE schedule.  The 21 bins are unrolled; each bin's pixel
-// row is a scalar offset from the lane's row of bin kc - 10, and the weight table is padded
-// with zeros so bins outside [1, M/2 - 1] contribute nothing.  The band-end rule keeps
-// kc + 10 <= M/2, so every row read lies in the store; a lane with kc < 10 would need a
-// row below 0, and a wave holding such a lane takes wave_tranche_bins_low instead.  The
-// exact Fresnel form is used only for the bins [jA, jB] where some lane of the wave may
-// need it (a wave-uniform choice).
+// Bins of one tranche for the WAVE schedule, fully unrolled (bin offsets are immediates) in
+// groups of three whose pixel loads are all issued before the group's first bin is evaluated
+// (a load consumed inside the band/asymptotic branch is otherwise waited for at once).  Each
+// bin's pixel row is a scalar offset from the lane's row of bin kc - 10, and the weight table
+// is padded with zeros so bins outside [1, M/2 - 1] contribute nothing.  The band-end rule keeps kc + 10 <= M/2, so every row
+// read lies in the store; a lane with kc < 10 would need a row below 0, and a wave holding
+// such a lane takes wave_tranche_bins_low instead.  The exact Fresnel form is used only for
+// the bins [jA, jB] where some lane of the wave may need it (a wave-uniform choice).
 template <int C, class R, class PixT, int LAYOUT>
 __device__ __forceinline__ void wave_tranche_bins(const TrancheSpec<R> &ts, int kc, int m, int Nt, int K,
                                                   __amdgpu_buffer_rsrc_t rsrc, const R *__restrict__ u_pad,
@@ -633,20 +686,27 @@ __device__ __forceinline__ void wave_tranche_bins(const TrancheSpec<R> &ts, int 
                                                   R &Q) {
     constexpr uint32_t B = sizeof(PixT) == 8 ? 16u : (sizeof(PixT) == 4 ? 8u : 4u);
     constexpr uint32_t BP = LAYOUT == 2 ? (uint32_t)C * B : B;  // bytes per (bin, tranche) cell
+    constexpr int NB = 2 * kHalfBins + 1, G = 3;
+    static_assert(NB % G == 0, "bin groups must tile the window");
     const uint32_t voff = (uint32_t)((kc - kHalfBins) * Nt + m) * BP;
     const uint32_t row = (uint32_t)Nt * BP, chan = (uint32_t)K * row;
     const int KP = K + 2 * kHalfBins;
     const R *uk = u_pad + kc;  // uk[jj] = u_pad[kc + jj] = u_{kc + jj - 10}
     const float *sk = sc_pad + kc;
+    BinSums<C, R> acc;
+    acc.zero();
 #pragma unroll
-    for (int c = 0; c < C; ++c) P[c] = {(R)0, (R)0};
-    Q = (R)0;
-#pragma unroll 7
-    for (int jj = 0; jj < 2 * kHalfBins + 1; ++jj) {
-        cx<typename PixTraits<PixT>::R> Dl[C];
-        bin_pixels<C, PixT, LAYOUT>(rsrc, voff, (uint32_t)jj * row, chan, Dl);
-        bin_accumulate<C, R, PixT>(ts, jj, uk[jj], jA, jB, Dl, sk + jj, KP, P, Q);
+    for (int j0 = 0; j0 < NB; j0 += G) {
+        cx<typename PixTraits<PixT>::R> Dl[G][C];
+#pragma unroll
+        for (int u = 0; u < G; ++u) bin_pixels<C, PixT, LAYOUT>(rsrc, voff, (uint32_t)(j0 + u) * row, chan, Dl[u]);
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int j = j0 + u - kHalfBins;
+            bin_accumulate<C, R, PixT>(ts, j, ts.x - (R)j, uk[j0 + u], jA, jB, Dl[u], sk + j0 + u, KP, acc);
+        }
     }
+    acc.finish(ts, P, Q);
 }
 
 // As wave_tranche_bins for a wave with some lane below bin 10: each bin's row is a per-lane
@@ -663,16 +723,17 @@ __device__ __forceinline__ void wave_tranche_bins_low(const TrancheSpec<R> &ts, 
     const int KP = K + 2 * kHalfBins;
     const R *uk = u_pad + kc;
     const float *sk = sc_pad + kc;
-#pragma unroll
-    for (int c = 0; c < C; ++c) P[c] = {(R)0, (R)0};
-    Q = (R)0;
+    BinSums<C, R> acc;
+    acc.zero();
 #pragma unroll 1
     for (int jj = 0; jj < 2 * kHalfBins + 1; ++jj) {
-        const int k = max(kc - kHalfBins + jj, 0);
+        const int j = jj - kHalfBins;
+        const int k = max(kc + j, 0);
         cx<typename PixTraits<PixT>::R> Dl[C];
         bin_pixels<C, PixT, LAYOUT>(rsrc, (uint32_t)(k * Nt + m) * BP, 0u, chan, Dl);
-        bin_accumulate<C, R, PixT>(ts, jj, uk[jj], jA, jB, Dl, sk + jj, KP, P, Q);
+        bin_accumulate<C, R, PixT>(ts, j, ts.x - (R)j, uk[jj], jA, jB, Dl, sk + jj, KP, acc);
     }
+    acc.finish(ts, P, Q);
 }
 
 // Per-template constants are the same in every lane of a wave; stating that with
