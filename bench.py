@@ -54,6 +54,13 @@ def parse():
     p.add_argument("--follow-up", action="store_true",
                    help="also run the differentiation workload: 50 Adam steps on the top 65,536 templates of "
                         "the batching bank (implies --batching)")
+    p.add_argument("--background", action="store_true",
+                   help="also build the background of the batching workload: per-tile maxima of the 16 "
+                        "realisations on an 8 x 8 (Mc, f0) tile grid, power-law and Gumbel tail fits "
+                        "(implies --batching)")
+    p.add_argument("--ladder", action="store_true",
+                   help="also run the segment ladder N_seg 16 -> 8 -> 4 -> 2 -> 1 (20 ascent steps per stage) "
+                        "on the top 65,536 templates of the batching bank (implies --batching)")
     p.add_argument("--copy-calibration", action="store_true",
                    help="copy 256 MiB device-to-device once, so profiler byte counters can be calibrated")
     return p.parse_args()
@@ -239,7 +246,7 @@ def main():
     }
 
     # ---------------- CPU baseline: the plain-C oracle on host cores, bounded sample
-    if args.batching or args.follow_up:
+    if args.batching or args.follow_up or args.background or args.ladder:
         del res, res_c, res_p, pix_plain
         torch.cuda.empty_cache()
         out["batching"] = batching_run(args, tfsc, ti, grid, g, psd_d, mu_d, keep_d, kw)
@@ -276,6 +283,44 @@ def batching_run(args, tfsc, ti, grid, g, psd_d, mu_d, keep_d, kw):
     log(f"batching: one replay {wall * 1e3:.1f} ms, {evals / wall / 1e6:.3f} M template-realisations/s")
     rec = {"templates": bank.n, "realisations": R, "ms_per_replay": round(wall * 1e3, 2),
            "template_realisations_per_s": round(evals / wall, 1), "graph": "transform + statistic x 16"}
+    if args.background:
+        from paper_2510_19047_amd import background as bg
+        n_m, n_f = 8, 8
+        tiles = bg.tile_ids(bank_h.mc, bank_h.f0, np.geomspace(5.0, 100.0, n_m + 1), np.linspace(0.005, 0.050, n_f + 1))
+        B = bg.Background(tiles, n_m * n_f, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r in range(R):
+            B.add(rg.results[r].stat)
+        wall = time.perf_counter() - t0
+        pl, gb = B.fits()
+        mx = B.maxima
+        log(f"background: per-tile maxima of {R} realisations x {n_m * n_f} tiles in {wall * 1e3:.1f} ms; "
+            f"Gumbel mu {gb.mu:.2f} beta {gb.beta:.3f}; power law delta {pl.delta:.2f} above {pl.u:.2f}")
+        rec["background"] = {"realisations": R, "tiles": n_m * n_f, "tile_grid": "8 log-Mc x 8 f0",
+                             "ms_tile_max_all_realisations": round(wall * 1e3, 3),
+                             "max_median": round(float(np.median(mx)), 3), "max_max": round(float(mx.max()), 3),
+                             "gumbel": {"mu": round(gb.mu, 4), "beta": round(gb.beta, 4)},
+                             "power_law": {"delta": round(pl.delta, 4), "u": round(pl.u, 4), "q": pl.q},
+                             "fap_at_max": {"gumbel": float(bg.fap_gumbel(mx.max(), gb)),
+                                            "power_law": float(bg.fap_power_law(mx.max(), pl))}}
+    if args.ladder:
+        from paper_2510_19047_amd import search
+        stat0 = rg.results[0].stat
+        top = torch.topk(torch.nan_to_num(stat0, nan=-1.0), 65536).indices
+        sub = tfsc.BankTensors(*(getattr(bank, k)[top].contiguous() for k in tfsc.BankTensors.FIELDS))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lad = search.segment_ladder(grid, rg.stores[0], sub, steps=20, lr_scale=0.5, precision="f32")
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        u1 = lad.upsilon1.cpu().numpy()
+        stages = [{"nseg": ns, "start_median": round(float(a.median().item()), 3),
+                   "best_median": round(float(b.median().item()), 3)} for ns, a, b in zip(lad.nseg, lad.start, lad.best)]
+        log(f"ladder: N_seg {'->'.join(str(v) for v in lad.nseg)}, 20 steps each, on 65536 templates in {wall:.2f} s; "
+            f"Upsilon_1 median {np.median(u1):.2f}")
+        rec["ladder"] = {"templates": 65536, "steps_per_stage": 20, "wall_s": round(wall, 3), "stages": stages,
+                         "upsilon1_median": round(float(np.median(u1)), 3), "upsilon1_p90": round(float(np.quantile(u1, 0.9)), 3)}
     if args.follow_up:
         stat0 = rg.results[0].stat
         top = torch.topk(torch.nan_to_num(stat0, nan=-1.0), 65536).indices

@@ -235,6 +235,19 @@ tfsc_status tfsc_follow_up_step(const tfsc_grid *grid, tfsc_bank *bank, const tf
                                 const double *stat, const double *g_params, double *state, double lr_scale,
                                 int step, void *stream);
 
+/* Largest statistic per parameter tile (paper Sec. "Results": the false-alarm
+ * probability of a candidate comes from the background distribution of the
+ * largest statistic a noise-only search returns in its tile).  stat[n] and
+ * tile[n] are device arrays (tile[i] in 0..n_tiles-1, or negative to leave
+ * template i out; stat[i] that is negative or NaN is also left out);
+ * tile_max[n_tiles] receives each tile's largest stat (0 for a tile with no
+ * template) and tile_arg[n_tiles] the smallest index attaining it (-1 for an
+ * empty tile).  Exact: a maximum, not a sum, so the result is independent of
+ * scheduling.  Plain kernels only (no memset), so the call can be captured
+ * into a HIP graph.  n = 0 is allowed; n_tiles >= 1.                       */
+tfsc_status tfsc_tile_max(const double *stat, const int32_t *tile, int64_t n, int32_t n_tiles, double *tile_max,
+                          int64_t *tile_arg, void *stream);
+
 /* The FP64 track behind every statistic call, for inspection: out[n][Nt][4]
  * holds (Phi_m, f_m, fdot_m, code_m) at each tranche start t_m = m dT, with
  * code_m = 0 for an active tranche, else the TFSC_FLAG_* bit of the

@@ -16,7 +16,7 @@ from . import _lib
 from ._lib import TfscError
 
 __all__ = ["GridSpec", "PixelStore", "BankTensors", "SegmentLayout", "StatResult", "transform", "segment_layout",
-           "bank_statistic", "statistic_vjp", "track", "TFSCStatistic", "lib", "TfscError"]
+           "bank_statistic", "statistic_vjp", "track", "tile_max", "TFSCStatistic", "lib", "TfscError"]
 
 _DTYPE = {"f64": _lib.F64, "f32": _lib.F32, "bf16": _lib.BF16, "f16": _lib.F16}
 _TORCH_STORE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
@@ -286,6 +286,21 @@ def follow_up(grid: GridSpec, pixels: PixelStore, bank: BankTensors, steps: int 
         statistic_vjp(grid, pixels, work, seg, res.seg_zn, g_stat=ones, out=gp)
         follow_up_step(grid, work, seg, res.stat, gp, state, lr_scale, step)
     return first, state[:, 10].clone(), state[:, 11:16].clone()
+
+
+def tile_max(stat: torch.Tensor, tile: torch.Tensor, n_tiles: int, out: tuple | None = None):
+    """tfsc_tile_max: (largest stat per tile [n_tiles] f64, smallest index attaining it [n_tiles] int64, -1 if
+    the tile is empty).  ``tile`` is int32 per template (negative = left out)."""
+    L = lib()
+    if stat.dtype != torch.float64 or tile.dtype != torch.int32 or stat.numel() != tile.numel():
+        raise TfscError("tile_max takes float64 stat and int32 tile ids of the same length")
+    dev = stat.device
+    if out is None:
+        out = (torch.empty(n_tiles, dtype=torch.float64, device=dev), torch.empty(n_tiles, dtype=torch.int64, device=dev))
+    stat, tile = stat.contiguous(), tile.contiguous()
+    _lib.check(L.tfsc_tile_max(_ptr(stat), _ptr(tile), stat.numel(), int(n_tiles), _ptr(out[0]), _ptr(out[1]),
+                               _stream()), "tfsc_tile_max")
+    return out
 
 
 def track(grid: GridSpec, bank: BankTensors) -> torch.Tensor:

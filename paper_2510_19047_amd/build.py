@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtfsc.so")
-SOURCES = ["tfsc_api.hip", "tfsc_stat.hip", "tfsc_transform.hip", "tfsc_vjp.hip", "tfsc_follow.hip"]
+SOURCES = ["tfsc_api.hip", "tfsc_stat.hip", "tfsc_transform.hip", "tfsc_vjp.hip", "tfsc_follow.hip", "tfsc_tiles.hip"]
 HEADERS = ["tfsc_device.hpp", "tfsc_kernels.hpp", os.path.join("..", "..", "include", "tfsc.h")]
 ARCH = os.environ.get("TFSC_OFFLOAD_ARCH", "gfx950")
 

@@ -299,6 +299,14 @@ tfsc_status tfsc_follow_up_step(const tfsc_grid *grid, tfsc_bank *bank, const tf
     return hip_status(tfsc::launch_follow_step(L, reinterpret_cast<hipStream_t>(stream)));
 }
 
+tfsc_status tfsc_tile_max(const double *stat, const int32_t *tile, int64_t n, int32_t n_tiles, double *tile_max,
+                          int64_t *tile_arg, void *stream) {
+    if (n < 0 || n_tiles < 1 || !tile_max || !tile_arg) return TFSC_ERR_ARG;
+    if (n > 0 && (!stat || !tile)) return TFSC_ERR_ARG;
+    return hip_status(tfsc::launch_tile_max(stat, tile, n, n_tiles, tile_max, tile_arg,
+                                            reinterpret_cast<hipStream_t>(stream)));
+}
+
 tfsc_status tfsc_transform(const tfsc_grid *grid, const void *x, int x_dtype, const double *psd0,
                            const double *tranche_psd_scale, const uint8_t *tranche_keep, tfsc_pixels *out,
                            void *ws, size_t ws_bytes, void *stream) {

@@ -101,6 +101,8 @@ hipError_t launch_vjp(const VjpLaunch &L, hipStream_t st);
 hipError_t launch_transform(const TransformLaunch &L, hipStream_t st);
 hipError_t launch_follow_step(const FollowLaunch &L, hipStream_t st);
 hipError_t launch_order(const OrderLaunch &L, hipStream_t st);
+hipError_t launch_tile_max(const double *stat, const int32_t *tile, int64_t n, int32_t n_tiles, double *tile_max,
+                           int64_t *tile_arg, hipStream_t st);
 hipError_t launch_track(int64_t n, int M, int Nt, double dt, const double *mc, const double *eta, const double *f0,
                         const double *ct, const double *ci, double *out, hipStream_t st);
 
