@@ -187,6 +187,34 @@ tfsc_status tfsc_bank_statistic(const tfsc_grid *grid, const tfsc_pixels *pix, c
                                 double *seg_zn, int32_t *flags, int32_t *n_active, void *ws, size_t ws_bytes,
                                 void *stream);
 
+/* The statistic of tfsc_bank_statistic for n_real noise realisations of the
+ * same grid in one pass over the bank (paper Sec. "Results": the background
+ * comes from many noise-only realisations; Sec. "Hardware acceleration and
+ * computational cost": large batches per launch).  Realisation r's pixel
+ * store lies r * real_stride bytes after pix->pix (same dtype, layout,
+ * inv_asd and tranche_w for all; real_stride a multiple of 16 and at least
+ * one store's size; n_real * real_stride < 4 GiB); 1 <= n_real <= 64.  Each
+ * template's track, Fresnel spectrum and response are formed once per group
+ * of `group` realisations (1, 2, 4 or 8; 0 = 8) and serve all of them; the
+ * remainder goes in smaller groups.  The per-tranche bin table is parked in
+ * LDS (21 complex values per lane), which limits residency to two waves per
+ * SIMD: on the full-size workload one tfsc_bank_statistic launch per
+ * realisation is faster, so this call serves callers that want one launch
+ * and one output block for several realisations.  Outputs: stat[r * n + i],
+ * seg_terms[r * seg_stride + seg_offset[i] + s] (seg_stride >= the total
+ * number of segments, the caller's to guarantee), flags[n] and n_active[n]
+ * (optional) once.  WAVE schedule; LAYER_MAJOR or LAYER_MAJOR_CI; FP32
+ * pixels with FP32 precision or FP64 pixels with FP64 precision, else
+ * TFSC_ERR_DTYPE; no seg_zn (the VJP takes one realisation).  Sums are
+ * formed per bin rather than through the single-realisation kernel's
+ * factored asymptotic sums, so the two agree to rounding, not bit for bit.
+ * Needs TFSC_WS_STATISTIC workspace.                                       */
+tfsc_status tfsc_bank_statistic_multi(const tfsc_grid *grid, const tfsc_pixels *pix, int32_t n_real,
+                                      int64_t real_stride, int32_t group, const tfsc_bank *bank,
+                                      const tfsc_segments *seg, const tfsc_options *opt, int64_t seg_stride,
+                                      double *seg_terms, double *stat, int32_t *flags, int32_t *n_active, void *ws,
+                                      size_t ws_bytes, void *stream);
+
 /* Vector-Jacobian product of the statistic (gradient of Eq. (Upsilon-seg)
  * through Eqs. (overlap-n), (inner-segment-tf), (fresnel-ft) and the
  * response): g_params[n][5] =

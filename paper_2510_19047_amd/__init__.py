@@ -16,7 +16,8 @@ from . import _lib
 from ._lib import TfscError
 
 __all__ = ["GridSpec", "PixelStore", "BankTensors", "SegmentLayout", "StatResult", "transform", "segment_layout",
-           "bank_statistic", "statistic_vjp", "track", "tile_max", "TFSCStatistic", "lib", "TfscError"]
+           "bank_statistic", "bank_statistic_multi", "realisation_stores", "MultiResult", "statistic_vjp", "track",
+           "tile_max", "TFSCStatistic", "lib", "TfscError"]
 
 _DTYPE = {"f64": _lib.F64, "f32": _lib.F32, "bf16": _lib.BF16, "f16": _lib.F16}
 _TORCH_STORE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
@@ -210,6 +211,69 @@ def bank_statistic(grid: GridSpec, pixels: PixelStore, bank: BankTensors, seg: S
                                ctypes.byref(opt), _ptr(out.seg_terms), _ptr(out.stat), _ptr(out.seg_zn),
                                _ptr(out.flags), _ptr(out.n_active), _ptr(ws), ws.numel(), _stream())
     _lib.check(st, "tfsc_bank_statistic")
+    return out
+
+
+def realisation_stores(grid: GridSpec, n_real: int, dtype: str = "f32", layout: str = "layer_ci",
+                       device="cuda") -> list:
+    """n_real pixel stores in one contiguous block (the input of bank_statistic_multi), sharing inv_asd and
+    tranche_w; fill them with ``transform(..., out=stores[r])``."""
+    if dtype not in ("f32", "f64") or layout not in ("layer", "layer_ci"):
+        raise TfscError("several realisations take f32 or f64 stores in a layer-major layout")
+    K, Nt, C = grid.n_bins, grid.n_tranches, grid.n_channels
+    shape = (C, K, Nt, 2) if layout == "layer" else (K, Nt, C, 2)
+    block = torch.empty((n_real, *shape), dtype=_TORCH_STORE[dtype], device=device)
+    inv_asd = torch.empty(K, dtype=torch.float64, device=device)
+    tranche_w = torch.empty(Nt, dtype=torch.float64, device=device)
+    return [PixelStore(block[r], inv_asd, tranche_w, dtype, layout) for r in range(n_real)]
+
+
+@dataclass
+class MultiResult:
+    """bank_statistic_multi outputs: stat [R][n], seg_terms [R][total], flags and n_active [n] (shared)."""
+    stat: torch.Tensor
+    seg_terms: torch.Tensor
+    flags: torch.Tensor
+    n_active: torch.Tensor | None = None
+
+    def realisation(self, r: int) -> "StatResult":
+        return StatResult(self.stat[r], self.seg_terms[r], self.flags, None, self.n_active)
+
+
+def bank_statistic_multi(grid: GridSpec, stores: list, bank: BankTensors, seg: SegmentLayout, precision: str = "f32",
+                         block_waves: int = 0, groups_per_cu: int = 0, order: torch.Tensor | None = None,
+                         out: MultiResult | None = None, ws: torch.Tensor | None = None,
+                         want_active: bool = False, group: int = 0) -> MultiResult:
+    """tfsc_bank_statistic_multi: the statistic of every realisation in ``stores`` (from realisation_stores,
+    or any stores laid out at one stride in one block), ``group`` realisations (1, 2, 4, 8; 0 = 8) per pass
+    over the bank."""
+    L = lib()
+    dev = bank.mc.device
+    R = len(stores)
+    if R == 0:
+        raise TfscError("no realisations")
+    p0 = stores[0].pix
+    stride = (stores[1].pix.data_ptr() - p0.data_ptr()) if R > 1 else p0.numel() * p0.element_size()
+    for r in range(1, R):
+        if stores[r].pix.data_ptr() - p0.data_ptr() != r * stride:
+            raise TfscError("realisation stores must lie at one stride in one block")
+    total = max(seg.total, 1)
+    if out is None:
+        out = MultiResult(torch.empty((R, bank.n), dtype=torch.float64, device=dev),
+                          torch.empty((R, total), dtype=torch.float64, device=dev),
+                          torch.empty(bank.n, dtype=torch.int32, device=dev),
+                          torch.empty(bank.n, dtype=torch.int32, device=dev) if want_active else None)
+    g = grid.c()
+    opt = _options(precision, "wave", block_waves, groups_per_cu, order)
+    nb = L.tfsc_workspace_bytes(ctypes.byref(g), bank.n, ctypes.byref(opt), _lib.WS_STATISTIC)
+    if ws is None or ws.numel() < nb:
+        ws = _ws(nb, dev)
+    pc, bc, sc = stores[0].c(), bank.c(), seg.c()
+    st = L.tfsc_bank_statistic_multi(ctypes.byref(g), ctypes.byref(pc), R, stride, int(group), ctypes.byref(bc),
+                                     ctypes.byref(sc),
+                                     ctypes.byref(opt), out.seg_terms.shape[1], _ptr(out.seg_terms), _ptr(out.stat),
+                                     _ptr(out.flags), _ptr(out.n_active), _ptr(ws), ws.numel(), _stream())
+    _lib.check(st, "tfsc_bank_statistic_multi")
     return out
 
 

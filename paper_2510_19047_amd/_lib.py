@@ -42,7 +42,8 @@ class Options(ctypes.Structure):
 
 
 EXPORTS = ("tfsc_abi_version", "tfsc_status_string", "tfsc_workspace_bytes", "tfsc_transform",
-           "tfsc_segment_layout", "tfsc_bank_statistic", "tfsc_statistic_vjp", "tfsc_follow_up_step",
+           "tfsc_segment_layout", "tfsc_bank_statistic", "tfsc_bank_statistic_multi", "tfsc_statistic_vjp",
+           "tfsc_follow_up_step",
            "tfsc_processing_order", "tfsc_tile_max", "tfsc_track")
 
 _lib = None
@@ -83,6 +84,11 @@ def load(path: str = LIB_PATH):
                                       ctypes.c_int, c_void_p]
     L.tfsc_processing_order.restype = ctypes.c_int
     L.tfsc_processing_order.argtypes = [P(Grid), P(Bank), c_void_p, c_void_p, c_size_t, c_void_p]
+    L.tfsc_bank_statistic_multi.restype = ctypes.c_int
+    L.tfsc_bank_statistic_multi.argtypes = [P(Grid), P(Pixels), ctypes.c_int32, ctypes.c_int64, ctypes.c_int32,
+                                            P(Bank), P(Segments),
+                                            P(Options), ctypes.c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
+                                            c_void_p, c_size_t, c_void_p]
     L.tfsc_tile_max.restype = ctypes.c_int
     L.tfsc_tile_max.argtypes = [c_void_p, c_void_p, ctypes.c_int64, ctypes.c_int32, c_void_p, c_void_p, c_void_p]
     L.tfsc_track.restype = ctypes.c_int

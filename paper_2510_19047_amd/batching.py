@@ -19,7 +19,8 @@ import os
 
 import torch
 
-from . import (BankTensors, GridSpec, PixelStore, SegmentLayout, StatResult, bank_statistic, transform)
+from . import (BankTensors, GridSpec, PixelStore, SegmentLayout, StatResult, bank_statistic, bank_statistic_multi,
+               realisation_stores, transform)
 
 CANDIDATES = ((4, 4), (4, 3), (4, 2), (2, 8), (2, 6), (2, 4), (1, 12), (1, 8))
 
@@ -88,22 +89,34 @@ class RealisationGraph:
     xs: [R][C][N] device time series (f32 or f64).  The pixel stores (``layout``: "layer_ci" or
     "layer", the two the WAVE schedule reads), results and workspace are
     allocated once (eager warm-up) and reused by every replay; ``results[r]`` holds realisation r's
-    output after ``replay()``.
+    output after ``replay()``.  multi=True keeps the stores in one block and evaluates every
+    realisation in one pass over the bank (bank_statistic_multi) instead of one launch each.
     """
 
     def __init__(self, grid: GridSpec, xs: torch.Tensor, psd0: torch.Tensor, mu: torch.Tensor, keep: torch.Tensor,
                  bank: BankTensors, seg: SegmentLayout, store: str = "f32", precision: str = "f32",
                  order: torch.Tensor | None = None, block_waves: int = 0, groups_per_cu: int = 0,
-                 layout: str = "layer_ci"):
+                 layout: str = "layer_ci", multi: bool = False, group: int = 0):
         self.grid, self.xs, self.psd0, self.mu, self.keep = grid, xs, psd0, mu, keep
         self.bank, self.seg, self.store, self.precision, self.order = bank, seg, store, precision, order
         self.shape = dict(block_waves=block_waves, groups_per_cu=groups_per_cu)
+        self.multi, self.group = multi, group
         R = xs.shape[0]
         dev = bank.mc.device
-        self.stores = [transform(grid, xs[r], psd0, mu, keep, dtype=store, layout=layout) for r in range(R)]
+        if multi:
+            self.stores = realisation_stores(grid, R, dtype=store, layout=layout, device=dev)
+            for r in range(R):
+                transform(grid, xs[r], psd0, mu, keep, dtype=store, out=self.stores[r])
+        else:
+            self.stores = [transform(grid, xs[r], psd0, mu, keep, dtype=store, layout=layout) for r in range(R)]
         self.ws = torch.empty(1 << 22, dtype=torch.uint8, device=dev)
-        self.results = [bank_statistic(grid, self.stores[r], bank, seg, precision=precision, schedule="wave",
-                                       order=order, ws=self.ws, **self.shape) for r in range(R)]
+        if multi:
+            self.multi_result = bank_statistic_multi(grid, self.stores, bank, seg, precision=precision, order=order,
+                                                     ws=self.ws, group=group, **self.shape)
+            self.results = [self.multi_result.realisation(r) for r in range(R)]
+        else:
+            self.results = [bank_statistic(grid, self.stores[r], bank, seg, precision=precision, schedule="wave",
+                                           order=order, ws=self.ws, **self.shape) for r in range(R)]
         torch.cuda.synchronize()
         self.graph = torch.cuda.CUDAGraph()
         with torch.cuda.graph(self.graph):
@@ -112,8 +125,12 @@ class RealisationGraph:
     def _enqueue(self):
         for r in range(self.xs.shape[0]):
             transform(self.grid, self.xs[r], self.psd0, self.mu, self.keep, dtype=self.store, out=self.stores[r])
-            bank_statistic(self.grid, self.stores[r], self.bank, self.seg, precision=self.precision,
-                           schedule="wave", order=self.order, out=self.results[r], ws=self.ws, **self.shape)
+            if not self.multi:
+                bank_statistic(self.grid, self.stores[r], self.bank, self.seg, precision=self.precision,
+                               schedule="wave", order=self.order, out=self.results[r], ws=self.ws, **self.shape)
+        if self.multi:
+            bank_statistic_multi(self.grid, self.stores, self.bank, self.seg, precision=self.precision,
+                                 order=self.order, out=self.multi_result, ws=self.ws, group=self.group, **self.shape)
 
     def replay(self) -> list[StatResult]:
         self.graph.replay()

@@ -218,6 +218,47 @@ tfsc_status tfsc_bank_statistic(const tfsc_grid *grid, const tfsc_pixels *pix, c
     return hip_status(tfsc::launch_statistic(L, st));
 }
 
+tfsc_status tfsc_bank_statistic_multi(const tfsc_grid *grid, const tfsc_pixels *pix, int32_t n_real,
+                                      int64_t real_stride, int32_t group, const tfsc_bank *bank,
+                                      const tfsc_segments *seg, const tfsc_options *opt, int64_t seg_stride,
+                                      double *seg_terms, double *stat, int32_t *flags, int32_t *n_active, void *ws,
+                                      size_t ws_bytes, void *stream) {
+    tfsc_status s;
+    if ((s = check_grid(grid)) != TFSC_OK) return s;
+    if ((s = check_bank(bank)) != TFSC_OK) return s;
+    if ((s = check_pixels(pix, bank->n > 0)) != TFSC_OK) return s;
+    if (!seg || (bank->n > 0 && (!seg->nseg || !seg->seg_offset))) return TFSC_ERR_ARG;
+    if (n_real < 1 || n_real > tfsc::kMaxRealisations || seg_stride < 0) return TFSC_ERR_ARG;
+    if (group != 0 && group != 1 && group != 2 && group != 4 && group != 8) return TFSC_ERR_ARG;
+    Resolved r;
+    if ((s = resolve_options(opt, pix, r)) != TFSC_OK) return s;
+    if (r.schedule != TFSC_SCHED_WAVE || pix->layout == TFSC_TRANCHE_MAJOR) return TFSC_ERR_UNSUPPORTED;
+    if (!(pix->dtype == TFSC_F32 && r.precision == TFSC_F32) && !(pix->dtype == TFSC_F64 && r.precision == TFSC_F64))
+        return TFSC_ERR_DTYPE;
+    const uint64_t one = pixel_store_bytes(grid, pix);
+    if (real_stride < 0 || (uint64_t)real_stride < one || real_stride % 16 != 0) return TFSC_ERR_SHAPE;
+    if ((uint64_t)real_stride * (uint64_t)n_real > 0xffffffffull) return TFSC_ERR_UNSUPPORTED;
+    if (bank->n > 0 && (!seg_terms || !stat || !flags)) return TFSC_ERR_ARG;
+    if (!ws || ws_bytes < ws_bytes_for(grid, bank->n, TFSC_WS_STATISTIC)) return TFSC_ERR_WORKSPACE;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (bank->n == 0) return TFSC_OK;
+    hipError_t e = tfsc::launch_geometry(grid->n_tranches, (double)grid->tranche_len * grid->dt,
+                                         reinterpret_cast<double *>(ws), st);
+    if (e != hipSuccess) return TFSC_ERR_HIP;
+    tfsc::StatLaunch L = stat_launch(grid, pix, bank, seg, r, ws);
+    e = tfsc::launch_weight_scale(grid->tranche_len / 2 + 1, pix->inv_asd, const_cast<double *>(L.u_scale), st);
+    if (e != hipSuccess) return TFSC_ERR_HIP;
+    L.seg_terms = seg_terms;
+    L.stat = stat;
+    L.flags = flags;
+    L.n_active = n_active;
+    L.n_real = n_real;
+    L.real_stride = real_stride;
+    L.seg_stride = seg_stride;
+    L.multi_group = group == 0 ? tfsc::kMultiGroupDefault : group;
+    return hip_status(tfsc::launch_statistic_multi(L, st));
+}
+
 tfsc_status tfsc_statistic_vjp(const tfsc_grid *grid, const tfsc_pixels *pix, const tfsc_bank *bank,
                                const tfsc_segments *seg, const tfsc_options *opt, const double *seg_zn,
                                const double *g_stat, const double *g_seg, double *g_params, void *ws,

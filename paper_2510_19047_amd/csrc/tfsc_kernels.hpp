@@ -48,7 +48,15 @@ struct StatLaunch {
     int32_t *flags;
     int32_t *n_active;
     uint32_t *counter;
+    // several realisations (launch_statistic_multi only)
+    int n_real;
+    int64_t real_stride;  // bytes between realisation stores
+    int64_t seg_stride;   // elements between realisation planes of seg_terms
+    int multi_group;      // realisations sharing one pass over the bank: 1, 2, 4 or 8
 };
+
+constexpr int kMultiGroupDefault = 8;
+constexpr int kMaxRealisations = 64;
 
 struct VjpLaunch {
     StatLaunch s;  // seg_terms / stat / flags unused
@@ -97,6 +105,7 @@ hipError_t launch_layout(const LayoutLaunch &L, hipStream_t st);
 hipError_t launch_geometry(int Nt, double dT, double *geo, hipStream_t st);
 hipError_t launch_weight_scale(int K, const double *inv_asd, double *scale_out, hipStream_t st);
 hipError_t launch_statistic(const StatLaunch &L, hipStream_t st);
+hipError_t launch_statistic_multi(const StatLaunch &L, hipStream_t st);
 hipError_t launch_vjp(const VjpLaunch &L, hipStream_t st);
 hipError_t launch_transform(const TransformLaunch &L, hipStream_t st);
 hipError_t launch_follow_step(const FollowLaunch &L, hipStream_t st);

@@ -242,6 +242,11 @@ struct StatArgs {
     int32_t *flags;
     int32_t *n_active;
     uint32_t *counter;
+    // several noise realisations of the same grid (k_stat_wave_multi): realisation r's store
+    // lies r * real_stride bytes after pix; its outputs at stat[r * n], seg_terms[r * seg_stride]
+    uint32_t real_stride;
+    int64_t seg_stride;
+    int rho0;  // first realisation of this launch
 };
 
 template <class R>
@@ -909,6 +914,247 @@ __global__ __launch_bounds__(256, 4) void k_stat_wave(StatArgs a) {
     }
 }
 
+// ------------------------------------------------------------------ WAVE schedule, several realisations
+// The same statistic for RR noise realisations of one grid in one pass over the bank (a design
+// alternative for the batching workload: one template's track, spectrum and response serve
+// every realisation of the group).  Per tranche the 21 weighted template bins c_j (exact form
+// on the wave's band, asymptotic form elsewhere) and Q = sum |c_j|^2 are formed once and parked
+// in LDS; each realisation then only gathers its pixels and forms P_c = sum_j conj(D_cj) c_j.
+// The segment state of realisation r (its z_n and running Upsilon) lives in lane r, the norm
+// N_n is shared.
+template <class R>
+__device__ __forceinline__ void wave_tranche_coefs(const TrancheSpec<R> &ts, int kc, const R *__restrict__ u_pad,
+                                                   int jA, int jB, cx<R> *cf, int lane, R &Q) {
+#pragma clang fp contract(fast)
+    const R *uk = u_pad + kc;  // uk[jj] = u_{kc + jj - 10}
+    Q = (R)0;
+#pragma unroll
+    for (int jj = 0; jj < 2 * kHalfBins + 1; ++jj) {
+        const int j = jj - kHalfBins;
+        const R xj = ts.x - (R)j;
+        const R w = uk[jj];
+        cx<R> g;
+        if (j >= jA && j <= jB) {
+            const cx<R> h = bin_full(ts, xj, j);
+            g = {h.re * w, h.im * w};
+        } else {
+            g = bin_fast_weighted(ts, xj, w);
+        }
+        Q += g.re * g.re;
+        Q += g.im * g.im;
+        cf[jj * 64 + lane] = g;
+    }
+}
+
+// P_c = sum_j conj(D_cj) c_j for one realisation (soff0 = its byte offset in the block);
+// loads in groups of three, issued before the group's arithmetic.  low: some lane of the
+// wave has kc < 10, so rows are per lane and clamped at 0 (their weight is 0).
+template <int C, class R, class PixT, int LAYOUT>
+__device__ __forceinline__ void wave_tranche_mac(const cx<R> *cf, int lane, int kc, int m, int Nt, int K,
+                                                 __amdgpu_buffer_rsrc_t rsrc, uint32_t soff0, bool low, cx<R> (&P)[C]) {
+#pragma clang fp contract(fast)
+    constexpr uint32_t B = sizeof(PixT) == 8 ? 16u : 8u;
+    constexpr uint32_t BP = LAYOUT == 2 ? (uint32_t)C * B : B;
+    constexpr int NB = 2 * kHalfBins + 1, G = 3;
+    const uint32_t row = (uint32_t)Nt * BP, chan = (uint32_t)K * row;
+    const uint32_t voff = (uint32_t)((kc - kHalfBins) * Nt + m) * BP;
+#pragma unroll
+    for (int c = 0; c < C; ++c) P[c] = {(R)0, (R)0};
+#pragma unroll
+    for (int j0 = 0; j0 < NB; j0 += G) {
+        cx<typename PixTraits<PixT>::R> Dl[G][C];
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            // low: the lane's own row, clamped at 0 (a per-lane offset; no branch per bin)
+            const int k = max(kc - kHalfBins + j0 + u, 0);
+            const uint32_t v = low ? (uint32_t)(k * Nt + m) * BP : voff;
+            const uint32_t so = low ? soff0 : soff0 + (uint32_t)(j0 + u) * row;
+            bin_pixels<C, PixT, LAYOUT>(rsrc, v, so, chan, Dl[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const cx<R> g = cf[(j0 + u) * 64 + lane];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const R dr = (R)Dl[u][c].re, di = (R)Dl[u][c].im;
+                P[c].re += dr * g.re;
+                P[c].re += di * g.im;
+                P[c].im += dr * g.im;
+                P[c].im -= di * g.re;
+            }
+        }
+    }
+}
+
+// Segment state of the multi-realisation kernel: N, cur and any are wave-uniform; zr, zi and
+// total belong to the realisation of the lane (lanes >= RR carry zeros).
+struct SegAccMulti {
+    double zr, zi, total;  // per lane
+    double N;              // shared
+    int cur;
+    bool any;
+};
+
+__device__ __forceinline__ void close_segments_multi(SegAccMulti &acc, int upto, int64_t off, double *seg_terms,
+                                                     int64_t seg_stride, bool owner, int lane) {
+    while (acc.cur < upto) {
+        const double v = acc.N > 0.0 ? 2.0 * (acc.zr * acc.zr + acc.zi * acc.zi) / acc.N : 0.0;
+        if (owner) seg_terms[(int64_t)lane * seg_stride + off + acc.cur] = v;
+        if (acc.N > 0.0) acc.any = true;
+        acc.total += v;
+        acc.zr = acc.zi = acc.N = 0.0;
+        ++acc.cur;
+    }
+}
+
+template <int C, class R, class PixT, int LAYOUT, int RR>
+__global__ __launch_bounds__(256, 4) void k_stat_wave_multi(StatArgs a) {
+    // LDS: u_pad[K + 20] (weights, as in k_stat_wave), then per wave the 21 weighted template
+    // bins of each lane's tranche, cf[j][lane], and the tranche sums of its RR realisations,
+    // zbuf[r][lane] = (Re z, Im z).
+    extern __shared__ unsigned char smem_raw[];
+    const int KP = a.K + 2 * kHalfBins;
+    R *u_pad = reinterpret_cast<R *>(smem_raw);
+    const size_t zoff = ((sizeof(R) * (size_t)KP + 15) / 16) * 16;
+    cx<R> *cfbuf = reinterpret_cast<cx<R> *>(smem_raw + zoff) + (size_t)(threadIdx.x >> 6) * (2 * kHalfBins + 1 + RR) * 64;
+    cx<R> *zbuf = cfbuf + (2 * kHalfBins + 1) * 64;
+    const double u_mul = a.u_scale[0];
+    const int kmax = a.M / 2 - 1;
+    for (int q = threadIdx.x; q < KP; q += blockDim.x) {
+        const int k = q - kHalfBins;
+        u_pad[q] = (k >= 1 && k <= kmax) ? (R)(a.inv_asd[k] * u_mul) : (R)0;
+    }
+    __syncthreads();
+    const __amdgpu_buffer_rsrc_t rsrc = pix_rsrc(a.pix, a.pix_bytes);
+    const GeoView gv = geo_view(a.geo, a.geo32, a.Nt);
+    double *const seg_terms = a.seg_terms + (int64_t)a.rho0 * a.seg_stride;
+    double *const stat = a.stat + (int64_t)a.rho0 * a.n;
+
+    const int lane = threadIdx.x & 63;
+    const bool owner = lane < RR;  // lane r holds realisation rho0 + r
+    for (;;) {
+        const uint32_t mine = atomicAdd(a.counter, lane == 0 ? 1u : 0u);
+        const int64_t item = (int64_t)__builtin_amdgcn_readfirstlane(mine);
+        if (item >= a.n) break;
+        const int64_t i = a.order ? (int64_t)__builtin_amdgcn_readfirstlane(a.order[item]) : item;
+        if (i < 0 || i >= a.n) continue;  // malformed processing order: skip rather than fault
+        const int ns = a.nseg[i];
+        const int64_t off = a.seg_offset[i];
+        SegAccMulti acc{0, 0, 0, 0, 0, false};
+        int flag = 0;
+        if (!params_valid(a.mc[i], a.eta[i], a.f0[i], a.ct[i], a.ci[i])) {
+            close_segments_multi(acc, ns, off, seg_terms, a.seg_stride, owner, lane);
+            if (owner) stat[(int64_t)lane * a.n + i] = 0.0;
+            if (lane == 0 && a.rho0 == 0) {
+                a.flags[i] = kFlagInvalid;
+                if (a.n_active) a.n_active[i] = 0;
+            }
+            continue;
+        }
+        Track T;
+        track_init(T, a.mc[i], a.eta[i], a.f0[i]);
+        wave_uniform(T);
+        Sky<R> S;
+        sky_init(S, a.ct[i], a.phi[i], a.psi[i], a.ci[i]);
+        wave_uniform(S);
+        int m_end = a.Nt, n_act = 0;
+        SegWalk sw;
+        sw.init(a.Nt, ns);
+        for (int m0 = 0; m0 < m_end; m0 += 64) {
+            const int m = m0 + lane;
+            const bool inr = m < a.Nt;
+            const double wm_raw = inr ? a.tranche_w[m] : 0.0;
+            double Phi = 0.0, f = 0.0, fdot = 0.0;
+            int code = inr ? track_step(T, (double)m * a.dT, a.dT, a.df, a.fnyq, Phi, f, fdot) : 0;
+            const uint64_t viol = __ballot(code != 0);
+            int lim = a.Nt;
+            if (viol) {
+                const int first = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)viol) - 1);
+                lim = m0 + first;
+                flag |= __builtin_amdgcn_readlane(code, first);
+                m_end = lim;
+            }
+            const bool active = inr && m < lim;
+            const double wmd = active ? wm_raw : 0.0;
+            const bool work = active && wmd != 0.0;
+            n_act += __popcll(__ballot(work));
+            TrancheSpec<R> ts;
+            int kc = 0;
+            int nlo = INT_MIN, hi = INT_MIN;
+            if (work) {
+                kc = tranche_setup(ts, Phi, f, fdot, a.dT);
+                nlo = -ts.j0lo;
+                hi = ts.j1hi;
+            }
+            wave_max2_i32(nlo, hi);
+            const int jA = -nlo;
+            const int jB = hi;
+            const bool low = __ballot(work && kc < kHalfBins) != 0;
+            R nn = 0;
+            if (work) {
+                // the response first, so its temporaries are gone before the bins are formed
+                cx<R> TA, TE;
+                transfer_ae(S, gv, m, f, TA, TE);
+                R tt = TA.re * TA.re + TA.im * TA.im;
+                if constexpr (C == 2) tt += TE.re * TE.re + TE.im * TE.im;
+                R Q;
+                wave_tranche_coefs<R>(ts, kc, u_pad, jA, jB, cfbuf, lane, Q);
+                const R wm = (R)wmd;
+                nn = wm * wm * tt * Q;
+#pragma unroll 1
+                for (int r = 0; r < RR; ++r) {
+                    cx<R> P[C];
+                    wave_tranche_mac<C, R, PixT, LAYOUT>(cfbuf, lane, kc, m, a.Nt, a.K, rsrc,
+                                                         (uint32_t)(a.rho0 + r) * a.real_stride, low, P);
+                    cx<R> z = cmul(TA, P[0]);
+                    if constexpr (C == 2) z = cadd(z, cmul(TE, P[1]));
+                    zbuf[r * 64 + lane] = {wm * z.re, wm * z.im};
+                }
+            } else {
+#pragma unroll 1
+                for (int r = 0; r < RR; ++r) zbuf[r * 64 + lane] = {(R)0, (R)0};
+            }
+            const int last = min(min(m0 + 63, lim - 1), a.Nt - 1);
+            if (last >= m0) {
+                while (sw.hi <= m0) sw.step();
+                for (;;) {
+                    const bool in_seg = active && m >= sw.lo && m < sw.hi;
+                    R vn = in_seg ? nn : (R)0;
+                    vn = wave_sum<R>(vn);
+                    close_segments_multi(acc, sw.s, off, seg_terms, a.seg_stride, owner, lane);
+                    acc.N += (double)vn;
+                    // realisation sums: lane r keeps realisation r's
+                    double myr = 0.0, myi = 0.0;
+#pragma unroll 1
+                    for (int r = 0; r < RR; r += 2) {
+                        const cx<R> z0 = zbuf[r * 64 + lane];
+                        const cx<R> z1 = r + 1 < RR ? zbuf[(r + 1) * 64 + lane] : cx<R>{(R)0, (R)0};
+                        R v0 = in_seg ? z0.re : (R)0, v1 = in_seg ? z0.im : (R)0, v2 = in_seg ? z1.re : (R)0;
+                        wave_sum3<R>(v0, v1, v2);
+                        R v3 = in_seg ? z1.im : (R)0;
+                        v3 = wave_sum<R>(v3);
+                        myr = lane == r ? (double)v0 : (lane == r + 1 ? (double)v2 : myr);
+                        myi = lane == r ? (double)v1 : (lane == r + 1 ? (double)v3 : myi);
+                    }
+                    acc.zr += myr;
+                    acc.zi += myi;
+                    if (sw.hi > last) break;
+                    sw.step();
+                }
+            }
+            if (viol) break;
+        }
+        if (m_end == 0) flag |= kFlagEmpty;
+        close_segments_multi(acc, ns, off, seg_terms, a.seg_stride, owner, lane);
+        if (!acc.any && m_end > 0) flag |= kFlagAllExcluded;
+        if (owner) stat[(int64_t)lane * a.n + i] = acc.total;
+        if (lane == 0 && a.rho0 == 0) {
+            a.flags[i] = flag;
+            if (a.n_active) a.n_active[i] = n_act;
+        }
+    }
+}
+
 // ------------------------------------------------------------------ track inspection
 __global__ void k_track(int64_t n, int Nt, double dt, double dT, const double *__restrict__ mc,
                         const double *__restrict__ eta, const double *__restrict__ f0, const double *__restrict__ ct,
@@ -1003,6 +1249,9 @@ static StatArgs make_args(const StatLaunch &L) {
     a.flags = L.flags;
     a.n_active = L.n_active;
     a.counter = L.counter;
+    a.real_stride = 0;
+    a.seg_stride = 0;
+    a.rho0 = 0;
     return a;
 }
 
@@ -1062,6 +1311,65 @@ static hipError_t dispatch_pix(const StatLaunch &L, const StatArgs &a, hipStream
 hipError_t launch_weight_scale(int K, const double *inv_asd, double *scale_out, hipStream_t st) {
     hipLaunchKernelGGL(k_weight_scale, dim3(1), dim3(256), 0, st, K, inv_asd, scale_out);
     return hipGetLastError();
+}
+
+template <int C, class R, int RR>
+static hipError_t launch_multi_rr(const StatArgs &a, int layout, int n_groups, int block_waves, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, a.counter, 1);
+    const size_t KP = (size_t)a.K + 2 * kHalfBins;
+    const size_t shmem =
+        ((sizeof(R) * KP + 15) / 16) * 16 + (size_t)block_waves * (2 * kHalfBins + 1 + RR) * 64 * sizeof(cx<R>);
+    if (shmem > 160 * 1024) return hipErrorInvalidValue;
+    static bool attr_set = false;  // the FP64 tables of four waves exceed the 64 KiB default
+    if (!attr_set) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_stat_wave_multi<C, R, R, 2, RR>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&k_stat_wave_multi<C, R, R, 0, RR>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        attr_set = true;
+    }
+    if (layout == 2)
+        hipLaunchKernelGGL((k_stat_wave_multi<C, R, R, 2, RR>), dim3(n_groups), dim3(64 * block_waves), shmem, st, a);
+    else
+        hipLaunchKernelGGL((k_stat_wave_multi<C, R, R, 0, RR>), dim3(n_groups), dim3(64 * block_waves), shmem, st, a);
+    return hipGetLastError();
+}
+
+// Realisations in launches of `group` (each forms the template work once for its group),
+// then the remainder in the largest smaller groups.
+template <int C, class R>
+static hipError_t launch_multi_t(const StatLaunch &L, StatArgs a, hipStream_t st) {
+    for (int r0 = 0; r0 < L.n_real;) {
+        a.rho0 = r0;
+        const int left = L.n_real - r0;
+        int g = L.multi_group;
+        while (g > left) g >>= 1;
+        hipError_t e;
+        switch (g) {
+            case 8: e = launch_multi_rr<C, R, 8>(a, L.layout, L.n_groups, L.block_waves, st); break;
+            case 4: e = launch_multi_rr<C, R, 4>(a, L.layout, L.n_groups, L.block_waves, st); break;
+            case 2: e = launch_multi_rr<C, R, 2>(a, L.layout, L.n_groups, L.block_waves, st); break;
+            default: e = launch_multi_rr<C, R, 1>(a, L.layout, L.n_groups, L.block_waves, st); g = 1; break;
+        }
+        if (e != hipSuccess) return e;
+        r0 += g;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_statistic_multi(const StatLaunch &L, hipStream_t st) {
+    StatArgs a = make_args(L);
+    if (L.n == 0 || L.n_real == 0) return hipSuccess;
+    const uint64_t tot = (uint64_t)L.real_stride * (uint64_t)L.n_real;
+    a.pix_bytes = tot > 0xffffffffull ? 0xffffffffu : (uint32_t)tot;
+    a.real_stride = (uint32_t)L.real_stride;
+    a.seg_stride = L.seg_stride;
+    if (L.precision == 0) {
+        if (L.pix_dtype != 0) return hipErrorInvalidValue;
+        return L.C == 1 ? launch_multi_t<1, double>(L, a, st) : launch_multi_t<2, double>(L, a, st);
+    }
+    if (L.pix_dtype != 1) return hipErrorInvalidValue;
+    return L.C == 1 ? launch_multi_t<1, float>(L, a, st) : launch_multi_t<2, float>(L, a, st);
 }
 
 hipError_t launch_statistic(const StatLaunch &L, hipStream_t st) {

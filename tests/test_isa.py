@@ -29,7 +29,7 @@ def asm(tmp_path_factory):
 
 def _kernels(asm, prefix):
     """(name, body up to and including its resource comment block) of each kernel whose name starts with prefix."""
-    names = sorted(set(re.findall(r"^(_ZN4tfsc11%s\w+):" % prefix, asm, flags=re.M)))
+    names = sorted(set(re.findall(r"^(_ZN4tfsc%d%s\w+):" % (len(prefix), prefix), asm, flags=re.M)))
     for n in names:
         start = asm.index(n + ":")
         end = asm.index("; ScratchSize:", start)
@@ -61,3 +61,20 @@ def test_wave_kernel_scratch_is_small(asm):
         size = int(re.search(r"; ScratchSize: (\d+)", body).group(1))
         assert size <= 64, (name, size)
     assert n >= 4
+
+
+def test_multi_realisation_kernel_fetch_and_spills(asm):
+    """The several-realisation kernel fetches its work the same way (one atomic per wave), and its FP32
+    instantiations spill only per-chunk state, a few hundred bytes, none inside the realisation loop."""
+    found = 0
+    for name, body in _kernels(asm, "k_stat_wave_multi"):
+        lines = body.splitlines()
+        for i, line in enumerate(lines):
+            if "global_atomic" in line and "_add" in line:
+                found += 1
+                window = "\n".join(lines[max(0, i - 16):i])
+                assert "v_mbcnt" in window, f"{name}: lane-wide atomic at line {i}"
+        if re.match(r"_ZN4tfsc17k_stat_wave_multiILi[12]Ef", name):
+            size = int(re.search(r"; ScratchSize: (\d+)", body).group(1))
+            assert size <= 320, (name, size)
+    assert found >= 4
