@@ -343,6 +343,25 @@ def batching_run(args, tfsc, ti, grid, g, psd_d, mu_d, keep_d, kw):
         top = torch.topk(torch.nan_to_num(stat0, nan=-1.0), 65536).indices
         sub = tfsc.BankTensors(*(getattr(bank, k)[top].contiguous() for k in tfsc.BankTensors.FIELDS))
         store0 = rg.stores[0]
+        # one forward and one VJP on the candidates, each timed with events on the launch stream
+        sseg = tfsc.segment_layout(grid, sub)
+        st = torch.cuda.current_stream()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        fw = tfsc.bank_statistic(grid, store0, sub, sseg, precision="f32", want_zn=True)
+        ones = torch.ones(sub.n, dtype=torch.float64, device=dev)
+        gp = tfsc.statistic_vjp(grid, store0, sub, sseg, fw.seg_zn, g_stat=ones)
+        torch.cuda.synchronize()
+        ev[0].record(st)
+        tfsc.bank_statistic(grid, store0, sub, sseg, precision="f32", want_zn=True, out=fw)
+        ev[1].record(st)
+        tfsc.statistic_vjp(grid, store0, sub, sseg, fw.seg_zn, g_stat=ones, out=gp)
+        ev[2].record(st)
+        torch.cuda.synchronize()
+        f_ms, v_ms = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
+        log(f"follow-up candidates: statistic {f_ms:.1f} ms, VJP {v_ms:.1f} ms for 65536 templates "
+            f"({65536 / v_ms * 1e3 / 1e6:.3f} M templates/s)")
+        rec["vjp"] = {"templates": 65536, "statistic_ms": round(f_ms, 3), "vjp_ms": round(v_ms, 3),
+                      "vjp_templates_per_s": round(65536 / v_ms * 1e3, 1), "arith": "f64"}
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         first, best, _ = tfsc.follow_up(grid, store0, sub, steps=50, lr_scale=0.5, precision="f32")

@@ -441,7 +441,7 @@ struct VjpArgs {
     const int64_t *seg_offset;
     const double *seg_zn, *g_stat, *g_seg;
     double *g_params;
-    int64_t total_waves;
+    uint32_t *counter;  // work counter: each wave takes its next template with one atomic
 };
 
 __device__ __forceinline__ double wave_sum_f64(double v) {
@@ -463,8 +463,11 @@ __global__ __launch_bounds__(256) void k_vjp_wave(VjpArgs a) {
     }
     __syncthreads();
     const int lane = threadIdx.x & 63;
-    const int64_t wave0 = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    for (int64_t i = wave0; i < a.n; i += a.total_waves) {
+    for (;;) {
+        // dynamic work fetch, as in the statistic kernel: one atomic per wave on a uniform address
+        const uint32_t mine = atomicAdd(a.counter, lane == 0 ? 1u : 0u);
+        const int64_t i = (int64_t)__builtin_amdgcn_readfirstlane(mine);
+        if (i >= a.n) break;
         double gr[5] = {0, 0, 0, 0, 0};
         const bool ok = params_valid(a.mc[i], a.eta[i], a.f0[i], a.ct[i], a.ci[i]);
         if (ok) {
@@ -603,6 +606,10 @@ __global__ __launch_bounds__(256) void k_vjp_wave(VjpArgs a) {
     }
 }
 
+__global__ void k_vjp_zero(uint32_t *counter) {
+    if (threadIdx.x == 0) counter[0] = 0u;
+}
+
 template <int C, class PixT>
 static hipError_t launch_vjp_t(const VjpArgs &a, int n_groups, int block_waves, hipStream_t st) {
     const size_t shmem = sizeof(double) * ((size_t)a.K + 2 * kHalfBins);
@@ -653,10 +660,11 @@ hipError_t launch_vjp(const VjpLaunch &V, hipStream_t st) {
     a.g_stat = V.g_stat;
     a.g_seg = V.g_seg;
     a.g_params = V.g_params;
+    a.counter = L.counter;
     const int bw = L.block_waves;
     int64_t groups = (L.n + bw - 1) / bw;
     if (groups > (int64_t)L.n_groups) groups = L.n_groups;
-    a.total_waves = groups * bw;
+    hipLaunchKernelGGL(k_vjp_zero, dim3(1), dim3(64), 0, st, a.counter);
     return L.C == 1 ? dispatch_vjp<1>(a, L.pix_dtype, (int)groups, bw, st)
                     : dispatch_vjp<2>(a, L.pix_dtype, (int)groups, bw, st);
 }

@@ -78,3 +78,27 @@ def test_multi_realisation_kernel_fetch_and_spills(asm):
             size = int(re.search(r"; ScratchSize: (\d+)", body).group(1))
             assert size <= 320, (name, size)
     assert found >= 4
+
+
+@pytest.fixture(scope="module")
+def asm_vjp(tmp_path_factory):
+    if not os.path.exists(HIPCC):
+        pytest.skip("hipcc not available")
+    out = tmp_path_factory.mktemp("isa_vjp") / "vjp.s"
+    src = os.path.join(ROOT, "paper_2510_19047_amd", "csrc", "tfsc_vjp.hip")
+    subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off", "-Xclang",
+                           "-target-feature", "-Xclang", "-packed-fp32-ops", "--cuda-device-only", "-S", src,
+                           "-o", str(out)], stderr=subprocess.DEVNULL)
+    return out.read_text()
+
+
+def test_vjp_kernel_fetch_is_one_atomic_per_wave(asm_vjp):
+    found = 0
+    for name, body in _kernels(asm_vjp, "k_vjp_wave"):
+        lines = body.splitlines()
+        for i, line in enumerate(lines):
+            if "global_atomic" in line:
+                found += 1
+                window = "\n".join(lines[max(0, i - 16):i])
+                assert "v_mbcnt" in window, f"{name}: lane-wide atomic at line {i}"
+    assert found >= 4
