@@ -194,8 +194,10 @@ def main():
     sc, sp = res_c.stat.cpu().numpy(), res_p.stat.cpu().numpy()
     rel_cp = float(np.max(np.abs(sc - sp) / np.maximum(np.abs(sp), 1.0)))
 
-    traffic, traffic_shape = measured_traffic(n, args.chosen_store, args.chosen_layout,
-                                              "bank" if order is None else "f0 bin")
+    traffic, traffic_shape, valu_insts = measured_traffic(n, args.chosen_store, args.chosen_layout,
+                                                          "bank" if order is None else "f0 bin")
+    # vector-ALU issue: a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles; 1,024 SIMDs at 2.4 GHz
+    valu_frac = None if valu_insts is None else valu_insts * 4.0 / (1024 * 2.4e9) / (k_ms / 1e3)
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -228,6 +230,7 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
             "traffic_launch_shape": traffic_shape,
+            "valu_issue_frac": None if valu_frac is None else round(valu_frac, 4),
             "kernel": "k_stat_wave",
             "kernel_ms": round(k_ms, 3),
             "alg_bytes_per_launch": alg_bytes,
@@ -378,7 +381,8 @@ def batching_run(args, tfsc, ti, grid, g, psd_d, mu_d, keep_d, kw):
 
 
 def measured_traffic(n, store, layout, order):
-    """Calibrated bytes beyond L2 per k_stat_wave launch from the committed rocprofv3 counter runs.
+    """Calibrated bytes beyond L2 (and VALU instructions) per k_stat_wave launch from the committed rocprofv3
+    counter runs.
 
     Only valid while the kernel source, the bank, the store, its layout and the processing order are the ones
     that were profiled; otherwise None.  The launch shape the counters were taken with is returned
@@ -388,7 +392,7 @@ def measured_traffic(n, store, layout, order):
     root = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(root, "profiles", "k_stat_wave_traffic.txt")
     if not os.path.exists(path):
-        return None, None
+        return None, None, None
     rec = {}
     with open(path) as fh:
         for line in fh:
@@ -402,7 +406,10 @@ def measured_traffic(n, store, layout, order):
     same = (rec.get("source_sha256") == h.hexdigest() and rec.get("n_templates") == str(n)
             and rec.get("pixel_store") == store and rec.get("pixel_layout", "layer") == layout
             and rec.get("order") == order)
-    return (float(rec["traffic_bytes"]), rec.get("launch_shape")) if same else (None, None)
+    if not same:
+        return None, None, None
+    valu = float(rec["valu_insts"]) if "valu_insts" in rec else None
+    return float(rec["traffic_bytes"]), rec.get("launch_shape"), valu
 
 
 def cpu_baseline(g, x, psd, mu, keep, bank_h, seconds):
