@@ -202,7 +202,8 @@ tfsc_status tfsc_bank_statistic(const tfsc_grid *grid, const tfsc_pixels *pix, c
  * realisation is faster, so this call serves callers that want one launch
  * and one output block for several realisations.  Outputs: stat[r * n + i],
  * seg_terms[r * seg_stride + seg_offset[i] + s] (seg_stride >= the total
- * number of segments, the caller's to guarantee), flags[n] and n_active[n]
+ * number of segments; terms at or beyond seg_stride are not written, so a
+ * short plane loses terms but never overruns), flags[n] and n_active[n]
  * (optional) once.  WAVE schedule; LAYER_MAJOR or LAYER_MAJOR_CI; FP32
  * pixels with FP32 precision or FP64 pixels with FP64 precision, else
  * TFSC_ERR_DTYPE; no seg_zn (the VJP takes one realisation).  Sums are

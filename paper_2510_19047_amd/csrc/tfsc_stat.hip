@@ -999,7 +999,8 @@ __device__ __forceinline__ void close_segments_multi(SegAccMulti &acc, int upto,
                                                      int64_t seg_stride, bool owner, int lane) {
     while (acc.cur < upto) {
         const double v = acc.N > 0.0 ? 2.0 * (acc.zr * acc.zr + acc.zi * acc.zi) / acc.N : 0.0;
-        if (owner) seg_terms[(int64_t)lane * seg_stride + off + acc.cur] = v;
+        // a plane shorter than the segment layout (a caller error) loses terms instead of overrunning
+        if (owner && off + acc.cur < seg_stride) seg_terms[(int64_t)lane * seg_stride + off + acc.cur] = v;
         if (acc.N > 0.0) acc.any = true;
         acc.total += v;
         acc.zr = acc.zi = acc.N = 0.0;
