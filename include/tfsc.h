@@ -33,7 +33,7 @@ typedef enum {
     TFSC_ERR_SHAPE = 2,        /* inconsistent sizes                        */
     TFSC_ERR_DTYPE = 3,        /* unsupported element type / combination    */
     TFSC_ERR_WORKSPACE = 4,    /* workspace missing or too small            */
-    TFSC_ERR_UNSUPPORTED = 5,  /* valid request this build does not handle  */
+    TFSC_ERR_UNSUPPORTED = 5,  /* valid request the library does not handle */
     TFSC_ERR_HIP = 6           /* a HIP runtime call failed                 */
 } tfsc_status;
 

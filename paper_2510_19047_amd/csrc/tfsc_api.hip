@@ -154,7 +154,7 @@ const char *tfsc_status_string(int s) {
         case TFSC_ERR_SHAPE: return "inconsistent or unsupported sizes";
         case TFSC_ERR_DTYPE: return "unsupported element type or precision combination";
         case TFSC_ERR_WORKSPACE: return "workspace missing or too small";
-        case TFSC_ERR_UNSUPPORTED: return "request not supported by this build";
+        case TFSC_ERR_UNSUPPORTED: return "request not supported by the library";
         case TFSC_ERR_HIP: return "HIP runtime error";
     }
     return "unknown status";
