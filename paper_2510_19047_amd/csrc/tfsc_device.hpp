@@ -141,6 +141,7 @@ struct cx {
 };
 template <class R>
 __device__ __forceinline__ cx<R> cmul(cx<R> a, cx<R> b) {
+#pragma clang fp contract(fast)
     return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
 }
 template <class R>
@@ -206,6 +207,7 @@ __device__ inline void sky_init(Sky<R> &S, double ct, double phi, double psi, do
 
 template <class R>
 __device__ __forceinline__ R sinc_of(R x) {
+#pragma clang fp contract(fast)
     // sin(x)/x for 0 <= x <= ~2 pi f L; series near 0 (a select, not a branch: the
     // unselected quotient may be inf or nan at x = 0)
     const R q = sin_rev(x * (R)(1.0 / kTwoPi)) * rcp(x);
