@@ -23,6 +23,10 @@
 #include "tfsc_device.hpp"
 #include "tfsc_kernels.hpp"
 
+// The tangent arithmetic below contracts multiply-adds into FMAs.  The FP64 track that fixes
+// the integer structure (track_step, from tfsc_device.hpp, included above) is not affected.
+#pragma clang fp contract(fast)
+
 namespace tfsc {
 
 // ------------------------------------------------------------------ dual numbers
