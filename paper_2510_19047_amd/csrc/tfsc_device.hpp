@@ -163,9 +163,22 @@ __device__ __forceinline__ cx<float> expi_rev(float r) {
 }
 __device__ __forceinline__ double sin_rev(double r) { return sinpi(2.0 * r); }
 __device__ __forceinline__ float sin_rev(float r) { return __builtin_amdgcn_sinf(r); }
-// sin(2 pi r) with relative (not only absolute) accuracy for small r
+// sin(2 pi r) for |r| <= 1/4 with relative (not only absolute) accuracy for small r.  FP32: the
+// odd Taylor series of sin x through x^13 at x = 2 pi r (|x| <= pi/2, where the first omitted
+// term is below 7e-10 and every partial sum keeps the sign of x); Horner form in x^2.
 __device__ __forceinline__ double sin_rev_accurate(double r) { return sinpi(2.0 * r); }
-__device__ __forceinline__ float sin_rev_accurate(float r) { return sinpif(2.0f * r); }
+__device__ __forceinline__ float sin_rev_accurate(float r) {
+#pragma clang fp contract(fast)
+    const float x = r * (float)kTwoPi;
+    const float x2 = x * x;
+    float p = 1.0f / 6227020800.0f;  // 1/13!
+    p = p * x2 - 1.0f / 39916800.0f;  // 1/11!
+    p = p * x2 + 1.0f / 362880.0f;    // 1/9!
+    p = p * x2 - 1.0f / 5040.0f;      // 1/7!
+    p = p * x2 + 1.0f / 120.0f;       // 1/5!
+    p = p * x2 - 1.0f / 6.0f;         // 1/3!
+    return x + (x * x2) * p;
+}
 __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
@@ -176,33 +189,39 @@ __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x);
 // n_01, n_12, n_20 (from the first spacecraft to the second).
 constexpr int kGeoRows = 18;
 
+// Sky constants of one template.  With the sky basis u = (cos th cos phi, cos th sin phi,
+// -sin th), v = (sin phi, -cos phi, 0) and an arm direction n, the arm's polarisation factor is
+//   a_+ [cos 2psi (n.u^2 - n.v^2) + sin 2psi 2 n.u n.v] - i cos(iota) [-sin 2psi (...) + cos 2psi (...)],
+// a_+ = (1 + cos^2 iota) / 2.  Rotating the basis by psi (u' = cos psi u + sin psi v,
+// v' = -sin psi u + cos psi v) turns the two brackets into n.u'^2 - n.v'^2 and 2 n.u' n.v', and
+// scaling u', v' by sqrt(a_+) leaves  (n.u''^2 - n.v''^2) + i q n.u'' n.v''  with
+// q = -2 cos(iota) / a_+ : the same value with four fewer operations per arm and tranche.
 template <class R>
 struct Sky {
-    R k[3], u[3], v[3];
-    R c2, s2, ap, ci;
+    R k[3], u[3], v[3];  // propagation direction; u'', v'' as above
+    R q;
     double kd[3];
 };
 
 template <class R>
 __device__ inline void sky_init(Sky<R> &S, double ct, double phi, double psi, double ci) {
     double st = sqrt(1.0 - ct * ct);
-    double sp, cp, s2, c2;
+    double sp, cp, ss, cs;
     sincos(phi, &sp, &cp);
-    sincos(2.0 * psi, &s2, &c2);
+    sincos(psi, &ss, &cs);
     S.kd[0] = -st * cp;
     S.kd[1] = -st * sp;
     S.kd[2] = -ct;
     for (int i = 0; i < 3; ++i) S.k[i] = (R)S.kd[i];
-    S.u[0] = (R)(ct * cp);
-    S.u[1] = (R)(ct * sp);
-    S.u[2] = (R)(-st);
-    S.v[0] = (R)sp;
-    S.v[1] = (R)(-cp);
-    S.v[2] = (R)0;
-    S.c2 = (R)c2;
-    S.s2 = (R)s2;
-    S.ap = (R)((1.0 + ci * ci) / 2.0);
-    S.ci = (R)ci;
+    const double ap = (1.0 + ci * ci) / 2.0;
+    const double ra = sqrt(ap);
+    const double u[3] = {ct * cp, ct * sp, -st};
+    const double v[3] = {sp, -cp, 0.0};
+    for (int i = 0; i < 3; ++i) {
+        S.u[i] = (R)(ra * (cs * u[i] + ss * v[i]));
+        S.v[i] = (R)(ra * (cs * v[i] - ss * u[i]));
+    }
+    S.q = (R)(-2.0 * ci / ap);
 }
 
 template <class R>
@@ -261,7 +280,9 @@ __device__ inline void transfer_ae(const Sky<R> &S, const GeoView &gv, int m, do
     for (int i = 0; i < 3; ++i)
         kp[i] = S.kd[0] * geo_d(gv, m, 3 * i) + S.kd[1] * geo_d(gv, m, 3 * i + 1) + S.kd[2] * geo_d(gv, m, 3 * i + 2);
     const R pfL = (R)(kPi * f * L);
-    cx<R> Gd[3], Gr[3];  // arm a: direction (s -> r) and reverse
+    // Arm a, direction (s -> r) and reverse: G = -i pi f L e^{i ph} amp sinc(pi f L (1 -+ k.n));
+    // the common factor -i pi f L is applied once, to T_A and T_E below.
+    cx<R> Gd[3], Gr[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int s = a, r = (a + 1) % 3;
@@ -271,16 +292,12 @@ __device__ inline void transfer_ae(const Sky<R> &S, const GeoView &gv, int m, do
         R kn = S.k[0] * n0 + S.k[1] * n1 + S.k[2] * n2;
         R nu = S.u[0] * n0 + S.u[1] * n1 + S.u[2] * n2;
         R nv = S.v[0] * n0 + S.v[1] * n1 + S.v[2] * n2;
-        R xp0 = nu * nu - nv * nv, xx0 = (R)2 * nu * nv;
-        R xp = S.c2 * xp0 + S.s2 * xx0;
-        R xx = -S.s2 * xp0 + S.c2 * xx0;
-        cx<R> amp = {S.ap * xp, -S.ci * xx};
+        cx<R> amp = {nu * nu - nv * nv, S.q * (nu * nv)};
         double rev = frac_rev(-0.5 * f * (L + (kp[s] + kp[r])));  // -pi f (L + k.(p_s + p_r)) / 2 pi
         cx<R> E = expi_rev((R)rev);
         cx<R> Ea = cmul(E, amp);
-        cx<R> B = {pfL * Ea.im, -pfL * Ea.re};  // -i pi f L e^{i ph} amp
-        Gd[a] = cscale(B, sinc_of(pfL * ((R)1 - kn)));
-        Gr[a] = cscale(B, sinc_of(pfL * ((R)1 + kn)));
+        Gd[a] = cscale(Ea, sinc_of(pfL * ((R)1 - kn)));
+        Gr[a] = cscale(Ea, sinc_of(pfL * ((R)1 + kn)));
     }
     // 0-based spacecraft: arm 0 = (0,1), arm 1 = (1,2), arm 2 = (2,0)
     const cx<R> G01 = Gd[0], G10 = Gr[0], G12 = Gd[1], G21 = Gr[1], G20 = Gd[2], G02 = Gr[2];
@@ -296,9 +313,11 @@ __device__ inline void transfer_ae(const Sky<R> &S, const GeoView &gv, int m, do
     const cx<R> Xp = cadd(csub(G20, G10), cmul(D, csub(G02, G01)));
     const cx<R> Yp = cadd(csub(G01, G21), cmul(D, csub(G10, G12)));
     const cx<R> Zp = cadd(csub(G12, G02), cmul(D, csub(G21, G20)));
+    // (1 - D^2)(-i pi f L) = 2 sin(2 pi f L) pi f L D, times 1/sqrt2 (A) or 1/sqrt6 (E)
     const R is2 = (R)0.70710678118654752440, is6 = (R)0.40824829046386301637;
-    const cx<R> oma = {(R)-2 * is2 * s2 * D.im, (R)2 * is2 * s2 * D.re};
-    const cx<R> ome = {(R)-2 * is6 * s2 * D.im, (R)2 * is6 * s2 * D.re};
+    const R sp = (R)2 * s2 * pfL;
+    const cx<R> oma = cscale(D, sp * is2);
+    const cx<R> ome = cscale(D, sp * is6);
     TA = cmul(oma, csub(Zp, Xp));
     TE = cmul(ome, cadd(csub(Xp, cscale(Yp, (R)2)), Zp));
 }

@@ -781,10 +781,7 @@ __device__ __forceinline__ void wave_uniform(Sky<R> &S) {
         S.v[q] = wave_uniform(S.v[q]);
         S.kd[q] = wave_uniform(S.kd[q]);
     }
-    S.c2 = wave_uniform(S.c2);
-    S.s2 = wave_uniform(S.s2);
-    S.ap = wave_uniform(S.ap);
-    S.ci = wave_uniform(S.ci);
+    S.q = wave_uniform(S.q);
 }
 
 template <int C, class R, class PixT, int LAYOUT>
