@@ -43,11 +43,14 @@ def _bins(f_m: torch.Tensor, dT: float, M: int):
 
 
 def template_pixels(mc, eta, f0, cos_theta, phi, psi, cos_iota, m_end: int, grid, u, wm,
-                    exact_fresnel: bool = False):
+                    exact_fresnel: bool = False, weight_tf=None):
     """Whitened template pixels of one template on its active tranches.
 
     Parameters may be 0-d tensors carrying autograd.  Returns (m, kc, k, valid, Y)
     with Y[C, n_m, 21] complex (zero on invalid bins and excluded tranches).
+    weight_tf: optional per-pixel weights [K][Nt] (1/sqrt(S_m(f_k)), 0 on excluded
+    tranches) for a PSD that varies between tranches in a general way; u and wm
+    are then not used.
     """
     dT = float(grid.tranche_dur)
     M = grid.tranche_len
@@ -60,9 +63,14 @@ def template_pixels(mc, eta, f0, cos_theta, phi, psi, cos_iota, m_end: int, grid
     h = tranche_spectrum(Phi[:, None], f[:, None], fdot[:, None], A[:, None], fk, dT, exact=exact_fresnel)
     TA, TE = transfer_ae(tm, f, cos_theta, phi, psi, cos_iota)
     T = [TA, TE][: grid.n_channels]
-    uk = torch.as_tensor(np.asarray(u), dtype=torch.float64)[k.clamp(0, M // 2)]
-    w = torch.as_tensor(np.asarray(wm), dtype=torch.float64)[m]
-    weight = torch.where(valid, uk, torch.zeros_like(uk)) * w[:, None]
+    if weight_tf is not None:
+        wt = torch.as_tensor(np.asarray(weight_tf), dtype=torch.float64)
+        wkm = wt[k.clamp(0, M // 2), m[:, None]]
+        weight = torch.where(valid, wkm, torch.zeros_like(wkm))
+    else:
+        uk = torch.as_tensor(np.asarray(u), dtype=torch.float64)[k.clamp(0, M // 2)]
+        w = torch.as_tensor(np.asarray(wm), dtype=torch.float64)[m]
+        weight = torch.where(valid, uk, torch.zeros_like(uk)) * w[:, None]
     Y = torch.stack([Tc[:, None] * h * weight for Tc in T], dim=0)
     return m, kc, k, valid, Y
 
@@ -99,12 +107,16 @@ class Result:
 
 
 def statistic(pix, u, wm, bank, grid, layout: trk.Layout | None = None, exact_fresnel: bool = False,
-              idx=None) -> Result:
+              idx=None, weight_tf=None) -> Result:
     """Upsilon and its per-segment terms for every template of ``bank``.
 
     pix: complex [C][K][Nt] whitened data pixels (numpy), u: [K], wm: [Nt].
     idx: optional subset of template indices (others are left at zero).
+    weight_tf: optional per-pixel template weights [K][Nt] in place of u_k w_m
+    (``transform.transform_tf``); u and wm must then be None.
     """
+    if weight_tf is not None and (u is not None or wm is not None):
+        raise ValueError("give either (u, wm) or weight_tf")
     if layout is None:
         layout = trk.Layout(bank, grid)
     res = Result(layout.n, layout.seg_offset)
@@ -119,7 +131,7 @@ def statistic(pix, u, wm, bank, grid, layout: trk.Layout | None = None, exact_fr
                 continue
             m, kc, k, valid, Y = template_pixels(
                 bank.mc[i], bank.eta[i], bank.f0[i], bank.cos_theta[i], bank.phi[i], bank.psi[i],
-                bank.cos_iota[i], layout.m_end[i], grid, u, wm, exact_fresnel)
+                bank.cos_iota[i], layout.m_end[i], grid, u, wm, exact_fresnel, weight_tf)
             z, N = _segment_sums(pix_t, m, k, valid, Y, layout.nseg[i], grid.n_tranches)
             ups = _upsilon(z, N)
             o = layout.seg_offset[i]

@@ -17,6 +17,10 @@ Readings fixed here:
   excluded).  DC and Nyquist are never used by the statistic.
 * Layout of the pixel store: [C][K][Nt] complex, K = M/2 + 1 (tranches
   contiguous within a frequency layer).
+* A PSD that varies between tranches in a general way (not mu_m S0(f)) is
+  given as S[K, Nt] = S_m(f_k); the pixels are whitened by it pixel by pixel,
+  D_mk = X_mk sqrt(2 dt / (M W2 S_m(f_k))), and the template weight of pixel
+  (m, k) is keep_m / sqrt(S_m(f_k)) (``transform_tf``).
 """
 from __future__ import annotations
 
@@ -78,3 +82,29 @@ def transform(x: np.ndarray, grid, psd0: np.ndarray, mu: np.ndarray, keep: np.nd
     for c in range(x.shape[0]):
         pix[c] = tranche_dft(x[c], M, alpha, method) * scale
     return pix, u, wm
+
+
+def whitening_tf(M: int, dt: float, alpha: float, psd_tf: np.ndarray, keep: np.ndarray):
+    """(scale[K, Nt], weight[K, Nt]) for a PSD S_m(f_k) given pixel by pixel (psd_tf[K, Nt])."""
+    w = tukey(M, alpha)
+    W2 = float(np.mean(w * w))
+    keep = np.asarray(keep, dtype=np.float64)
+    S = np.asarray(psd_tf, dtype=np.float64)
+    if S.shape != (M // 2 + 1, keep.shape[0]):
+        raise ValueError("psd_tf must be [M/2 + 1, Nt]")
+    scale = np.sqrt(2.0 * dt / (M * W2 * S)) * keep[None, :]
+    weight = np.where(keep[None, :] > 0, 1.0 / np.sqrt(S), 0.0)
+    return scale, weight
+
+
+def transform_tf(x: np.ndarray, grid, psd_tf: np.ndarray, keep: np.ndarray, alpha: float = 0.1,
+                 method: str = "direct"):
+    """Pixels [C][K][Nt] complex128 plus the per-pixel template weights [K][Nt] for a PSD that differs
+    from tranche to tranche in a general way (psd_tf[K, Nt] = S_m(f_k))."""
+    M = grid.tranche_len
+    x = np.atleast_2d(x)
+    scale, weight = whitening_tf(M, grid.dt, alpha, psd_tf, keep)
+    pix = np.empty((x.shape[0], M // 2 + 1, grid.n_tranches), dtype=np.complex128)
+    for c in range(x.shape[0]):
+        pix[c] = tranche_dft(x[c], M, alpha, method) * scale
+    return pix, weight

@@ -147,6 +147,19 @@ def tranche_psd_scale(grid: GridSpec) -> np.ndarray:
     return modulation(tm)
 
 
+def tranche_psd_tf(grid: GridSpec, tilt: float = 0.3, period_s: float = 0.5 * YEAR_S) -> np.ndarray:
+    """A locally stationary PSD that is not separable in time and frequency, S[K, Nt] = S_m(f_k):
+    mu_m S0_k times a spectral tilt that drifts with time, (f_k / 10 mHz)^(gamma_m) with
+    gamma_m = tilt sin(2 pi t_m / period + 0.7) at the middle of each tranche (bin 0 uses bin 1's
+    frequency).  Like a confusion-noise foreground whose shape changes over the orbit."""
+    S0 = psd_on_bins(grid)
+    mu = tranche_psd_scale(grid)
+    tm = (np.arange(grid.n_tranches) + 0.5) * grid.tranche_dur
+    gamma = tilt * np.sin(2.0 * np.pi * tm / period_s + 0.7)
+    fk = np.maximum(np.arange(grid.n_bins, dtype=np.float64), 1.0) / grid.tranche_dur
+    return S0[:, None] * mu[None, :] * np.power(fk[:, None] / 0.01, gamma[None, :])
+
+
 def gap_intervals(grid: GridSpec):
     """List of (start, stop) seconds of the scheduled 7-h gaps (every 14 d from day 7)."""
     if not grid.gapped:
