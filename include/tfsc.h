@@ -25,7 +25,7 @@
 extern "C" {
 #endif
 
-#define TFSC_ABI_VERSION 1
+#define TFSC_ABI_VERSION 2
 
 typedef enum {
     TFSC_OK = 0,
@@ -66,7 +66,18 @@ typedef struct {
  * inv_asd[K] = u_k = 1/sqrt(S0(f_k)) and tranche_w[Nt] = w_m = 1/sqrt(mu_m)
  * (0 = tranche excluded, e.g. it overlaps a data gap).  The template pixel of
  * channel c is T_c(t_m, f_m) h_m(f_k) u_k w_m (paper Eqs. (tdi2),
- * (inner-tranche-tf)).  tfsc_transform writes all five arrays.             */
+ * (inner-tranche-tf)).  tfsc_transform writes these five arrays.
+ *
+ * rho: NULL for a PSD separable as S_m(f_k) = mu_m S0(f_k).  For a PSD that
+ * varies between tranches in a general way (paper Sec. "Search extension to
+ * data with gaps": a time-frequency PSD per tranche, for locally stationary
+ * noise), rho[K][Nt] FP32 (bin-major, tranches contiguous; device memory,
+ * owned by the caller) holds rho_mk = sqrt(mu_m S0(f_k) / S_m(f_k)) and the
+ * template pixel becomes T_c h_m(f_k) u_k w_m rho_mk; tfsc_transform_tf
+ * writes it.  Read by tfsc_bank_statistic (THREAD schedule: every pixel
+ * type; WAVE schedule: F64 or F32 pixels with the same arithmetic, or F32
+ * pixels with F64 arithmetic); tfsc_bank_statistic_multi and
+ * tfsc_statistic_vjp return TFSC_ERR_UNSUPPORTED when it is set.            */
 typedef struct {
     tfsc_dtype dtype;
     tfsc_layout layout;
@@ -74,6 +85,7 @@ typedef struct {
     float *layer_scale;
     double *inv_asd;
     double *tranche_w;
+    float *rho;
 } tfsc_pixels;
 
 /* Template bank, structure of arrays, n templates, FP64:
@@ -159,6 +171,19 @@ size_t tfsc_workspace_bytes(const tfsc_grid *grid, int64_t n_templates, const tf
 tfsc_status tfsc_transform(const tfsc_grid *grid, const void *x, int x_dtype, const double *psd0,
                            const double *tranche_psd_scale, const uint8_t *tranche_keep, tfsc_pixels *out,
                            void *ws, size_t ws_bytes, void *stream);
+
+/* tfsc_transform for a PSD that varies between tranches in a general way
+ * (paper Sec. "Search extension to data with gaps"): psd_tf[K][Nt] FP64
+ * (device, bin-major, tranches contiguous) = S_m(f_k), positive and finite
+ * for 1 <= k <= M/2 - 1.  The pixels are whitened pixel by pixel,
+ * D_cmk = X_cmk sqrt(2 dt / (M W2 S_m(f_k))) (0 on excluded tranches), and
+ * the template weights are written as u_k = 1/sqrt(S0_k) with S0_k the mean
+ * of S_m(f_k) over the tranches, w_m = 1 (0 = excluded) and
+ * rho_mk = sqrt(S0_k / S_m(f_k)) into out->rho, which must be set.  Same
+ * dtypes, layouts and workspace as tfsc_transform.                         */
+tfsc_status tfsc_transform_tf(const tfsc_grid *grid, const void *x, int x_dtype, const double *psd_tf,
+                              const uint8_t *tranche_keep, tfsc_pixels *out, void *ws, size_t ws_bytes,
+                              void *stream);
 
 /* Per-template setup (paper Sec. "Methods": N_seg = tau / T_seg; here set
  * per template from fdot at t = 0, or fixed).  Writes seg->nseg and

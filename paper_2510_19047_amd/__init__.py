@@ -15,7 +15,7 @@ import torch
 from . import _lib
 from ._lib import TfscError
 
-__all__ = ["GridSpec", "PixelStore", "BankTensors", "SegmentLayout", "StatResult", "transform", "segment_layout",
+__all__ = ["GridSpec", "PixelStore", "BankTensors", "SegmentLayout", "StatResult", "transform", "transform_tf", "segment_layout",
            "bank_statistic", "bank_statistic_multi", "realisation_stores", "MultiResult", "statistic_vjp", "track",
            "tile_max", "TFSCStatistic", "lib", "TfscError"]
 
@@ -74,10 +74,11 @@ class PixelStore:
     dtype: str = "f32"
     layout: str = "layer"
     layer_scale: torch.Tensor | None = None  # [C][K] f32 for 16-bit stores
+    rho: torch.Tensor | None = None   # [K][Nt] f32 per-pixel weight factor of a general per-tranche PSD
 
     def c(self) -> _lib.Pixels:
         return _lib.Pixels(_DTYPE[self.dtype], _LAYOUT[self.layout], _ptr(self.pix), _ptr(self.layer_scale),
-                           _ptr(self.inv_asd), _ptr(self.tranche_w))
+                           _ptr(self.inv_asd), _ptr(self.tranche_w), _ptr(self.rho))
 
     @staticmethod
     def from_complex(pix: torch.Tensor, inv_asd: torch.Tensor, tranche_w: torch.Tensor, dtype: str = "f64",
@@ -166,6 +167,37 @@ def transform(grid: GridSpec, x: torch.Tensor, psd0: torch.Tensor, mu: torch.Ten
     st = L.tfsc_transform(ctypes.byref(g), _ptr(x), xd, _ptr(psd0), _ptr(mu), _ptr(keep), ctypes.byref(pc),
                           _ptr(ws), nb if ws is not None else 0, _stream())
     _lib.check(st, "tfsc_transform")
+    return out
+
+
+def transform_tf(grid: GridSpec, x: torch.Tensor, psd_tf: torch.Tensor, keep: torch.Tensor, dtype: str = "f32",
+                 layout: str = "layer", out: PixelStore | None = None) -> PixelStore:
+    """tfsc_transform_tf: time series [C][N] -> pixel store whitened by a PSD given per (bin, tranche),
+    psd_tf[K][Nt] = S_m(f_k) (f64, device); the store carries the per-pixel weight factor ``rho``."""
+    L = lib()
+    dev = x.device
+    K, Nt, C = grid.n_bins, grid.n_tranches, grid.n_channels
+    if tuple(psd_tf.shape) != (K, Nt) or psd_tf.dtype != torch.float64 or not psd_tf.is_contiguous():
+        raise TfscError(f"psd_tf must be a contiguous float64 [{K}, {Nt}] tensor")
+    if out is None:
+        if layout not in _LAYOUT:
+            raise TfscError(f"unknown pixel layout {layout!r}")
+        shape = {"layer": (C, K, Nt, 2), "tranche": (C, Nt, K, 2), "layer_ci": (K, Nt, C, 2)}[layout]
+        out = PixelStore(torch.empty(shape, dtype=_TORCH_STORE[dtype], device=dev),
+                         torch.empty(K, dtype=torch.float64, device=dev), torch.empty(Nt, dtype=torch.float64, device=dev),
+                         dtype, layout,
+                         torch.empty((C, K), dtype=torch.float32, device=dev) if dtype in ("bf16", "f16") else None,
+                         torch.empty((K, Nt), dtype=torch.float32, device=dev))
+    elif out.rho is None:
+        raise TfscError("transform_tf needs a store with a rho tensor")
+    g = grid.c()
+    xd = _lib.F64 if x.dtype == torch.float64 else _lib.F32
+    nb = L.tfsc_workspace_bytes(ctypes.byref(g), 0, None, _lib.WS_TRANSFORM)
+    ws = _ws(nb, dev) if dtype in ("bf16", "f16") else None
+    pc = out.c()
+    st = L.tfsc_transform_tf(ctypes.byref(g), _ptr(x), xd, _ptr(psd_tf), _ptr(keep), ctypes.byref(pc), _ptr(ws),
+                             nb if ws is not None else 0, _stream())
+    _lib.check(st, "tfsc_transform_tf")
     return out
 
 

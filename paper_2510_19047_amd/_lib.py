@@ -24,7 +24,7 @@ class Grid(ctypes.Structure):
 
 class Pixels(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int), ("layout", ctypes.c_int), ("pix", c_void_p), ("layer_scale", c_void_p),
-                ("inv_asd", c_void_p), ("tranche_w", c_void_p)]
+                ("inv_asd", c_void_p), ("tranche_w", c_void_p), ("rho", c_void_p)]
 
 
 class Bank(ctypes.Structure):
@@ -41,7 +41,7 @@ class Options(ctypes.Structure):
                 ("order", c_void_p)]
 
 
-EXPORTS = ("tfsc_abi_version", "tfsc_status_string", "tfsc_workspace_bytes", "tfsc_transform",
+EXPORTS = ("tfsc_abi_version", "tfsc_status_string", "tfsc_workspace_bytes", "tfsc_transform", "tfsc_transform_tf",
            "tfsc_segment_layout", "tfsc_bank_statistic", "tfsc_bank_statistic_multi", "tfsc_statistic_vjp",
            "tfsc_follow_up_step",
            "tfsc_processing_order", "tfsc_tile_max", "tfsc_track")
@@ -71,6 +71,9 @@ def load(path: str = LIB_PATH):
     L.tfsc_transform.restype = ctypes.c_int
     L.tfsc_transform.argtypes = [P(Grid), c_void_p, ctypes.c_int, c_void_p, c_void_p, c_void_p, P(Pixels),
                                  c_void_p, c_size_t, c_void_p]
+    L.tfsc_transform_tf.restype = ctypes.c_int
+    L.tfsc_transform_tf.argtypes = [P(Grid), c_void_p, ctypes.c_int, c_void_p, c_void_p, P(Pixels), c_void_p,
+                                    c_size_t, c_void_p]
     L.tfsc_segment_layout.restype = ctypes.c_int
     L.tfsc_segment_layout.argtypes = [P(Grid), P(Bank), P(Segments), c_void_p, c_size_t, c_void_p]
     L.tfsc_bank_statistic.restype = ctypes.c_int

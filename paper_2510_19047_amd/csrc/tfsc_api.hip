@@ -123,6 +123,7 @@ tfsc::StatLaunch stat_launch(const tfsc_grid *grid, const tfsc_pixels *pix, cons
     L.layer_scale = pix->layer_scale;
     L.inv_asd = pix->inv_asd;
     L.tranche_w = pix->tranche_w;
+    L.rho = pix->rho;
     L.geo = reinterpret_cast<const double *>(ws);
     L.n = bank->n;
     L.mc = bank->mc;
@@ -202,6 +203,8 @@ tfsc_status tfsc_bank_statistic(const tfsc_grid *grid, const tfsc_pixels *pix, c
     if (bank->n > 0 && (!seg_terms || !stat || !flags)) return TFSC_ERR_ARG;
     if (!ws || ws_bytes < ws_bytes_for(grid, bank->n, TFSC_WS_STATISTIC)) return TFSC_ERR_WORKSPACE;
     if (r.schedule == TFSC_SCHED_WAVE && pixel_store_bytes(grid, pix) > 0xffffffffull) return TFSC_ERR_UNSUPPORTED;
+    if (pix->rho && r.schedule == TFSC_SCHED_WAVE && pix->dtype != TFSC_F64 && pix->dtype != TFSC_F32)
+        return TFSC_ERR_UNSUPPORTED;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (bank->n == 0) return TFSC_OK;
     hipError_t e = tfsc::launch_geometry(grid->n_tranches, (double)grid->tranche_len * grid->dt,
@@ -232,7 +235,7 @@ tfsc_status tfsc_bank_statistic_multi(const tfsc_grid *grid, const tfsc_pixels *
     if (group != 0 && group != 1 && group != 2 && group != 4 && group != 8) return TFSC_ERR_ARG;
     Resolved r;
     if ((s = resolve_options(opt, pix, r)) != TFSC_OK) return s;
-    if (r.schedule != TFSC_SCHED_WAVE || pix->layout == TFSC_TRANCHE_MAJOR) return TFSC_ERR_UNSUPPORTED;
+    if (r.schedule != TFSC_SCHED_WAVE || pix->layout == TFSC_TRANCHE_MAJOR || pix->rho) return TFSC_ERR_UNSUPPORTED;
     if (!(pix->dtype == TFSC_F32 && r.precision == TFSC_F32) && !(pix->dtype == TFSC_F64 && r.precision == TFSC_F64))
         return TFSC_ERR_DTYPE;
     const uint64_t one = pixel_store_bytes(grid, pix);
@@ -272,6 +275,7 @@ tfsc_status tfsc_statistic_vjp(const tfsc_grid *grid, const tfsc_pixels *pix, co
     // from the options.
     Resolved r;
     if ((s = resolve_options(opt, nullptr, r)) != TFSC_OK) return s;
+    if (pix->rho) return TFSC_ERR_UNSUPPORTED;
     if (bank->n > 0 && (!seg_zn || !g_params || (!g_stat && !g_seg))) return TFSC_ERR_ARG;
     if (!ws || ws_bytes < ws_bytes_for(grid, bank->n, TFSC_WS_VJP)) return TFSC_ERR_WORKSPACE;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -377,6 +381,43 @@ tfsc_status tfsc_transform(const tfsc_grid *grid, const void *x, int x_dtype, co
     L.layer_scale = out->layer_scale;
     L.inv_asd = out->inv_asd;
     L.tranche_w = out->tranche_w;
+    L.psd_tf = nullptr;
+    L.rho = nullptr;
+    L.ws = ws;
+    return hip_status(tfsc::launch_transform(L, reinterpret_cast<hipStream_t>(stream)));
+}
+
+tfsc_status tfsc_transform_tf(const tfsc_grid *grid, const void *x, int x_dtype, const double *psd_tf,
+                              const uint8_t *tranche_keep, tfsc_pixels *out, void *ws, size_t ws_bytes,
+                              void *stream) {
+    tfsc_status s;
+    if ((s = check_grid(grid)) != TFSC_OK) return s;
+    if ((s = check_pixels(out, true)) != TFSC_OK) return s;
+    if (!x || !psd_tf || !tranche_keep || !out->rho) return TFSC_ERR_ARG;
+    if (x_dtype != TFSC_F64 && x_dtype != TFSC_F32) return TFSC_ERR_DTYPE;
+    if (out->dtype == TFSC_F64 && x_dtype != TFSC_F64) return TFSC_ERR_DTYPE;
+    if (out->dtype == TFSC_F64 && grid->tranche_len > 2048) return TFSC_ERR_UNSUPPORTED;
+    const bool q16 = out->dtype == TFSC_BF16 || out->dtype == TFSC_F16;
+    if (q16 && (!ws || ws_bytes < ws_bytes_for(grid, 0, TFSC_WS_TRANSFORM))) return TFSC_ERR_WORKSPACE;
+    tfsc::TransformLaunch L;
+    L.M = grid->tranche_len;
+    L.Nt = grid->n_tranches;
+    L.C = grid->n_channels;
+    L.dt = grid->dt;
+    L.alpha = grid->tukey_alpha;
+    L.x = x;
+    L.x_dtype = x_dtype;
+    L.psd0 = nullptr;
+    L.mu = nullptr;
+    L.psd_tf = psd_tf;
+    L.keep = tranche_keep;
+    L.out_dtype = out->dtype;
+    L.out_layout = out->layout;
+    L.pix = out->pix;
+    L.layer_scale = out->layer_scale;
+    L.inv_asd = out->inv_asd;
+    L.tranche_w = out->tranche_w;
+    L.rho = out->rho;
     L.ws = ws;
     return hip_status(tfsc::launch_transform(L, reinterpret_cast<hipStream_t>(stream)));
 }

@@ -38,6 +38,7 @@ struct StatLaunch {
     const void *pix;
     const float *layer_scale;
     const double *inv_asd, *tranche_w, *geo;
+    const float *rho;       // [K][Nt] per-pixel weight factor, NULL for a separable PSD
     const double *u_scale;  // device scalar written by launch_weight_scale
     int64_t n;
     const double *mc, *eta, *f0, *ct, *phi, *psi, *ci;
@@ -93,11 +94,13 @@ struct TransformLaunch {
     const void *x;
     int x_dtype;
     const double *psd0, *mu;
+    const double *psd_tf;  // [K][Nt] S_m(f_k) for a general per-pixel PSD (then psd0, mu unused), else NULL
     const uint8_t *keep;
     int out_dtype, out_layout;
     void *pix;
     float *layer_scale;
     double *inv_asd, *tranche_w;
+    float *rho;  // written when psd_tf is set
     void *ws;  // FP32 staging for 16-bit outputs
 };
 

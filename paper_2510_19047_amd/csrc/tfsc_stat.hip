@@ -233,6 +233,8 @@ struct StatArgs {
     const double *geo;
     const float *geo32;
     const double *u_scale;  // [1], see k_weight_scale
+    const float *rho;       // [K][Nt] per-pixel weight factor (general per-tranche PSD), else NULL
+    uint32_t rho_bytes;
     int64_t n;
     const double *mc, *eta, *f0, *ct, *phi, *psi, *ci;
     const int32_t *nseg;
@@ -307,7 +309,7 @@ struct SegWalk {
 };
 
 // Sum over the 21 bins of tranche m: P_c = sum conj(D_ck) h_k u_k, Q = sum |h_k u_k|^2.
-template <int C, class R, class PixT, int LAYOUT, class U>
+template <int C, class R, class PixT, int LAYOUT, class U, bool RHO>
 __device__ __forceinline__ void tranche_bins(const StatArgs &a, const TrancheSpec<R> &ts, int kc, int m,
                                              const U *__restrict__ u_tab, U u_mul, const float *__restrict__ sc_tab,
                                              cx<R> (&P)[C], R &Q) {
@@ -321,7 +323,9 @@ __device__ __forceinline__ void tranche_bins(const StatArgs &a, const TrancheSpe
     for (int j = -kHalfBins; j <= kHalfBins; ++j) {
         int k = kc + j;
         if (k < 1 || k > kmax) continue;
-        const cx<R> g = tranche_bin_weighted(ts, j, (R)(u_tab[k] * u_mul));
+        R wk = (R)(u_tab[k] * u_mul);
+        if constexpr (RHO) wk *= (R)a.rho[(size_t)k * a.Nt + m];
+        const cx<R> g = tranche_bin_weighted(ts, j, wk);
         Q += g.re * g.re;
         Q += g.im * g.im;
 #pragma unroll
@@ -363,7 +367,7 @@ __device__ __forceinline__ void tranche_combine(const Sky<R> &S, const GeoView &
 }
 
 // ------------------------------------------------------------------ THREAD schedule
-template <int C, class R, class PixT, int LAYOUT>
+template <int C, class R, class PixT, int LAYOUT, bool RHO>
 __global__ __launch_bounds__(256) void k_stat_thread(StatArgs a) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= a.n) return;
@@ -404,7 +408,7 @@ __global__ __launch_bounds__(256) void k_stat_thread(StatArgs a) {
         int kc = tranche_setup(ts, Phi, f, fdot, a.dT);
         cx<R> P[C];
         R Q;
-        tranche_bins<C, R, PixT, LAYOUT, double>(a, ts, kc, m, a.inv_asd, u_mul, a.layer_scale, P, Q);
+        tranche_bins<C, R, PixT, LAYOUT, double, RHO>(a, ts, kc, m, a.inv_asd, u_mul, a.layer_scale, P, Q);
         R zr, zi, nn;
         tranche_combine<C, R>(S, gv, m, f, (R)wmd, P, Q, zr, zi, nn);
         acc.zr += zr;
@@ -684,17 +688,18 @@ __device__ __forceinline__ void bin_accumulate(const TrancheSpec<R> &ts, int j, 
 // read lies in the store; a lane with kc < 10 would need a row below 0, and a wave holding
 // such a lane takes wave_tranche_bins_low instead.  The exact Fresnel form is used only for
 // the bins [jA, jB] where some lane of the wave may need it (a wave-uniform choice).
-template <int C, class R, class PixT, int LAYOUT>
+template <int C, class R, class PixT, int LAYOUT, bool RHO>
 __device__ __forceinline__ void wave_tranche_bins(const TrancheSpec<R> &ts, int kc, int m, int Nt, int K,
-                                                  __amdgpu_buffer_rsrc_t rsrc, const R *__restrict__ u_pad,
-                                                  const float *__restrict__ sc_pad, int jA, int jB, cx<R> (&P)[C],
-                                                  R &Q) {
+                                                  __amdgpu_buffer_rsrc_t rsrc, __amdgpu_buffer_rsrc_t rho_rsrc,
+                                                  const R *__restrict__ u_pad, const float *__restrict__ sc_pad,
+                                                  int jA, int jB, cx<R> (&P)[C], R &Q) {
     constexpr uint32_t B = sizeof(PixT) == 8 ? 16u : (sizeof(PixT) == 4 ? 8u : 4u);
     constexpr uint32_t BP = LAYOUT == 2 ? (uint32_t)C * B : B;  // bytes per (bin, tranche) cell
     constexpr int NB = 2 * kHalfBins + 1, G = 3;
     static_assert(NB % G == 0, "bin groups must tile the window");
     const uint32_t voff = (uint32_t)((kc - kHalfBins) * Nt + m) * BP;
     const uint32_t row = (uint32_t)Nt * BP, chan = (uint32_t)K * row;
+    const uint32_t voff_rho = (uint32_t)((kc - kHalfBins) * Nt + m) * 4u, row_rho = (uint32_t)Nt * 4u;
     const int KP = K + 2 * kHalfBins;
     const R *uk = u_pad + kc;  // uk[jj] = u_pad[kc + jj] = u_{kc + jj - 10}
     const float *sk = sc_pad + kc;
@@ -703,12 +708,20 @@ __device__ __forceinline__ void wave_tranche_bins(const TrancheSpec<R> &ts, int 
 #pragma unroll
     for (int j0 = 0; j0 < NB; j0 += G) {
         cx<typename PixTraits<PixT>::R> Dl[G][C];
+        float rh[G];
 #pragma unroll
-        for (int u = 0; u < G; ++u) bin_pixels<C, PixT, LAYOUT>(rsrc, voff, (uint32_t)(j0 + u) * row, chan, Dl[u]);
+        for (int u = 0; u < G; ++u) {
+            bin_pixels<C, PixT, LAYOUT>(rsrc, voff, (uint32_t)(j0 + u) * row, chan, Dl[u]);
+            if constexpr (RHO)
+                rh[u] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                      rho_rsrc, voff_rho, (uint32_t)(j0 + u) * row_rho, 0));
+        }
 #pragma unroll
         for (int u = 0; u < G; ++u) {
             const int j = j0 + u - kHalfBins;
-            bin_accumulate<C, R, PixT>(ts, j, ts.x - (R)j, uk[j0 + u], jA, jB, Dl[u], sk + j0 + u, KP, acc);
+            R w = uk[j0 + u];
+            if constexpr (RHO) w *= (R)rh[u];
+            bin_accumulate<C, R, PixT>(ts, j, ts.x - (R)j, w, jA, jB, Dl[u], sk + j0 + u, KP, acc);
         }
     }
     acc.finish(ts, P, Q);
@@ -717,11 +730,11 @@ __device__ __forceinline__ void wave_tranche_bins(const TrancheSpec<R> &ts, int 
 // As wave_tranche_bins for a wave with some lane below bin 10: each bin's row is a per-lane
 // offset, clamped at row 0 (rows below 0 have weight 0, so the clamped load adds nothing).
 // Same arithmetic in the same order, so a lane's result does not depend on its wave.
-template <int C, class R, class PixT, int LAYOUT>
+template <int C, class R, class PixT, int LAYOUT, bool RHO>
 __device__ __forceinline__ void wave_tranche_bins_low(const TrancheSpec<R> &ts, int kc, int m, int Nt, int K,
-                                                   __amdgpu_buffer_rsrc_t rsrc, const R *__restrict__ u_pad,
-                                                   const float *__restrict__ sc_pad, int jA, int jB, cx<R> (&P)[C],
-                                                   R &Q) {
+                                                   __amdgpu_buffer_rsrc_t rsrc, __amdgpu_buffer_rsrc_t rho_rsrc,
+                                                   const R *__restrict__ u_pad, const float *__restrict__ sc_pad,
+                                                   int jA, int jB, cx<R> (&P)[C], R &Q) {
     constexpr uint32_t B = sizeof(PixT) == 8 ? 16u : (sizeof(PixT) == 4 ? 8u : 4u);
     constexpr uint32_t BP = LAYOUT == 2 ? (uint32_t)C * B : B;
     const uint32_t chan = (uint32_t)K * (uint32_t)Nt * BP;
@@ -736,7 +749,10 @@ __device__ __forceinline__ void wave_tranche_bins_low(const TrancheSpec<R> &ts, 
         const int k = max(kc + j, 0);
         cx<typename PixTraits<PixT>::R> Dl[C];
         bin_pixels<C, PixT, LAYOUT>(rsrc, (uint32_t)(k * Nt + m) * BP, 0u, chan, Dl);
-        bin_accumulate<C, R, PixT>(ts, j, ts.x - (R)j, uk[jj], jA, jB, Dl, sk + jj, KP, acc);
+        R w = uk[jj];
+        if constexpr (RHO)
+            w *= (R)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rho_rsrc, (uint32_t)(k * Nt + m) * 4u, 0u, 0));
+        bin_accumulate<C, R, PixT>(ts, j, ts.x - (R)j, w, jA, jB, Dl, sk + jj, KP, acc);
     }
     acc.finish(ts, P, Q);
 }
@@ -784,7 +800,7 @@ __device__ __forceinline__ void wave_uniform(Sky<R> &S) {
     S.q = wave_uniform(S.q);
 }
 
-template <int C, class R, class PixT, int LAYOUT>
+template <int C, class R, class PixT, int LAYOUT, bool RHO>
 __global__ __launch_bounds__(256, 4) void k_stat_wave(StatArgs a) {
     // Zero-padded template weights u_pad[k + 10] = u_k for 1 <= k <= M/2 - 1 (else 0), and
     // the 16-bit layer scales, staged in LDS once per block.
@@ -805,6 +821,7 @@ __global__ __launch_bounds__(256, 4) void k_stat_wave(StatArgs a) {
         }
     __syncthreads();
     const __amdgpu_buffer_rsrc_t rsrc = pix_rsrc(a.pix, a.pix_bytes);
+    const __amdgpu_buffer_rsrc_t rho_rsrc = pix_rsrc(RHO ? a.rho : a.pix, RHO ? a.rho_bytes : 0u);
     const GeoView gv = geo_view(a.geo, a.geo32, a.Nt);
 
     const int lane = threadIdx.x & 63;
@@ -877,9 +894,11 @@ __global__ __launch_bounds__(256, 4) void k_stat_wave(StatArgs a) {
                 cx<R> P[C];
                 R Q;
                 if (low)
-                    wave_tranche_bins_low<C, R, PixT, LAYOUT>(ts, kc, m, a.Nt, a.K, rsrc, u_pad, sc_pad, jA, jB, P, Q);
+                    wave_tranche_bins_low<C, R, PixT, LAYOUT, RHO>(ts, kc, m, a.Nt, a.K, rsrc, rho_rsrc, u_pad, sc_pad,
+                                                                   jA, jB, P, Q);
                 else
-                    wave_tranche_bins<C, R, PixT, LAYOUT>(ts, kc, m, a.Nt, a.K, rsrc, u_pad, sc_pad, jA, jB, P, Q);
+                    wave_tranche_bins<C, R, PixT, LAYOUT, RHO>(ts, kc, m, a.Nt, a.K, rsrc, rho_rsrc, u_pad, sc_pad,
+                                                               jA, jB, P, Q);
                 tranche_combine<C, R>(S, gv, m, f, (R)wmd, P, Q, zr, zi, nn);
             }
             // segmented reduction over the lanes of this chunk
@@ -1230,6 +1249,11 @@ static StatArgs make_args(const StatLaunch &L) {
     a.geo = L.geo;
     a.geo32 = geo32_of(L.geo, L.Nt);
     a.u_scale = L.u_scale;
+    a.rho = L.rho;
+    {
+        const uint64_t rb = (uint64_t)a.K * (uint64_t)a.Nt * 4u;
+        a.rho_bytes = L.rho ? (rb > 0xffffffffull ? 0xffffffffu : (uint32_t)rb) : 0u;
+    }
     a.n = L.n;
     a.mc = L.mc;
     a.eta = L.eta;
@@ -1256,12 +1280,21 @@ static StatArgs make_args(const StatLaunch &L) {
 template <int C, class R, class PixT>
 static hipError_t launch_thread_t(const StatArgs &a, int layout, hipStream_t st) {
     dim3 grid((unsigned)((a.n + 255) / 256)), block(256);
+    if (a.rho) {
+        if (layout == 0)
+            hipLaunchKernelGGL((k_stat_thread<C, R, PixT, 0, true>), grid, block, 0, st, a);
+        else if (layout == 1)
+            hipLaunchKernelGGL((k_stat_thread<C, R, PixT, 1, true>), grid, block, 0, st, a);
+        else
+            hipLaunchKernelGGL((k_stat_thread<C, R, PixT, 2, true>), grid, block, 0, st, a);
+        return hipGetLastError();
+    }
     if (layout == 0)
-        hipLaunchKernelGGL((k_stat_thread<C, R, PixT, 0>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((k_stat_thread<C, R, PixT, 0, false>), grid, block, 0, st, a);
     else if (layout == 1)
-        hipLaunchKernelGGL((k_stat_thread<C, R, PixT, 1>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((k_stat_thread<C, R, PixT, 1, false>), grid, block, 0, st, a);
     else
-        hipLaunchKernelGGL((k_stat_thread<C, R, PixT, 2>), grid, block, 0, st, a);
+        hipLaunchKernelGGL((k_stat_thread<C, R, PixT, 2, false>), grid, block, 0, st, a);
     return hipGetLastError();
 }
 
@@ -1270,10 +1303,23 @@ static hipError_t launch_wave_t(const StatArgs &a, int layout, int n_groups, int
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, a.counter, 1);
     const size_t KP = (size_t)a.K + 2 * kHalfBins;
     size_t shmem = sizeof(R) * KP + (PixTraits<PixT>::scaled ? sizeof(float) * C * KP : 0);
+    if constexpr (!PixTraits<PixT>::scaled) {
+        if (a.rho) {
+            if (layout == 2)
+                hipLaunchKernelGGL((k_stat_wave<C, R, PixT, 2, true>), dim3(n_groups), dim3(64 * block_waves), shmem,
+                                   st, a);
+            else
+                hipLaunchKernelGGL((k_stat_wave<C, R, PixT, 0, true>), dim3(n_groups), dim3(64 * block_waves), shmem,
+                                   st, a);
+            return hipGetLastError();
+        }
+    } else {
+        if (a.rho) return hipErrorInvalidValue;
+    }
     if (layout == 2)
-        hipLaunchKernelGGL((k_stat_wave<C, R, PixT, 2>), dim3(n_groups), dim3(64 * block_waves), shmem, st, a);
+        hipLaunchKernelGGL((k_stat_wave<C, R, PixT, 2, false>), dim3(n_groups), dim3(64 * block_waves), shmem, st, a);
     else
-        hipLaunchKernelGGL((k_stat_wave<C, R, PixT, 0>), dim3(n_groups), dim3(64 * block_waves), shmem, st, a);
+        hipLaunchKernelGGL((k_stat_wave<C, R, PixT, 0, false>), dim3(n_groups), dim3(64 * block_waves), shmem, st, a);
     return hipGetLastError();
 }
 

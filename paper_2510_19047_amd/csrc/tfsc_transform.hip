@@ -78,9 +78,10 @@ __global__ __launch_bounds__(256) void k_transform(TransformLaunch L, double w2)
             dst = t;
         }
         const bool keep = L.keep[m] != 0;
-        const double mu = L.mu[m];
+        const double mu = L.psd_tf ? 1.0 : L.mu[m];
         for (int k = threadIdx.x; k < K; k += blockDim.x) {
-            double sc = keep ? sqrt(2.0 * L.dt / ((double)M * w2 * L.psd0[k] * mu)) : 0.0;
+            const double S = L.psd_tf ? L.psd_tf[(size_t)k * Nt + m] : L.psd0[k] * mu;
+            double sc = keep ? sqrt(2.0 * L.dt / ((double)M * w2 * S)) : 0.0;
             tile[(size_t)k * TB + tt] = cscale(src[k], (R)sc);
         }
         __syncthreads();
@@ -158,6 +159,30 @@ __global__ void k_weights(int K, int Nt, const double *__restrict__ psd0, const 
     if (i < Nt) tw[i] = keep[i] ? 1.0 / sqrt(mu[i]) : 0.0;
 }
 
+// Template weights for a per-pixel PSD S_m(f_k) (psd[K][Nt]): one block per bin k forms
+// S0_k = mean over the tranches of S_m(f_k) (fixed-order partial sums, then a fixed tree),
+// u_k = 1/sqrt(S0_k) and rho_mk = sqrt(S0_k / S_m(f_k)); block 0 also writes w_m = keep_m.
+__global__ __launch_bounds__(256) void k_weights_tf(int K, int Nt, const double *__restrict__ psd,
+                                                   const uint8_t *__restrict__ keep, double *__restrict__ inv_asd,
+                                                   double *__restrict__ tw, float *__restrict__ rho) {
+    __shared__ double part[256];
+    const int k = blockIdx.x;
+    const double *row = psd + (size_t)k * Nt;
+    double s = 0.0;
+    for (int m = threadIdx.x; m < Nt; m += blockDim.x) s += row[m];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    const double S0 = part[0] / (double)Nt;
+    if (threadIdx.x == 0) inv_asd[k] = 1.0 / sqrt(S0);
+    for (int m = threadIdx.x; m < Nt; m += blockDim.x) rho[(size_t)k * Nt + m] = (float)sqrt(S0 / row[m]);
+    if (k == 0)
+        for (int m = threadIdx.x; m < Nt; m += blockDim.x) tw[m] = keep[m] ? 1.0 : 0.0;
+}
+
 static double window_w2(int M, double alpha) {
     // mean of w^2 of the symmetric Tukey window (host side, FP64)
     if (alpha <= 0.0) return 1.0;
@@ -190,8 +215,12 @@ hipError_t launch_transform(const TransformLaunch &L, hipStream_t st) {
     const int K = L.M / 2 + 1;
     const double w2 = window_w2(L.M, L.alpha);
     int nw = K > L.Nt ? K : L.Nt;
-    hipLaunchKernelGGL(k_weights, dim3((nw + 255) / 256), dim3(256), 0, st, K, L.Nt, L.psd0, L.mu, L.keep,
-                       L.inv_asd, L.tranche_w);
+    if (L.psd_tf)
+        hipLaunchKernelGGL(k_weights_tf, dim3(K), dim3(256), 0, st, K, L.Nt, L.psd_tf, L.keep, L.inv_asd,
+                           L.tranche_w, L.rho);
+    else
+        hipLaunchKernelGGL(k_weights, dim3((nw + 255) / 256), dim3(256), 0, st, K, L.Nt, L.psd0, L.mu, L.keep,
+                           L.inv_asd, L.tranche_w);
     const bool q16 = L.out_dtype == 2 || L.out_dtype == 3;
     TransformLaunch Lw = L;
     hipError_t e;

@@ -31,7 +31,7 @@ def test_every_declared_function_is_exported(L):
 
 
 def test_version_and_status_strings(L):
-    assert L.tfsc_abi_version() == 1
+    assert L.tfsc_abi_version() == 2
     for s in range(7):
         assert len(L.tfsc_status_string(s)) > 0
 

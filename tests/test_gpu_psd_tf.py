@@ -1,0 +1,150 @@
+"""A PSD that varies between tranches in a general way (tfsc_transform_tf, the rho factor of tfsc_pixels)
+through the C ABI, against the oracle's per-pixel whitening and weights."""
+import numpy as np
+import pytest
+import torch
+
+import tfsc_inputs as ti
+from oracle import o2
+from oracle import track as otrk
+from oracle import transform as otf
+
+from gpu_common import dev, gridspec, lib, note, rel, small_data
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle(d, S, x=None):
+    g = d["grid"]
+    b = d["bank"]
+    pix, wt = otf.transform_tf(d["x"] if x is None else x, g, S, d["keep"], 0.1, "rfft")
+    res = o2.statistic(pix, None, None, b, g, layout=otrk.Layout(b, g), weight_tf=wt)
+    return pix, wt, res
+
+
+def test_transform_tf_matches_the_oracle():
+    """Pixels whitened pixel by pixel (FP64 store, both layer-major layouts) and the weights u_k w_m rho_mk
+    against the oracle's keep_m / sqrt(S_m(f_k)); rho is FP32, so the weights agree to FP32 rounding."""
+    tfsc = lib()
+    d = small_data()
+    g = d["grid"]
+    S = ti.tranche_psd_tf(g)
+    note(f"transform_tf: grid {g.n_bins}x{g.n_tranches}, C={g.n_channels}")
+    pix, wt = otf.transform_tf(d["x"], g, S, d["keep"], 0.1, "rfft")
+    for layout in ("layer", "layer_ci"):
+        st = tfsc.transform_tf(gridspec(g), dev(d["x"]), dev(S), dev(d["keep"]), dtype="f64", layout=layout)
+        p = torch.view_as_complex(st.pix).cpu().numpy()
+        p = p if layout == "layer" else np.transpose(p, (2, 0, 1))
+        scale = np.abs(pix).max()
+        assert np.max(np.abs(p - pix)) < 1e-12 * scale, layout
+        w = (st.inv_asd.cpu().numpy()[:, None] * st.tranche_w.cpu().numpy()[None, :]
+             * st.rho.cpu().numpy().astype(np.float64))
+        inner = slice(1, g.n_bins - 1)
+        err = np.abs(w[inner] - wt[inner]) / np.abs(wt[inner]).max(axis=None)
+        assert err.max() < 2e-7, layout
+        assert np.array_equal(st.tranche_w.cpu().numpy() == 0, wt[1] == 0)
+
+
+@pytest.mark.parametrize("schedule,layout", [("wave", "layer_ci"), ("wave", "layer"), ("thread", "tranche")])
+def test_statistic_fp64_against_the_oracle(schedule, layout):
+    """FP64 pixels and arithmetic with the drifting-tilt PSD: Upsilon, segment terms and flags."""
+    tfsc = lib()
+    d = small_data()
+    g = d["grid"]
+    S = ti.tranche_psd_tf(g)
+    note(f"psd_tf statistic f64 {schedule} {layout}")
+    _, _, ref = _oracle(d, S)
+    st = tfsc.transform_tf(gridspec(g), dev(d["x"]), dev(S), dev(d["keep"]), dtype="f64", layout=layout)
+    bt = tfsc.BankTensors.from_host(d["bank"])
+    seg = tfsc.segment_layout(gridspec(g), bt)
+    res = tfsc.bank_statistic(gridspec(g), st, bt, seg, precision="f64", schedule=schedule)
+    r = rel(res.stat.cpu().numpy(), ref.stat)
+    stt = res.seg_terms[:seg.total].cpu().numpy()
+    note(f"  max rel {r.max():.2e}")
+    assert r.max() < 1e-6
+    assert np.max(np.abs(stt - ref.seg_terms) / np.maximum(ref.seg_terms, 1.0)) < 1e-6
+    assert np.array_equal(res.flags.cpu().numpy(), ref.flags)
+
+
+def test_statistic_fp32_chosen_form_and_ranking():
+    """The chosen form (FP32 channel-interleaved store, wave schedule) with the per-pixel PSD: within 1e-4
+    of the oracle (given the same FP32-rounded data) and the same best template."""
+    tfsc = lib()
+    d = small_data()
+    g = d["grid"]
+    S = ti.tranche_psd_tf(g)
+    note("psd_tf statistic f32 wave layer_ci")
+    _, _, ref = _oracle(d, S, d["x"].astype(np.float32).astype(np.float64))
+    st = tfsc.transform_tf(gridspec(g), dev(d["x"].astype(np.float32)), dev(S), dev(d["keep"]), dtype="f32",
+                           layout="layer_ci")
+    bt = tfsc.BankTensors.from_host(d["bank"])
+    seg = tfsc.segment_layout(gridspec(g), bt)
+    res = tfsc.bank_statistic(gridspec(g), st, bt, seg, precision="f32", schedule="wave")
+    s = res.stat.cpu().numpy()
+    r = rel(s, ref.stat)
+    note(f"  max rel {r.max():.2e}")
+    assert r.max() < 1e-4
+    assert int(np.argmax(s)) == int(np.argmax(ref.stat))
+    # a different PSD gives a different statistic (the weights are used)
+    sep = tfsc.transform(gridspec(g), dev(d["x"].astype(np.float32)), dev(d["psd"]), dev(d["mu"]), dev(d["keep"]),
+                         dtype="f32", layout="layer_ci")
+    other = tfsc.bank_statistic(gridspec(g), sep, bt, seg, precision="f32", schedule="wave").stat.cpu().numpy()
+    assert np.max(np.abs(other - s) / np.maximum(np.abs(s), 1.0)) > 1e-3
+
+
+@pytest.mark.parametrize("schedule,layout,prec,dtype", [("wave", "layer_ci", "f32", "f32"),
+                                                        ("wave", "layer", "f64", "f64"),
+                                                        ("wave", "layer_ci", "f64", "f32"),
+                                                        ("thread", "tranche", "f32", "f32")])
+def test_unit_rho_is_bit_identical_to_the_separable_path(schedule, layout, prec, dtype):
+    """rho = 1 multiplies every weight by 1: the same bits as the store without rho."""
+    tfsc = lib()
+    d = small_data()
+    g = d["grid"]
+    note(f"unit rho {schedule} {layout} {prec}/{dtype}")
+    xx = d["x"] if dtype == "f64" else d["x"].astype(np.float32)
+    st = tfsc.transform(gridspec(g), dev(xx), dev(d["psd"]), dev(d["mu"]), dev(d["keep"]), dtype=dtype, layout=layout)
+    bt = tfsc.BankTensors.from_host(d["bank"])
+    seg = tfsc.segment_layout(gridspec(g), bt)
+    a = tfsc.bank_statistic(gridspec(g), st, bt, seg, precision=prec, schedule=schedule, want_active=True)
+    st1 = tfsc.PixelStore(st.pix, st.inv_asd, st.tranche_w, st.dtype, st.layout, st.layer_scale,
+                          torch.ones((g.n_bins, g.n_tranches), dtype=torch.float32, device="cuda"))
+    b = tfsc.bank_statistic(gridspec(g), st1, bt, seg, precision=prec, schedule=schedule, want_active=True)
+    assert torch.equal(a.stat, b.stat)
+    assert torch.equal(a.seg_terms, b.seg_terms)
+    assert torch.equal(a.flags, b.flags) and torch.equal(a.n_active, b.n_active)
+
+
+def test_rho_is_refused_where_it_is_not_supported():
+    tfsc = lib()
+    d = small_data()
+    g = d["grid"]
+    S = ti.tranche_psd_tf(g)
+    bt = tfsc.BankTensors.from_host(d["bank"])
+    seg = tfsc.segment_layout(gridspec(g), bt)
+    st = tfsc.transform_tf(gridspec(g), dev(d["x"].astype(np.float32)), dev(S), dev(d["keep"]), dtype="f32",
+                           layout="layer_ci")
+    stores = tfsc.realisation_stores(gridspec(g), 2, dtype="f32", layout="layer_ci")
+    for r in range(2):
+        stores[r].pix.copy_(st.pix)
+    stores[0].inv_asd.copy_(st.inv_asd)
+    stores[0].tranche_w.copy_(st.tranche_w)
+    tfsc.bank_statistic_multi(gridspec(g), stores, bt, seg, precision="f32")  # accepted without rho
+    stores[0].rho = st.rho
+    with pytest.raises(tfsc.TfscError):  # several realisations with rho
+        tfsc.bank_statistic_multi(gridspec(g), stores, bt, seg, precision="f32")
+    fw = tfsc.bank_statistic(gridspec(g), st, bt, seg, precision="f32", want_zn=True)
+    with pytest.raises(tfsc.TfscError):  # VJP
+        tfsc.statistic_vjp(gridspec(g), st, bt, seg, fw.seg_zn,
+                           g_stat=torch.ones(bt.n, dtype=torch.float64, device="cuda"))
+    h = tfsc.transform_tf(gridspec(g), dev(d["x"].astype(np.float32)), dev(S), dev(d["keep"]), dtype="f16",
+                          layout="layer_ci")
+    with pytest.raises(tfsc.TfscError):  # 16-bit store on the wave schedule
+        tfsc.bank_statistic(gridspec(g), h, bt, seg, precision="f32", schedule="wave")
+    # the thread schedule takes 16-bit stores with rho: within the F16 store's bar of the oracle
+    _, _, ref = _oracle(d, S, d["x"].astype(np.float32).astype(np.float64))
+    ht = tfsc.transform_tf(gridspec(g), dev(d["x"].astype(np.float32)), dev(S), dev(d["keep"]), dtype="f16",
+                           layout="tranche")
+    s = tfsc.bank_statistic(gridspec(g), ht, bt, seg, precision="f32", schedule="thread").stat.cpu().numpy()
+    assert rel(s, ref.stat).max() < 2e-3
+    assert int(np.argmax(s)) == int(np.argmax(ref.stat))
