@@ -76,8 +76,8 @@ typedef struct {
  * template pixel becomes T_c h_m(f_k) u_k w_m rho_mk; tfsc_transform_tf
  * writes it.  Read by tfsc_bank_statistic (THREAD schedule: every pixel
  * type; WAVE schedule: F64 or F32 pixels with the same arithmetic, or F32
- * pixels with F64 arithmetic); tfsc_bank_statistic_multi and
- * tfsc_statistic_vjp return TFSC_ERR_UNSUPPORTED when it is set.            */
+ * pixels with F64 arithmetic) and by tfsc_statistic_vjp (every pixel type);
+ * tfsc_bank_statistic_multi returns TFSC_ERR_UNSUPPORTED when it is set.    */
 typedef struct {
     tfsc_dtype dtype;
     tfsc_layout layout;

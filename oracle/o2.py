@@ -144,7 +144,7 @@ def statistic(pix, u, wm, bank, grid, layout: trk.Layout | None = None, exact_fr
     return res
 
 
-def gradient(pix, u, wm, bank, grid, i: int, g_seg=None, layout: trk.Layout | None = None):
+def gradient(pix, u, wm, bank, grid, i: int, g_seg=None, layout: trk.Layout | None = None, weight_tf=None):
     """d(sum_n g_n Upsilon_n)/d(ln Mc, f0, cos theta, phi, psi) for template i (float64 autograd).
 
     g_seg defaults to all ones (the gradient of Upsilon).  The integer
@@ -168,7 +168,7 @@ def gradient(pix, u, wm, bank, grid, i: int, g_seg=None, layout: trk.Layout | No
     mc = torch.tensor(float(bank.mc[i]), dtype=torch.float64) * torch.exp(ln_mc - ln_mc.detach())
     m, kc, k, valid, Y = template_pixels(mc, torch.tensor(float(bank.eta[i]), dtype=torch.float64), f0,
                                          ct, ph, ps, torch.tensor(float(bank.cos_iota[i]), dtype=torch.float64),
-                                         layout.m_end[li], grid, u, wm)
+                                         layout.m_end[li], grid, u, wm, weight_tf=weight_tf)
     z, N = _segment_sums(pix_t, m, k, valid, Y, layout.nseg[li], grid.n_tranches)
     ups = _upsilon(z, N)
     g = torch.ones_like(ups) if g_seg is None else torch.as_tensor(np.asarray(g_seg), dtype=torch.float64)

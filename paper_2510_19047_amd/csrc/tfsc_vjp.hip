@@ -439,6 +439,7 @@ struct VjpArgs {
     int layout;  // 0 layer-major, 1 tranche-major, 2 layer-major with interleaved channels
     const float *layer_scale;
     const double *inv_asd, *tranche_w, *geo, *u_scale;
+    const float *rho;  // [K][Nt] per-pixel weight factor (general per-tranche PSD), else NULL
     int64_t n;
     const double *mc, *eta, *f0, *ct, *phi, *psi, *ci;
     const int32_t *nseg;
@@ -528,7 +529,8 @@ __global__ __launch_bounds__(256) void k_vjp_wave(VjpArgs a) {
                         for (int j = -kHalfBins; j <= kHalfBins; ++j) {
                             const int k = kc + j;
                             if (k < 1 || k > kmax) continue;
-                            const double u = u_pad[k + kHalfBins];
+                            double u = u_pad[k + kHalfBins];
+                            if (a.rho) u *= (double)a.rho[(size_t)k * a.Nt + m];
                             CDn<2> H = bin_dual(sp, j);
                             H = cdscale(H, u);
                             const double hr = H.re.v, hi = H.im.v;
@@ -650,6 +652,7 @@ hipError_t launch_vjp(const VjpLaunch &V, hipStream_t st) {
     a.tranche_w = L.tranche_w;
     a.geo = L.geo;
     a.u_scale = L.u_scale;
+    a.rho = L.rho;
     a.n = L.n;
     a.mc = L.mc;
     a.eta = L.eta;

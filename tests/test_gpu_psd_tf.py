@@ -9,7 +9,7 @@ from oracle import o2
 from oracle import track as otrk
 from oracle import transform as otf
 
-from gpu_common import dev, gridspec, lib, note, rel, small_data
+from gpu_common import dev, gridspec, lib, note, rel, small_data, tiny_data
 
 pytestmark = pytest.mark.gpu
 
@@ -133,10 +133,6 @@ def test_rho_is_refused_where_it_is_not_supported():
     stores[0].rho = st.rho
     with pytest.raises(tfsc.TfscError):  # several realisations with rho
         tfsc.bank_statistic_multi(gridspec(g), stores, bt, seg, precision="f32")
-    fw = tfsc.bank_statistic(gridspec(g), st, bt, seg, precision="f32", want_zn=True)
-    with pytest.raises(tfsc.TfscError):  # VJP
-        tfsc.statistic_vjp(gridspec(g), st, bt, seg, fw.seg_zn,
-                           g_stat=torch.ones(bt.n, dtype=torch.float64, device="cuda"))
     h = tfsc.transform_tf(gridspec(g), dev(d["x"].astype(np.float32)), dev(S), dev(d["keep"]), dtype="f16",
                           layout="layer_ci")
     with pytest.raises(tfsc.TfscError):  # 16-bit store on the wave schedule
@@ -148,3 +144,68 @@ def test_rho_is_refused_where_it_is_not_supported():
     s = tfsc.bank_statistic(gridspec(g), ht, bt, seg, precision="f32", schedule="thread").stat.cpu().numpy()
     assert rel(s, ref.stat).max() < 2e-3
     assert int(np.argmax(s)) == int(np.argmax(ref.stat))
+
+
+def test_vjp_with_rho_against_oracle_autograd():
+    """The FP64 VJP reads rho like the statistic: against float64 autograd of the oracle with per-pixel weights
+    (the same bars as the separable case), and rho = 1 gives the separable VJP bit for bit."""
+    tfsc = lib()
+    d = small_data()
+    g = d["grid"]
+    b = d["bank"]
+    S = ti.tranche_psd_tf(g)
+    lay = otrk.Layout(b, g)
+    ok = np.nonzero((lay.flags & (otrk.FLAG_INVALID | otrk.FLAG_EMPTY)) == 0)[0]
+    idx = np.concatenate([ok[:5], ok[-3:]])
+    note(f"vjp with rho, templates {idx.tolist()}")
+    pix, wt = otf.transform_tf(d["x"], g, S, d["keep"], 0.1, "rfft")
+    st = tfsc.transform_tf(gridspec(g), dev(d["x"]), dev(S), dev(d["keep"]), dtype="f64", layout="layer_ci")
+    bt = tfsc.BankTensors.from_host(b)
+    seg = tfsc.segment_layout(gridspec(g), bt)
+    fw = tfsc.bank_statistic(gridspec(g), st, bt, seg, precision="f64", want_zn=True)
+    ones = torch.ones(bt.n, dtype=torch.float64, device="cuda")
+    gp = tfsc.statistic_vjp(gridspec(g), st, bt, seg, fw.seg_zn, g_stat=ones).cpu().numpy()
+    ref = np.zeros((len(idx), 5))
+    for r, i in enumerate(idx):
+        ref[r], _ = o2.gradient(pix, None, None, b, g, int(i), layout=lay, weight_tf=wt)
+    floor = 1e-3 * np.max(np.abs(ref), axis=0, keepdims=True)
+    err = np.abs(gp[idx] - ref) / np.maximum(np.abs(ref), floor)
+    note(f"  max rel vs oracle autograd {err.max():.2e}")
+    assert err.max() < 2e-5
+    # rho = 1 against no rho, FP32 pixels
+    sep = tfsc.transform(gridspec(g), dev(d["x"].astype(np.float32)), dev(d["psd"]), dev(d["mu"]), dev(d["keep"]),
+                         dtype="f32", layout="layer_ci")
+    one = tfsc.PixelStore(sep.pix, sep.inv_asd, sep.tranche_w, sep.dtype, sep.layout, None,
+                          torch.ones((g.n_bins, g.n_tranches), dtype=torch.float32, device="cuda"))
+    f1 = tfsc.bank_statistic(gridspec(g), sep, bt, seg, precision="f32", want_zn=True)
+    a = tfsc.statistic_vjp(gridspec(g), sep, bt, seg, f1.seg_zn, g_stat=ones)
+    c = tfsc.statistic_vjp(gridspec(g), one, bt, seg, f1.seg_zn, g_stat=ones)
+    assert torch.equal(a, c)
+
+
+def test_follow_up_with_a_per_pixel_psd():
+    """The Adam follow-up (statistic + VJP + step) on a store whitened by the per-pixel PSD climbs towards the
+    tiny injection, as with the separable PSD."""
+    tfsc = lib()
+    d = tiny_data()
+    g = d["grid"]
+    inj = ti.TINY_INJECTION
+    S = ti.tranche_psd_tf(g)
+    note("follow-up with rho on the tiny injection")
+    st = tfsc.transform_tf(gridspec(g), dev(d["x"]), dev(S), dev(d["keep"]), dtype="f64", layout="layer_ci")
+    rng = np.random.default_rng(11)
+    n = 16
+    b = ti.Bank(mc=inj["mc"] * np.exp(rng.uniform(-2, 2, n) * 1.4e-3), eta=np.full(n, 0.25),
+                f0=inj["f0"] + rng.uniform(-2, 2, n) * 2.5e-7, cos_theta=np.full(n, inj["cos_theta"]) + 0.05,
+                phi=np.full(n, inj["phi"]) - 0.05, psi=np.full(n, inj["psi"]),
+                cos_iota=np.full(n, inj["cos_iota"]), phase=np.zeros(n))
+    bt = tfsc.BankTensors.from_host(b)
+    first, best, _ = tfsc.follow_up(gridspec(g), st, bt, steps=30, lr_scale=0.5, nseg_fixed=8, precision="f64")
+    first, best = first.cpu().numpy(), best.cpu().numpy()
+    one = ti.tiny_bank().subset([256])
+    exact = tfsc.bank_statistic(gridspec(g), st, tfsc.BankTensors.from_host(one),
+                                tfsc.segment_layout(gridspec(g), tfsc.BankTensors.from_host(one), nseg_fixed=8),
+                                precision="f64").stat.item()
+    note(f"  exact {exact:.1f}; start median {np.median(first):.1f}; best median {np.median(best):.1f}")
+    assert np.all(best >= first)
+    assert np.median(best) > 0.9 * exact
