@@ -10,7 +10,7 @@ definitions directly:
 1. the template's strain (TaylorT3 phase, amplitude f^(2/3), polarisation
    amplitudes (1 + cos^2 iota)/2 and cos iota) is evaluated at every
    delayed time each single link needs, and TDI A/E are formed sample by
-   sample (``oracle.response.tdi_ae_td``) -- no Taylor expansion, no
+   sample (``oracle.response.tdi_aet_td``) -- no Taylor expansion, no
    Fresnel forms, no per-tranche transfer function;
 2. every tranche of the template and of the data is transformed by the
    direct DFT of ``oracle.transform``; template pixels are weighted by
@@ -30,7 +30,7 @@ import numpy as np
 import torch
 
 from . import track as trk
-from .response import tdi_ae_td
+from .response import tdi_aet_td
 from .transform import tranche_dft
 
 
@@ -68,10 +68,12 @@ def synthesize(bank, i: int, grid, analytic: bool = False, t_stop: float | None 
     for s in range(0, N, chunk):
         e = min(N, s + chunk)
         t = torch.arange(s, e, dtype=torch.float64) * grid.dt
-        A, E = tdi_ae_td(t, hfun, bank.cos_theta[i], bank.phi[i], bank.psi[i])
+        A, E, T = tdi_aet_td(t, hfun, bank.cos_theta[i], bank.phi[i], bank.psi[i])
         out[0, s:e] = A.numpy()
         if grid.n_channels > 1:
             out[1, s:e] = E.numpy()
+        if grid.n_channels > 2:
+            out[2, s:e] = T.numpy()
     return out
 
 

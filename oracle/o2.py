@@ -27,7 +27,7 @@ import torch
 
 from . import track as trk
 from .fresnel import tranche_spectrum
-from .response import transfer_ae
+from .response import transfer_aet
 
 NF_HALF = 10
 PARAM_NAMES = ("ln_mc", "f0", "cos_theta", "phi", "psi")
@@ -61,8 +61,7 @@ def template_pixels(mc, eta, f0, cos_theta, phi, psi, cos_iota, m_end: int, grid
     kc, k, valid = _bins(f, dT, M)
     fk = k.to(torch.float64) / dT
     h = tranche_spectrum(Phi[:, None], f[:, None], fdot[:, None], A[:, None], fk, dT, exact=exact_fresnel)
-    TA, TE = transfer_ae(tm, f, cos_theta, phi, psi, cos_iota)
-    T = [TA, TE][: grid.n_channels]
+    T = list(transfer_aet(tm, f, cos_theta, phi, psi, cos_iota))[: grid.n_channels]
     if weight_tf is not None:
         wt = torch.as_tensor(np.asarray(weight_tf), dtype=torch.float64)
         wkm = wt[k.clamp(0, M // 2), m[:, None]]

@@ -98,6 +98,22 @@ def transfer_ae(t, f, cos_theta, phi, psi, cos_iota):
     cos_theta, phi, psi, cos_iota are 0-d tensors (one template); t and f share
     a shape.
     """
+    TA, TE, _ = transfer_aet(t, f, cos_theta, phi, psi, cos_iota)
+    return TA, TE
+
+
+def transfer_aet(t, f, cos_theta, phi, psi, cos_iota):
+    """(T_A, T_E, T_T): the third channel T = (X + Y + Z) / sqrt 3 completes A and E to an orthonormal
+    combination of X, Y, Z (so |T_A|^2 + |T_E|^2 + |T_T|^2 = |T_X|^2 + |T_Y|^2 + |T_Z|^2)."""
+    TX, TY, TZ = transfer_xyz(t, f, cos_theta, phi, psi, cos_iota)
+    TA = (TZ - TX) / math.sqrt(2.0)
+    TE = (TX - 2.0 * TY + TZ) / math.sqrt(6.0)
+    TT = (TX + TY + TZ) / math.sqrt(3.0)
+    return TA, TE, TT
+
+
+def transfer_xyz(t, f, cos_theta, phi, psi, cos_iota):
+    """Per-tranche transfer of the Michelson combinations (T_X, T_Y, T_Z) that A, E and T are formed from."""
     t = t if torch.is_tensor(t) else torch.as_tensor(t, dtype=torch.float64)
     f = f if torch.is_tensor(f) else torch.as_tensor(f, dtype=torch.float64)
     ci = cos_iota if torch.is_tensor(cos_iota) else torch.as_tensor(cos_iota, dtype=torch.float64)
@@ -122,9 +138,7 @@ def transfer_ae(t, f, cos_theta, phi, psi, cos_iota):
     TX = one_m_d2 * ((g(3, 1) + D * g(1, 3)) - (g(2, 1) + D * g(1, 2)))
     TY = one_m_d2 * ((g(1, 2) + D * g(2, 1)) - (g(3, 2) + D * g(2, 3)))
     TZ = one_m_d2 * ((g(2, 3) + D * g(3, 2)) - (g(1, 3) + D * g(3, 1)))
-    TA = (TZ - TX) / math.sqrt(2.0)
-    TE = (TX - 2.0 * TY + TZ) / math.sqrt(6.0)
-    return TA, TE
+    return TX, TY, TZ
 
 
 def link_td(t, hfun, s, r, k, ep, ex):
@@ -143,6 +157,12 @@ def link_td(t, hfun, s, r, k, ep, ex):
 
 def tdi_ae_td(t, hfun, cos_theta, phi, psi):
     """TDI A and E time series at sample times t for strain callback hfun."""
+    A, E, _ = tdi_aet_td(t, hfun, cos_theta, phi, psi)
+    return A, E
+
+
+def tdi_aet_td(t, hfun, cos_theta, phi, psi):
+    """TDI A, E and T = (X + Y + Z) / sqrt 3 time series at sample times t."""
     k, ep, ex = sky_frame(cos_theta, phi, psi)
     L = L_S
 
@@ -157,4 +177,5 @@ def tdi_ae_td(t, hfun, cos_theta, phi, psi):
         - (y(2, 3, 2) + y(3, 2, 3)) + (y(1, 3, 2) + y(3, 1, 3))
     A = (Z - X) / math.sqrt(2.0)
     E = (X - 2.0 * Y + Z) / math.sqrt(6.0)
-    return A, E
+    T = (X + Y + Z) / math.sqrt(3.0)
+    return A, E, T
