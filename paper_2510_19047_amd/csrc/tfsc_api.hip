@@ -27,7 +27,7 @@ bool pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 tfsc_status check_grid(const tfsc_grid *g) {
     if (!g) return TFSC_ERR_ARG;
-    if (g->n_channels != 1 && g->n_channels != 2) return TFSC_ERR_SHAPE;
+    if (g->n_channels < 1 || g->n_channels > 3) return TFSC_ERR_SHAPE;
     if (g->tranche_len < 64 || g->tranche_len > 4096 || !pow2(g->tranche_len)) return TFSC_ERR_SHAPE;
     if (g->n_tranches < 1) return TFSC_ERR_SHAPE;
     if (g->n_fresnel != 21) return TFSC_ERR_UNSUPPORTED;
@@ -235,7 +235,8 @@ tfsc_status tfsc_bank_statistic_multi(const tfsc_grid *grid, const tfsc_pixels *
     if (group != 0 && group != 1 && group != 2 && group != 4 && group != 8) return TFSC_ERR_ARG;
     Resolved r;
     if ((s = resolve_options(opt, pix, r)) != TFSC_OK) return s;
-    if (r.schedule != TFSC_SCHED_WAVE || pix->layout == TFSC_TRANCHE_MAJOR || pix->rho) return TFSC_ERR_UNSUPPORTED;
+    if (r.schedule != TFSC_SCHED_WAVE || pix->layout == TFSC_TRANCHE_MAJOR || pix->rho || grid->n_channels == 3)
+        return TFSC_ERR_UNSUPPORTED;
     if (!(pix->dtype == TFSC_F32 && r.precision == TFSC_F32) && !(pix->dtype == TFSC_F64 && r.precision == TFSC_F64))
         return TFSC_ERR_DTYPE;
     const uint64_t one = pixel_store_bytes(grid, pix);
@@ -275,6 +276,7 @@ tfsc_status tfsc_statistic_vjp(const tfsc_grid *grid, const tfsc_pixels *pix, co
     // from the options.
     Resolved r;
     if ((s = resolve_options(opt, nullptr, r)) != TFSC_OK) return s;
+    if (grid->n_channels == 3) return TFSC_ERR_UNSUPPORTED;
     if (bank->n > 0 && (!seg_zn || !g_params || (!g_stat && !g_seg))) return TFSC_ERR_ARG;
     if (!ws || ws_bytes < ws_bytes_for(grid, bank->n, TFSC_WS_VJP)) return TFSC_ERR_WORKSPACE;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);

@@ -271,8 +271,9 @@ __device__ __forceinline__ void load_geo(const double *__restrict__ geo, int m, 
 
 // T_A, T_E at tranche m (time t_m) and frequency f from the geometry tables; each value
 // is read where it is used, which keeps register pressure down.
-template <class R>
-__device__ inline void transfer_ae(const Sky<R> &S, const GeoView &gv, int m, double f, cx<R> &TA, cx<R> &TE) {
+template <class R, bool WITH_T = false>
+__device__ inline void transfer_ae(const Sky<R> &S, const GeoView &gv, int m, double f, cx<R> &TA, cx<R> &TE,
+                                   cx<R> *TT = nullptr) {
 #pragma clang fp contract(fast)
     const double L = kArmM / kClight;
     double kp[3];
@@ -320,6 +321,11 @@ __device__ inline void transfer_ae(const Sky<R> &S, const GeoView &gv, int m, do
     const cx<R> ome = cscale(D, sp * is6);
     TA = cmul(oma, csub(Zp, Xp));
     TE = cmul(ome, cadd(csub(Xp, cscale(Yp, (R)2)), Zp));
+    if constexpr (WITH_T) {
+        // the third channel T = (X + Y + Z) / sqrt3, the null channel of the equal-arm constellation
+        const R is3 = (R)0.57735026918962576451;
+        *TT = cmul(cscale(D, sp * is3), cadd(cadd(Xp, Yp), Zp));
+    }
 }
 
 // ------------------------------------------------------------------ tranche spectrum

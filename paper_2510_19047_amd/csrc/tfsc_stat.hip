@@ -353,13 +353,17 @@ template <int C, class R>
 __device__ __forceinline__ void tranche_combine(const Sky<R> &S, const GeoView &gv, int m, double f, R wm,
                                                 const cx<R> (&P)[C], R Q, R &zr, R &zi, R &nn) {
 #pragma clang fp contract(fast)
-    cx<R> TA, TE;
-    transfer_ae(S, gv, m, f, TA, TE);
+    cx<R> TA, TE, TT;
+    transfer_ae<R, (C == 3)>(S, gv, m, f, TA, TE, &TT);
     cx<R> z = cmul(TA, P[0]);
     R tt = TA.re * TA.re + TA.im * TA.im;
-    if constexpr (C == 2) {
+    if constexpr (C >= 2) {
         z = cadd(z, cmul(TE, P[1]));
         tt += TE.re * TE.re + TE.im * TE.im;
+    }
+    if constexpr (C == 3) {
+        z = cadd(z, cmul(TT, P[2]));
+        tt += TT.re * TT.re + TT.im * TT.im;
     }
     zr = wm * z.re;
     zi = wm * z.im;
@@ -588,6 +592,10 @@ __device__ __forceinline__ void bin_pixels(__amdgpu_buffer_rsrc_t r, uint32_t vo
                 D[1] = {__uint_as_float(w1 << 16), __uint_as_float(w1 & 0xffff0000u)};
             }
         }
+    } else if constexpr (LAYOUT == 2) {
+        // one or three channels side by side: one load per channel at the pixel size apart
+#pragma unroll
+        for (int c = 0; c < C; ++c) D[c] = buf_load<PixT>(r, voff, soff + (uint32_t)(c * 2 * sizeof(PixT)));
     } else {
 #pragma unroll
         for (int c = 0; c < C; ++c) D[c] = buf_load<PixT>(r, voff, soff + (uint32_t)c * chan);
@@ -1413,6 +1421,7 @@ hipError_t launch_statistic_multi(const StatLaunch &L, hipStream_t st) {
         return L.C == 1 ? launch_multi_t<1, double>(L, a, st) : launch_multi_t<2, double>(L, a, st);
     }
     if (L.pix_dtype != 1) return hipErrorInvalidValue;
+    if (L.C == 3) return hipErrorInvalidValue;
     return L.C == 1 ? launch_multi_t<1, float>(L, a, st) : launch_multi_t<2, float>(L, a, st);
 }
 
@@ -1420,6 +1429,7 @@ hipError_t launch_statistic(const StatLaunch &L, hipStream_t st) {
     StatArgs a = make_args(L);
     if (L.n == 0) return hipSuccess;
     if (L.C == 1) return L.precision == 0 ? dispatch_pix<1, double>(L, a, st) : dispatch_pix<1, float>(L, a, st);
+    if (L.C == 3) return L.precision == 0 ? dispatch_pix<3, double>(L, a, st) : dispatch_pix<3, float>(L, a, st);
     return L.precision == 0 ? dispatch_pix<2, double>(L, a, st) : dispatch_pix<2, float>(L, a, st);
 }
 

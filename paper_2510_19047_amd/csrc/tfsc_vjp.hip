@@ -672,6 +672,7 @@ hipError_t launch_vjp(const VjpLaunch &V, hipStream_t st) {
     int64_t groups = (L.n + bw - 1) / bw;
     if (groups > (int64_t)L.n_groups) groups = L.n_groups;
     hipLaunchKernelGGL(k_vjp_zero, dim3(1), dim3(64), 0, st, a.counter);
+    if (L.C == 3) return hipErrorInvalidValue;
     return L.C == 1 ? dispatch_vjp<1>(a, L.pix_dtype, (int)groups, bw, st)
                     : dispatch_vjp<2>(a, L.pix_dtype, (int)groups, bw, st);
 }

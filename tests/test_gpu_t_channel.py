@@ -1,0 +1,134 @@
+"""Three channels (TDI A, E and T) through the C ABI against the oracle: transform, statistic on both
+schedules and all layouts, and the calls that refuse C = 3."""
+import functools
+
+import numpy as np
+import pytest
+import torch
+
+import tfsc_inputs as ti
+from oracle import o2
+from oracle import track as otrk
+from oracle import transform as otf
+
+from gpu_common import dev, gridspec, lib, note, rel
+
+pytestmark = pytest.mark.gpu
+
+
+@functools.lru_cache(maxsize=1)
+def _data():
+    """Three channels with gaps and modulation; noise plus an SNR-30 injection (the first template)."""
+    from oracle import o1
+    g = ti.custom_grid(3, 512, 400, dt=5.0, modulated=True, gapped=True, cfg_id=13)
+    psd = ti.psd_on_bins(g)
+    mu, keep = ti.tranche_psd_scale(g), ti.tranche_keep(g)
+    inj = ti.Bank(mc=np.array([30.0]), eta=np.array([0.25]), f0=np.array([0.02]), cos_theta=np.array([0.3]),
+                  phi=np.array([1.0]), psi=np.array([0.4]), cos_iota=np.array([0.6]), phase=np.zeros(1))
+    sig = o1.synthesize(inj, 0, g, analytic=False)
+    spix, _, _ = otf.transform(sig, g, psd, mu, keep, 0.1, "rfft")
+    x = ti.noise(g) + sig * (30.0 / np.sqrt(2 * np.sum(np.abs(spix[:, 1:-1]) ** 2)))  # SNR 30 over A, E, T
+    pix, u, wm = otf.transform(x, g, psd, mu, keep, 0.1, "rfft")
+    b = ti.random_bank(40, 7, mc_range=(10.0, 60.0), f0_range=(0.008, 0.05), eta=None, stream=71)
+    b = ti.Bank.concat(inj, b)
+    return dict(grid=g, x=x, psd=psd, mu=mu, keep=keep, pix=pix, u=u, wm=wm, bank=b)
+
+
+@functools.lru_cache(maxsize=2)
+def _oracle(f32_data: bool):
+    d = _data()
+    g, b = d["grid"], d["bank"]
+    x = d["x"].astype(np.float32).astype(np.float64) if f32_data else d["x"]
+    pix, u, wm = otf.transform(x, g, d["psd"], d["mu"], d["keep"], 0.1, "rfft")
+    return pix, o2.statistic(pix, u, wm, b, g, layout=otrk.Layout(b, g))
+
+
+def test_transform_three_channels():
+    tfsc = lib()
+    d = _data()
+    g = d["grid"]
+    note("transform C=3")
+    for layout in ("layer", "layer_ci", "tranche"):
+        st = tfsc.transform(gridspec(g), dev(d["x"]), dev(d["psd"]), dev(d["mu"]), dev(d["keep"]), dtype="f64",
+                            layout=layout)
+        p = torch.view_as_complex(st.pix).cpu().numpy()
+        p = {"layer": p, "layer_ci": np.transpose(p, (2, 0, 1)), "tranche": np.transpose(p, (0, 2, 1))}[layout]
+        assert np.max(np.abs(p - d["pix"])) < 1e-12 * np.abs(d["pix"]).max(), layout
+
+
+@pytest.mark.parametrize("schedule,layout", [("wave", "layer_ci"), ("wave", "layer"), ("thread", "tranche")])
+def test_statistic_fp64_three_channels(schedule, layout):
+    tfsc = lib()
+    d = _data()
+    g = d["grid"]
+    note(f"C=3 statistic f64 {schedule} {layout}")
+    _, ref = _oracle(False)
+    st = tfsc.transform(gridspec(g), dev(d["x"]), dev(d["psd"]), dev(d["mu"]), dev(d["keep"]), dtype="f64",
+                        layout=layout)
+    bt = tfsc.BankTensors.from_host(d["bank"])
+    seg = tfsc.segment_layout(gridspec(g), bt)
+    res = tfsc.bank_statistic(gridspec(g), st, bt, seg, precision="f64", schedule=schedule)
+    r = rel(res.stat.cpu().numpy(), ref.stat)
+    stt = res.seg_terms[:seg.total].cpu().numpy()
+    note(f"  max rel {r.max():.2e}; injection Upsilon {ref.stat[0]:.1f}")
+    assert r.max() < 1e-6
+    assert np.max(np.abs(stt - ref.seg_terms) / np.maximum(ref.seg_terms, 1.0)) < 1e-6
+    assert np.array_equal(res.flags.cpu().numpy(), ref.flags)
+
+
+@pytest.mark.parametrize("schedule,layout", [("wave", "layer_ci"), ("thread", "tranche")])
+def test_statistic_fp32_three_channels(schedule, layout):
+    tfsc = lib()
+    d = _data()
+    g = d["grid"]
+    note(f"C=3 statistic f32 {schedule} {layout}")
+    _, ref = _oracle(True)
+    st = tfsc.transform(gridspec(g), dev(d["x"].astype(np.float32)), dev(d["psd"]), dev(d["mu"]), dev(d["keep"]),
+                        dtype="f32", layout=layout)
+    bt = tfsc.BankTensors.from_host(d["bank"])
+    seg = tfsc.segment_layout(gridspec(g), bt)
+    s = tfsc.bank_statistic(gridspec(g), st, bt, seg, precision="f32", schedule=schedule).stat.cpu().numpy()
+    r = rel(s, ref.stat)
+    note(f"  max rel {r.max():.2e}")
+    assert r.max() < 1e-4
+    assert int(np.argmax(s)) == int(np.argmax(ref.stat)) == 0
+
+
+def test_t_channel_contributes():
+    """The third channel is read: the injection's Upsilon over A, E and T differs from its A+E value on the
+    same data by T's small share (signal and noise)."""
+    tfsc = lib()
+    d = _data()
+    g = d["grid"]
+    g2 = ti.custom_grid(2, g.tranche_len, g.n_tranches, dt=g.dt, modulated=True, gapped=True, cfg_id=13)
+    st3 = tfsc.transform(gridspec(g), dev(d["x"]), dev(d["psd"]), dev(d["mu"]), dev(d["keep"]), dtype="f64",
+                         layout="layer_ci")
+    st2 = tfsc.transform(gridspec(g2), dev(np.ascontiguousarray(d["x"][:2])), dev(d["psd"]), dev(d["mu"]),
+                         dev(d["keep"]), dtype="f64", layout="layer_ci")
+    bt = tfsc.BankTensors.from_host(d["bank"])
+    s3 = tfsc.bank_statistic(gridspec(g), st3, bt, tfsc.segment_layout(gridspec(g), bt), precision="f64")
+    s2 = tfsc.bank_statistic(gridspec(g2), st2, bt, tfsc.segment_layout(gridspec(g2), bt), precision="f64")
+    a, b = s3.stat[0].item(), s2.stat[0].item()
+    note(f"  injection: A+E+T {a:.2f}, A+E {b:.2f}")
+    assert a != b and abs(a / b - 1.0) < 0.1
+
+
+def test_three_channels_refused_by_vjp_and_multi():
+    tfsc = lib()
+    d = _data()
+    g = d["grid"]
+    bt = tfsc.BankTensors.from_host(d["bank"])
+    seg = tfsc.segment_layout(gridspec(g), bt)
+    st = tfsc.transform(gridspec(g), dev(d["x"].astype(np.float32)), dev(d["psd"]), dev(d["mu"]), dev(d["keep"]),
+                        dtype="f32", layout="layer_ci")
+    fw = tfsc.bank_statistic(gridspec(g), st, bt, seg, precision="f32", want_zn=True)
+    with pytest.raises(tfsc.TfscError):
+        tfsc.statistic_vjp(gridspec(g), st, bt, seg, fw.seg_zn,
+                           g_stat=torch.ones(bt.n, dtype=torch.float64, device="cuda"))
+    stores = tfsc.realisation_stores(gridspec(g), 2, dtype="f32", layout="layer_ci")
+    for r in range(2):
+        stores[r].pix.copy_(st.pix)
+    stores[0].inv_asd.copy_(st.inv_asd)
+    stores[0].tranche_w.copy_(st.tranche_w)
+    with pytest.raises(tfsc.TfscError):
+        tfsc.bank_statistic_multi(gridspec(g), stores, bt, seg, precision="f32")
