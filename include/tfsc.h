@@ -47,9 +47,9 @@ typedef enum { TFSC_F64 = 0, TFSC_F32 = 1, TFSC_BF16 = 2, TFSC_F16 = 3 } tfsc_dt
 typedef enum { TFSC_LAYER_MAJOR = 0, TFSC_TRANCHE_MAJOR = 1, TFSC_LAYER_MAJOR_CI = 2 } tfsc_layout;
 
 /* Sampling grid.  C = 1 (TDI A), 2 (A, E; the paper's channels, Eq. (tdi2))
- * or 3 (A, E and T = (X + Y + Z)/sqrt3, the null channel; statistic and
- * transform only: tfsc_statistic_vjp and tfsc_bank_statistic_multi return
- * TFSC_ERR_UNSUPPORTED for C = 3); M even, 64 <= M <= 4096 and a
+ * or 3 (A, E and T = (X + Y + Z)/sqrt3, the null channel;
+ * tfsc_bank_statistic_multi returns TFSC_ERR_UNSUPPORTED for C = 3); M even,
+ * 64 <= M <= 4096 and a
  * power of two (the transform's FFT); K = M/2 + 1 bins per tranche;
  * n_fresnel must be 21 (paper: N_F = 21 bins centred on the bin just above
  * the track frequency).  tukey_alpha is the data window's shape (paper: 0.1;

@@ -276,7 +276,6 @@ tfsc_status tfsc_statistic_vjp(const tfsc_grid *grid, const tfsc_pixels *pix, co
     // from the options.
     Resolved r;
     if ((s = resolve_options(opt, nullptr, r)) != TFSC_OK) return s;
-    if (grid->n_channels == 3) return TFSC_ERR_UNSUPPORTED;
     if (bank->n > 0 && (!seg_zn || !g_params || (!g_stat && !g_seg))) return TFSC_ERR_ARG;
     if (!ws || ws_bytes < ws_bytes_for(grid, bank->n, TFSC_WS_VJP)) return TFSC_ERR_WORKSPACE;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);

@@ -301,8 +301,9 @@ __device__ inline void sky_dual(SkyD &S, double ct, double phi, double psi, doub
     S.ci = ci;
 }
 
+template <bool WITH_T>
 __device__ inline void transfer_ae_dual(const SkyD &S, const double (&g)[kGeoRows], double f, CDn<4> &TA,
-                                        CDn<4> &TE) {
+                                        CDn<4> &TE, CDn<4> &TT) {
     const double L = kArmM / kClight;
     Dn<4> F = dconst<4>(f);
     F.d[0] = 1.0;
@@ -344,6 +345,7 @@ __device__ inline void transfer_ae_dual(const SkyD &S, const double (&g)[kGeoRow
     const double is2 = 0.70710678118654752440, is6 = 0.40824829046386301637;
     TA = cdscale(cdsub(TZ, TX), is2);
     TE = cdscale(cdadd(cdsub(TX, cdscale(TY, 2.0)), TZ), is6);
+    if constexpr (WITH_T) TT = cdscale(cdadd(cdadd(TX, TY), TZ), 0.57735026918962576451);  // (X + Y + Z) / sqrt3
 }
 
 // ------------------------------------------------------------------ spectrum tangents
@@ -570,10 +572,10 @@ __global__ __launch_bounds__(256) void k_vjp_wave(VjpArgs a) {
                             Vr[p] *= w2;
                             Vi[p] *= w2;
                         }
-                        CDn<4> Tc[2];
+                        CDn<4> Tc[3];
                         double gm[kGeoRows];
                         load_geo(a.geo, m, a.Nt, gm);
-                        transfer_ae_dual(S, gm, f, Tc[0], Tc[1]);
+                        transfer_ae_dual<(C == 3)>(S, gm, f, Tc[0], Tc[1], Tc[2]);
 #pragma unroll
                         for (int c = 0; c < C; ++c) {
                             const double tr = Tc[c].re.v, ti = Tc[c].im.v;
@@ -672,7 +674,7 @@ hipError_t launch_vjp(const VjpLaunch &V, hipStream_t st) {
     int64_t groups = (L.n + bw - 1) / bw;
     if (groups > (int64_t)L.n_groups) groups = L.n_groups;
     hipLaunchKernelGGL(k_vjp_zero, dim3(1), dim3(64), 0, st, a.counter);
-    if (L.C == 3) return hipErrorInvalidValue;
+    if (L.C == 3) return dispatch_vjp<3>(a, L.pix_dtype, (int)groups, bw, st);
     return L.C == 1 ? dispatch_vjp<1>(a, L.pix_dtype, (int)groups, bw, st)
                     : dispatch_vjp<2>(a, L.pix_dtype, (int)groups, bw, st);
 }

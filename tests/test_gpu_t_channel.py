@@ -1,5 +1,5 @@
 """Three channels (TDI A, E and T) through the C ABI against the oracle: transform, statistic on both
-schedules and all layouts, and the calls that refuse C = 3."""
+schedules and all layouts, the VJP, and the several-realisation call that refuses C = 3."""
 import functools
 
 import numpy as np
@@ -113,7 +113,33 @@ def test_t_channel_contributes():
     assert a != b and abs(a / b - 1.0) < 0.1
 
 
-def test_three_channels_refused_by_vjp_and_multi():
+def test_vjp_three_channels_against_oracle_autograd():
+    """The FP64 VJP with T's dual response: against float64 autograd of the oracle over A, E and T (the
+    two-channel bar)."""
+    tfsc = lib()
+    d = _data()
+    g, b = d["grid"], d["bank"]
+    lay = otrk.Layout(b, g)
+    ok = np.nonzero((lay.flags & (otrk.FLAG_INVALID | otrk.FLAG_EMPTY)) == 0)[0]
+    idx = np.concatenate([ok[:5], ok[-3:]])
+    note(f"C=3 vjp, templates {idx.tolist()}")
+    st = tfsc.transform(gridspec(g), dev(d["x"]), dev(d["psd"]), dev(d["mu"]), dev(d["keep"]), dtype="f64",
+                        layout="layer_ci")
+    bt = tfsc.BankTensors.from_host(b)
+    seg = tfsc.segment_layout(gridspec(g), bt)
+    fw = tfsc.bank_statistic(gridspec(g), st, bt, seg, precision="f64", want_zn=True)
+    gp = tfsc.statistic_vjp(gridspec(g), st, bt, seg, fw.seg_zn,
+                            g_stat=torch.ones(bt.n, dtype=torch.float64, device="cuda")).cpu().numpy()
+    ref = np.zeros((len(idx), 5))
+    for r, i in enumerate(idx):
+        ref[r], _ = o2.gradient(d["pix"], d["u"], d["wm"], b, g, int(i), layout=lay)
+    floor = 1e-3 * np.max(np.abs(ref), axis=0, keepdims=True)
+    err = np.abs(gp[idx] - ref) / np.maximum(np.abs(ref), floor)
+    note(f"  max rel vs oracle autograd {err.max():.2e}")
+    assert err.max() < 2e-5
+
+
+def test_three_channels_refused_by_multi():
     tfsc = lib()
     d = _data()
     g = d["grid"]
@@ -121,10 +147,6 @@ def test_three_channels_refused_by_vjp_and_multi():
     seg = tfsc.segment_layout(gridspec(g), bt)
     st = tfsc.transform(gridspec(g), dev(d["x"].astype(np.float32)), dev(d["psd"]), dev(d["mu"]), dev(d["keep"]),
                         dtype="f32", layout="layer_ci")
-    fw = tfsc.bank_statistic(gridspec(g), st, bt, seg, precision="f32", want_zn=True)
-    with pytest.raises(tfsc.TfscError):
-        tfsc.statistic_vjp(gridspec(g), st, bt, seg, fw.seg_zn,
-                           g_stat=torch.ones(bt.n, dtype=torch.float64, device="cuda"))
     stores = tfsc.realisation_stores(gridspec(g), 2, dtype="f32", layout="layer_ci")
     for r in range(2):
         stores[r].pix.copy_(st.pix)
