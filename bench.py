@@ -64,6 +64,9 @@ def parse():
     p.add_argument("--psd-tf", action="store_true",
                    help="also time the chosen form with a PSD that varies between tranches in a general way "
                         "(per-pixel whitening and weights), with sampled parity against the oracle")
+    p.add_argument("--aet", action="store_true",
+                   help="also time the chosen form on three channels (A, E and the null channel T) of the same "
+                        "2-yr grid and bank, with sampled parity against the oracle")
     p.add_argument("--copy-calibration", action="store_true",
                    help="copy 256 MiB device-to-device once, so profiler byte counters can be calibrated")
     return p.parse_args()
@@ -252,6 +255,9 @@ def main():
     }
 
     # ---------------- CPU baseline: the plain-C oracle on host cores, bounded sample
+    if args.aet:
+        out["aet"] = aet_run(args, tfsc, ti, g, psd_d, mu_d, keep_d, bank, bank_h, seg, order, kw, pix_cols, value,
+                             k_ms)
     if args.psd_tf:
         out["psd_tf"] = psd_tf_run(args, tfsc, ti, grid, g, x, x_d, keep_d, bank, bank_h, seg, order, kw, pix_cols,
                                    value, k_ms)
@@ -262,6 +268,70 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, x, psd, mu, keep, bank_h, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def aet_run(args, tfsc, ti, g, psd_d, mu_d, keep_d, bank, bank_h, seg, order, kw, pix_cols, value_ae, k_ms_ae):
+    """The chosen form on three channels (A, E, T) of the same 2-yr grid: transform + layout + order + statistic
+    per step, the statistic kernel timed alone, and sampled templates checked against the oracle."""
+    import torch
+    from oracle import o2
+    from oracle import track as otrk
+    from oracle import transform as otf
+    dev = psd_d.device
+    n = bank.n
+    g3 = ti.GridSpec("full-aet", g.cfg_id, 3, g.dt, g.tranche_len, g.n_tranches, g.modulated, g.gapped)
+    grid3 = tfsc.GridSpec(3, g.tranche_len, g.n_tranches, g.dt, 0.1)
+    x3 = (ti.noise(g3) * ti.sample_keep_mask(g3)[None, :]).astype(np.float32)
+    x3_d = torch.from_numpy(x3).to(dev)
+    layout = args.chosen_layout
+    pix = tfsc.transform(grid3, x3_d, psd_d, mu_d, keep_d, dtype="f32", layout=layout)
+    res = tfsc.StatResult(torch.empty(n, dtype=torch.float64, device=dev),
+                          torch.empty(seg.total, dtype=torch.float64, device=dev),
+                          torch.empty(n, dtype=torch.int32, device=dev))
+
+    def step():
+        tfsc.transform(grid3, x3_d, psd_d, mu_d, keep_d, dtype="f32", layout=layout, out=pix)
+        tfsc.segment_layout(grid3, bank, out=seg, read_total=False)
+        o = None if order is None else tfsc.processing_order(grid3, bank, out=order)
+        tfsc.bank_statistic(grid3, pix, bank, seg, precision="f32", schedule="wave", out=res, order=o, **kw)
+
+    step()
+    torch.cuda.synchronize()
+    log("aet: warmup done")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ms_step = 1e3 * (time.perf_counter() - t0) / args.steps
+    st = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ks = []
+    for _ in range(3):
+        ev[0].record(st)
+        tfsc.bank_statistic(grid3, pix, bank, seg, precision="f32", schedule="wave", out=res, order=order, **kw)
+        ev[1].record(st)
+        torch.cuda.synchronize()
+        ks.append(ev[0].elapsed_time(ev[1]))
+    k_ms = float(np.median(ks))
+    alg_bytes = pix_cols * NF * 3 * 8 + n * 56 + 8 * (seg.total + n)
+    value = n / (ms_step / 1e3)
+    log(f"aet: {ms_step:.2f} ms/step, {value / 1e6:.3f} M templates/s; statistic kernel {k_ms:.2f} ms "
+        f"({k_ms / k_ms_ae:.3f}x the A+E kernel's)")
+    s = res.stat.cpu().numpy()
+    rng = np.random.default_rng(19)
+    idx = sorted(set(np.argsort(-np.nan_to_num(s, nan=-1.0))[:3].tolist()) | set(rng.choice(n, 5, replace=False).tolist()))
+    pix_o, u, wm = otf.transform(x3.astype(np.float64), g3, ti.psd_on_bins(g3), ti.tranche_psd_scale(g3),
+                                 ti.tranche_keep(g3), 0.1, "rfft")
+    sub = bank_h.subset(idx)
+    ref = o2.statistic(pix_o, u, wm, sub, g3, layout=otrk.Layout(sub, g3))
+    r = np.abs(s[idx] - ref.stat) / np.maximum(np.abs(ref.stat), 1.0)
+    log(f"aet: sampled parity on {len(idx)} templates, max rel {r.max():.2e}")
+    return {"workload": "same 2-yr grid and bank, three channels A, E, T (noise of the A/E model in each)",
+            "templates_per_s": round(value, 1), "ms_per_step": round(ms_step, 3), "kernel_ms": round(k_ms, 3),
+            "kernel_over_ae": round(k_ms / k_ms_ae, 4), "value_over_ae": round(value / value_ae, 4),
+            "alg_bytes_per_launch": alg_bytes, "alg_gbs": round(alg_bytes / (k_ms / 1e3) / 1e9, 1),
+            "store": f"f32 {layout}, 3 channels",
+            "sampled_parity": {"templates": len(idx), "max_rel_vs_oracle": float(r.max())}}
 
 
 def psd_tf_run(args, tfsc, ti, grid, g, x, x_d, keep_d, bank, bank_h, seg, order, kw, pix_cols, value_sep, k_ms_sep):
