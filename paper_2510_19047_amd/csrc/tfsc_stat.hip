@@ -592,6 +592,13 @@ __device__ __forceinline__ void bin_pixels(__amdgpu_buffer_rsrc_t r, uint32_t vo
                 D[1] = {__uint_as_float(w1 << 16), __uint_as_float(w1 & 0xffff0000u)};
             }
         }
+    } else if constexpr (LAYOUT == 2 && C == 3 && sizeof(PixT) == 4) {
+        // A and E with one 16-byte load, T with one 8-byte load (24-byte cells, 8-byte aligned)
+        const float4 q = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+        const float2 t = __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff + 16u, 0));
+        D[0] = {q.x, q.y};
+        D[1] = {q.z, q.w};
+        D[2] = {t.x, t.y};
     } else if constexpr (LAYOUT == 2) {
         // one or three channels side by side: one load per channel at the pixel size apart
 #pragma unroll
