@@ -79,8 +79,8 @@ typedef struct {
  * template pixel becomes T_c h_m(f_k) u_k w_m rho_mk; tfsc_transform_tf
  * writes it.  Read by tfsc_bank_statistic (THREAD schedule: every pixel
  * type; WAVE schedule: F64 or F32 pixels with the same arithmetic, or F32
- * pixels with F64 arithmetic) and by tfsc_statistic_vjp (every pixel type);
- * tfsc_bank_statistic_multi returns TFSC_ERR_UNSUPPORTED when it is set.    */
+ * pixels with F64 arithmetic), by tfsc_statistic_vjp (every pixel type) and
+ * by tfsc_bank_statistic_multi (one rho for all realisations).             */
 typedef struct {
     tfsc_dtype dtype;
     tfsc_layout layout;
@@ -220,7 +220,7 @@ tfsc_status tfsc_bank_statistic(const tfsc_grid *grid, const tfsc_pixels *pix, c
  * comes from many noise-only realisations; Sec. "Hardware acceleration and
  * computational cost": large batches per launch).  Realisation r's pixel
  * store lies r * real_stride bytes after pix->pix (same dtype, layout,
- * inv_asd and tranche_w for all; real_stride a multiple of 16 and at least
+ * inv_asd, tranche_w and rho for all; real_stride a multiple of 16 and at least
  * one store's size; n_real * real_stride < 4 GiB); 1 <= n_real <= 64.  Each
  * template's track, Fresnel spectrum and response are formed once per group
  * of `group` realisations (1, 2, 4 or 8; 0 = 8) and serve all of them; the

@@ -235,7 +235,7 @@ tfsc_status tfsc_bank_statistic_multi(const tfsc_grid *grid, const tfsc_pixels *
     if (group != 0 && group != 1 && group != 2 && group != 4 && group != 8) return TFSC_ERR_ARG;
     Resolved r;
     if ((s = resolve_options(opt, pix, r)) != TFSC_OK) return s;
-    if (r.schedule != TFSC_SCHED_WAVE || pix->layout == TFSC_TRANCHE_MAJOR || pix->rho || grid->n_channels == 3)
+    if (r.schedule != TFSC_SCHED_WAVE || pix->layout == TFSC_TRANCHE_MAJOR || grid->n_channels == 3)
         return TFSC_ERR_UNSUPPORTED;
     if (!(pix->dtype == TFSC_F32 && r.precision == TFSC_F32) && !(pix->dtype == TFSC_F64 && r.precision == TFSC_F64))
         return TFSC_ERR_DTYPE;

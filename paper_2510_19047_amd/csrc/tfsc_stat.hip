@@ -977,6 +977,26 @@ __device__ __forceinline__ void wave_tranche_coefs(const TrancheSpec<R> &ts, int
     }
 }
 
+// Per-pixel PSD factor on a lane's coefficient table (the same for every realisation): c_j *= rho at
+// (bin kc + j, tranche m), Q recomputed in the same order; rows below 0 already have weight 0.  A
+// separate pass, taken only when rho is set, so the table's own loop keeps its registers.
+template <class R>
+__device__ __forceinline__ void wave_tranche_coefs_rho(cx<R> *cf, int lane, int kc, int m, int Nt,
+                                                       const float *__restrict__ rho, R &Q) {
+#pragma clang fp contract(fast)
+    Q = (R)0;
+#pragma unroll 1
+    for (int jj = 0; jj < 2 * kHalfBins + 1; ++jj) {
+        const R r = (R)rho[max(kc + jj - kHalfBins, 0) * Nt + m];  // K Nt < 2^31 (the store is < 4 GiB)
+        cx<R> g = cf[jj * 64 + lane];
+        g.re *= r;
+        g.im *= r;
+        cf[jj * 64 + lane] = g;
+        Q += g.re * g.re;
+        Q += g.im * g.im;
+    }
+}
+
 // P_c = sum_j conj(D_cj) c_j for one realisation (soff0 = its byte offset in the block);
 // loads in groups of three, issued before the group's arithmetic.  low: some lane of the
 // wave has kc < 10, so rows are per lane and clamped at 0 (their weight is 0).
@@ -1131,6 +1151,7 @@ __global__ __launch_bounds__(256, 4) void k_stat_wave_multi(StatArgs a) {
                 if constexpr (C == 2) tt += TE.re * TE.re + TE.im * TE.im;
                 R Q;
                 wave_tranche_coefs<R>(ts, kc, u_pad, jA, jB, cfbuf, lane, Q);
+                if (a.rho) wave_tranche_coefs_rho<R>(cfbuf, lane, kc, m, a.Nt, a.rho, Q);
                 const R wm = (R)wmd;
                 nn = wm * wm * tt * Q;
 #pragma unroll 1

@@ -115,24 +115,14 @@ def test_unit_rho_is_bit_identical_to_the_separable_path(schedule, layout, prec,
     assert torch.equal(a.flags, b.flags) and torch.equal(a.n_active, b.n_active)
 
 
-def test_rho_is_refused_where_it_is_not_supported():
+def test_rho_with_16bit_stores():
+    """16-bit stores with rho: refused by the wave schedule, accepted by the thread schedule."""
     tfsc = lib()
     d = small_data()
     g = d["grid"]
     S = ti.tranche_psd_tf(g)
     bt = tfsc.BankTensors.from_host(d["bank"])
     seg = tfsc.segment_layout(gridspec(g), bt)
-    st = tfsc.transform_tf(gridspec(g), dev(d["x"].astype(np.float32)), dev(S), dev(d["keep"]), dtype="f32",
-                           layout="layer_ci")
-    stores = tfsc.realisation_stores(gridspec(g), 2, dtype="f32", layout="layer_ci")
-    for r in range(2):
-        stores[r].pix.copy_(st.pix)
-    stores[0].inv_asd.copy_(st.inv_asd)
-    stores[0].tranche_w.copy_(st.tranche_w)
-    tfsc.bank_statistic_multi(gridspec(g), stores, bt, seg, precision="f32")  # accepted without rho
-    stores[0].rho = st.rho
-    with pytest.raises(tfsc.TfscError):  # several realisations with rho
-        tfsc.bank_statistic_multi(gridspec(g), stores, bt, seg, precision="f32")
     h = tfsc.transform_tf(gridspec(g), dev(d["x"].astype(np.float32)), dev(S), dev(d["keep"]), dtype="f16",
                           layout="layer_ci")
     with pytest.raises(tfsc.TfscError):  # 16-bit store on the wave schedule
@@ -209,3 +199,42 @@ def test_follow_up_with_a_per_pixel_psd():
     note(f"  exact {exact:.1f}; start median {np.median(first):.1f}; best median {np.median(best):.1f}")
     assert np.all(best >= first)
     assert np.median(best) > 0.9 * exact
+
+
+def test_several_realisations_with_rho():
+    """Three noise realisations whitened by the same per-pixel PSD, in one pass over the bank (groups of 2
+    and 1), against one launch per realisation; and rho = 1 against no rho (the rho pass re-sums Q from the
+    stored coefficient table, so the two agree to rounding rather than bit for bit)."""
+    tfsc = lib()
+    d = small_data()
+    g = d["grid"]
+    S = ti.tranche_psd_tf(g)
+    R = 3
+    note("several realisations with rho")
+    bt = tfsc.BankTensors.from_host(d["bank"])
+    seg = tfsc.segment_layout(gridspec(g), bt)
+    stores = tfsc.realisation_stores(gridspec(g), R, dtype="f32", layout="layer_ci")
+    keep = ti.sample_keep_mask(g)[None, :]
+    singles = []
+    for r in range(R):
+        x = (ti.noise(g, realisation=r) * keep).astype(np.float32)
+        one = tfsc.transform_tf(gridspec(g), dev(x), dev(S), dev(d["keep"]), dtype="f32", layout="layer_ci")
+        stores[r].pix.copy_(one.pix)
+        singles.append(one)
+    stores[0].inv_asd.copy_(singles[0].inv_asd)
+    stores[0].tranche_w.copy_(singles[0].tranche_w)
+    stores[0].rho = singles[0].rho
+    res = tfsc.bank_statistic_multi(gridspec(g), stores, bt, seg, precision="f32", group=2)
+    worst = 0.0
+    for r in range(R):
+        one = tfsc.bank_statistic(gridspec(g), singles[r], bt, seg, precision="f32", schedule="wave")
+        err = rel(res.stat[r].cpu().numpy(), one.stat.cpu().numpy()).max()
+        worst = max(worst, err)
+        assert err < 2e-6, r
+    note(f"  max rel against single launches {worst:.2e}")
+    assert not torch.equal(res.stat[0], res.stat[1])
+    stores[0].rho = torch.ones_like(singles[0].rho)
+    a = tfsc.bank_statistic_multi(gridspec(g), stores, bt, seg, precision="f32", group=2)
+    stores[0].rho = None
+    b = tfsc.bank_statistic_multi(gridspec(g), stores, bt, seg, precision="f32", group=2)
+    assert rel(a.stat.cpu().numpy(), b.stat.cpu().numpy()).max() < 1e-6
