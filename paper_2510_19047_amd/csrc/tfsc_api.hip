@@ -352,13 +352,14 @@ tfsc_status tfsc_tile_max(const double *stat, const int32_t *tile, int64_t n, in
                                             reinterpret_cast<hipStream_t>(stream)));
 }
 
-tfsc_status tfsc_transform(const tfsc_grid *grid, const void *x, int x_dtype, const double *psd0,
-                           const double *tranche_psd_scale, const uint8_t *tranche_keep, tfsc_pixels *out,
-                           void *ws, size_t ws_bytes, void *stream) {
-    tfsc_status s;
-    if ((s = check_grid(grid)) != TFSC_OK) return s;
-    if ((s = check_pixels(out, true)) != TFSC_OK) return s;
-    if (!x || !psd0 || !tranche_psd_scale || !tranche_keep) return TFSC_ERR_ARG;
+}  // extern "C"
+
+namespace {
+
+// Shared by tfsc_transform (psd_tf NULL: S_m(f_k) = mu_m S0(f_k)) and tfsc_transform_tf (psd_tf set).
+tfsc_status transform_common(const tfsc_grid *grid, const void *x, int x_dtype, const double *psd0,
+                             const double *mu, const double *psd_tf, const uint8_t *tranche_keep, tfsc_pixels *out,
+                             void *ws, size_t ws_bytes, void *stream) {
     if (x_dtype != TFSC_F64 && x_dtype != TFSC_F32) return TFSC_ERR_DTYPE;
     if (out->dtype == TFSC_F64 && x_dtype != TFSC_F64) return TFSC_ERR_DTYPE;
     if (out->dtype == TFSC_F64 && grid->tranche_len > 2048) return TFSC_ERR_UNSUPPORTED;
@@ -373,7 +374,8 @@ tfsc_status tfsc_transform(const tfsc_grid *grid, const void *x, int x_dtype, co
     L.x = x;
     L.x_dtype = x_dtype;
     L.psd0 = psd0;
-    L.mu = tranche_psd_scale;
+    L.mu = mu;
+    L.psd_tf = psd_tf;
     L.keep = tranche_keep;
     L.out_dtype = out->dtype;
     L.out_layout = out->layout;
@@ -381,10 +383,24 @@ tfsc_status tfsc_transform(const tfsc_grid *grid, const void *x, int x_dtype, co
     L.layer_scale = out->layer_scale;
     L.inv_asd = out->inv_asd;
     L.tranche_w = out->tranche_w;
-    L.psd_tf = nullptr;
-    L.rho = nullptr;
+    L.rho = psd_tf ? out->rho : nullptr;
     L.ws = ws;
     return hip_status(tfsc::launch_transform(L, reinterpret_cast<hipStream_t>(stream)));
+}
+
+}  // namespace
+
+extern "C" {
+
+tfsc_status tfsc_transform(const tfsc_grid *grid, const void *x, int x_dtype, const double *psd0,
+                           const double *tranche_psd_scale, const uint8_t *tranche_keep, tfsc_pixels *out,
+                           void *ws, size_t ws_bytes, void *stream) {
+    tfsc_status s;
+    if ((s = check_grid(grid)) != TFSC_OK) return s;
+    if ((s = check_pixels(out, true)) != TFSC_OK) return s;
+    if (!x || !psd0 || !tranche_psd_scale || !tranche_keep) return TFSC_ERR_ARG;
+    return transform_common(grid, x, x_dtype, psd0, tranche_psd_scale, nullptr, tranche_keep, out, ws, ws_bytes,
+                            stream);
 }
 
 tfsc_status tfsc_transform_tf(const tfsc_grid *grid, const void *x, int x_dtype, const double *psd_tf,
@@ -394,32 +410,7 @@ tfsc_status tfsc_transform_tf(const tfsc_grid *grid, const void *x, int x_dtype,
     if ((s = check_grid(grid)) != TFSC_OK) return s;
     if ((s = check_pixels(out, true)) != TFSC_OK) return s;
     if (!x || !psd_tf || !tranche_keep || !out->rho) return TFSC_ERR_ARG;
-    if (x_dtype != TFSC_F64 && x_dtype != TFSC_F32) return TFSC_ERR_DTYPE;
-    if (out->dtype == TFSC_F64 && x_dtype != TFSC_F64) return TFSC_ERR_DTYPE;
-    if (out->dtype == TFSC_F64 && grid->tranche_len > 2048) return TFSC_ERR_UNSUPPORTED;
-    const bool q16 = out->dtype == TFSC_BF16 || out->dtype == TFSC_F16;
-    if (q16 && (!ws || ws_bytes < ws_bytes_for(grid, 0, TFSC_WS_TRANSFORM))) return TFSC_ERR_WORKSPACE;
-    tfsc::TransformLaunch L;
-    L.M = grid->tranche_len;
-    L.Nt = grid->n_tranches;
-    L.C = grid->n_channels;
-    L.dt = grid->dt;
-    L.alpha = grid->tukey_alpha;
-    L.x = x;
-    L.x_dtype = x_dtype;
-    L.psd0 = nullptr;
-    L.mu = nullptr;
-    L.psd_tf = psd_tf;
-    L.keep = tranche_keep;
-    L.out_dtype = out->dtype;
-    L.out_layout = out->layout;
-    L.pix = out->pix;
-    L.layer_scale = out->layer_scale;
-    L.inv_asd = out->inv_asd;
-    L.tranche_w = out->tranche_w;
-    L.rho = out->rho;
-    L.ws = ws;
-    return hip_status(tfsc::launch_transform(L, reinterpret_cast<hipStream_t>(stream)));
+    return transform_common(grid, x, x_dtype, nullptr, nullptr, psd_tf, tranche_keep, out, ws, ws_bytes, stream);
 }
 
 tfsc_status tfsc_track(const tfsc_grid *grid, const tfsc_bank *bank, double *out, void *stream) {
