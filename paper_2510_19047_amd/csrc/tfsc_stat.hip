@@ -516,16 +516,18 @@ __device__ __forceinline__ void dpp_step3(float &a, float &b, float &c) {
 }
 
 // Three wave sums at once: the three independent DPP moves of each step fill each other's
-// data-hazard slots.
+// data-hazard slots.  Only lane 63's total is read, so every step runs with full row and bank
+// masks: a source outside the row reads 0 (bound_ctrl), lane 63 sees the same additions in the
+// same order as with the masked inclusive scan, and each step folds into one DPP add.
 template <class R>
 __device__ __forceinline__ void wave_sum3(R &a, R &b, R &c) {
     if constexpr (sizeof(R) == 4) {
         dpp_step3<0x111, 0xf, 0xf>(a, b, c);
         dpp_step3<0x112, 0xf, 0xf>(a, b, c);
-        dpp_step3<0x114, 0xf, 0xe>(a, b, c);
-        dpp_step3<0x118, 0xf, 0xc>(a, b, c);
-        dpp_step3<0x142, 0xa, 0xf>(a, b, c);
-        dpp_step3<0x143, 0xc, 0xf>(a, b, c);
+        dpp_step3<0x114, 0xf, 0xf>(a, b, c);
+        dpp_step3<0x118, 0xf, 0xf>(a, b, c);
+        dpp_step3<0x142, 0xf, 0xf>(a, b, c);
+        dpp_step3<0x143, 0xf, 0xf>(a, b, c);
         a = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, a), 63));
         b = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, b), 63));
         c = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, c), 63));
