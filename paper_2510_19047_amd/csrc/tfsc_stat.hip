@@ -435,10 +435,10 @@ __device__ __forceinline__ float dpp_sum_f32(float v) {
 #pragma clang fp contract(fast)
     v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x111, 0xf, 0xf, true));
     v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x112, 0xf, 0xf, true));
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x114, 0xf, 0xe, true));
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x118, 0xf, 0xc, true));
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x142, 0xa, 0xf, true));
-    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x143, 0xc, 0xf, true));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x114, 0xf, 0xf, true));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x118, 0xf, 0xf, true));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x142, 0xf, 0xf, true));
+    v += __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x143, 0xf, 0xf, true));
     return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
 
@@ -452,13 +452,14 @@ __device__ __forceinline__ double dpp_add_step_f64(double v) {
 }
 
 __device__ __forceinline__ double dpp_sum_f64(double v) {
-    // the two 32-bit halves move by DPP; the adds are FP64
+    // the two 32-bit halves move by DPP; the adds are FP64.  Full masks as in wave_sum3: only
+    // lane 63's total is read, and a source outside the row reads +0.0.
     v = dpp_add_step_f64<0x111, 0xf, 0xf>(v);
     v = dpp_add_step_f64<0x112, 0xf, 0xf>(v);
-    v = dpp_add_step_f64<0x114, 0xf, 0xe>(v);
-    v = dpp_add_step_f64<0x118, 0xf, 0xc>(v);
-    v = dpp_add_step_f64<0x142, 0xa, 0xf>(v);
-    v = dpp_add_step_f64<0x143, 0xc, 0xf>(v);
+    v = dpp_add_step_f64<0x114, 0xf, 0xf>(v);
+    v = dpp_add_step_f64<0x118, 0xf, 0xf>(v);
+    v = dpp_add_step_f64<0x142, 0xf, 0xf>(v);
+    v = dpp_add_step_f64<0x143, 0xf, 0xf>(v);
     long long bits = __builtin_bit_cast(long long, v);
     int lo = __builtin_amdgcn_readlane((int)(bits & 0xffffffffLL), 63);
     int hi = __builtin_amdgcn_readlane((int)(bits >> 32), 63);
