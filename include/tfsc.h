@@ -232,9 +232,10 @@ tfsc_status tfsc_bank_statistic(const tfsc_grid *grid, const tfsc_pixels *pix, c
  * seg_terms[r * seg_stride + seg_offset[i] + s] (seg_stride >= the total
  * number of segments; terms at or beyond seg_stride are not written, so a
  * short plane loses terms but never overruns), flags[n] and n_active[n]
- * (optional) once.  WAVE schedule; LAYER_MAJOR or LAYER_MAJOR_CI; FP32
- * pixels with FP32 precision or FP64 pixels with FP64 precision, else
- * TFSC_ERR_DTYPE; no seg_zn (the VJP takes one realisation).  Sums are
+ * (optional) once.  WAVE schedule; LAYER_MAJOR or LAYER_MAJOR_CI; one or
+ * two channels (three: TFSC_ERR_UNSUPPORTED); FP32 pixels with FP32
+ * precision or FP64 pixels with FP64 precision, else TFSC_ERR_DTYPE; no
+ * seg_zn (the VJP takes one realisation).  Sums are
  * formed per bin rather than through the single-realisation kernel's
  * factored asymptotic sums, so the two agree to rounding, not bit for bit.
  * Needs TFSC_WS_STATISTIC workspace.                                       */
