@@ -99,3 +99,42 @@ def test_launch_shape_limits(L):
         opt = _lib.Options(1, 1, bw, gpc, None)
         assert L.tfsc_bank_statistic(ctypes.byref(g), ctypes.byref(pix), ctypes.byref(bank), ctypes.byref(seg),
                                      ctypes.byref(opt), p, p, None, p, None, p, 1 << 30, None) == 1
+
+
+def test_transform_tf_and_channel_argument_errors(L):
+    """Host-side checks of the per-pixel PSD transform and of the channel count (no device call is made)."""
+    from paper_2510_19047_amd import _lib
+    g = _grid()
+    dummy = ctypes.c_double(1.0)
+    keep = ctypes.c_uint8(1)
+    # a store without rho: invalid argument
+    pix = _lib.Pixels(1, 0, ctypes.addressof(dummy), None, ctypes.addressof(dummy), ctypes.addressof(dummy), None)
+    assert L.tfsc_transform_tf(ctypes.byref(g), ctypes.addressof(dummy), 1, ctypes.addressof(dummy),
+                               ctypes.addressof(keep), ctypes.byref(pix), None, 0, None) == 1
+    # FP64 store from FP32 samples: unsupported element-type combination
+    pix = _lib.Pixels(0, 0, ctypes.addressof(dummy), None, ctypes.addressof(dummy), ctypes.addressof(dummy),
+                      ctypes.addressof(dummy))
+    assert L.tfsc_transform_tf(ctypes.byref(g), ctypes.addressof(dummy), 1, ctypes.addressof(dummy),
+                               ctypes.addressof(keep), ctypes.byref(pix), None, 0, None) == 3
+    # no PSD
+    assert L.tfsc_transform_tf(ctypes.byref(g), ctypes.addressof(dummy), 0, None, ctypes.addressof(keep),
+                               ctypes.byref(pix), None, 0, None) == 1
+    # one to three channels; four is a shape error
+    assert L.tfsc_workspace_bytes(ctypes.byref(_grid(n_channels=3)), 10, None, _lib.WS_STATISTIC) > 0
+    assert L.tfsc_workspace_bytes(ctypes.byref(_grid(n_channels=4)), 10, None, _lib.WS_STATISTIC) == 0
+    bank = _lib.Bank(5)
+    seg = _lib.Segments(0, None, None)
+    assert L.tfsc_segment_layout(ctypes.byref(_grid(n_channels=4)), ctypes.byref(bank), ctypes.byref(seg), None, 0,
+                                 None) == 2
+
+
+def test_transform_tf_binding_checks_the_psd_shape():
+    import torch
+    import paper_2510_19047_amd as tfsc
+    grid = tfsc.GridSpec(2, 512, 100, 5.0, 0.1)
+    x = torch.zeros((2, 512 * 100), dtype=torch.float32)
+    keep = torch.ones(100, dtype=torch.uint8)
+    with pytest.raises(tfsc.TfscError):
+        tfsc.transform_tf(grid, x, torch.ones((100, 257), dtype=torch.float64), keep)  # transposed
+    with pytest.raises(tfsc.TfscError):
+        tfsc.transform_tf(grid, x, torch.ones((257, 100), dtype=torch.float32), keep)  # not float64
