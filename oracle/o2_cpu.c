@@ -32,7 +32,6 @@ enum { F_INVALID = 1, F_EMPTY = 2, F_BAND = 4, F_MERGE = 8, F_ALLEXCL = 16 };
 
 typedef struct {
     double M, c8, eta, a2, a3, a4, b2, b3, b4, tc;
-    double i5M, ic8, i40M, m2ieta; /* 1/(5M), 1/c8, 1/(40M), -2/eta */
 } tpl_t;
 
 static void tpl_init(tpl_t *T, double mc, double eta, double f0) {
@@ -64,29 +63,24 @@ static void tpl_init(tpl_t *T, double mc, double eta, double f0) {
     }
     double th2 = th * th, th4 = th2 * th2, th8 = th4 * th4;
     T->tc = (5.0 * T->M) / (eta * th8);
-    T->i5M = 1.0 / (5.0 * T->M);
-    T->ic8 = 1.0 / T->c8;
-    T->i40M = 1.0 / (40.0 * T->M);
-    T->m2ieta = -2.0 / eta;
 }
 
 static void tpl_at(const tpl_t *T, double t, double *Phi, double *f, double *fdot, double *A) {
     double tau = T->tc - t;
-    double q = (T->eta * tau) * T->i5M;
+    double q = (T->eta * tau) / (5.0 * T->M);
     double s = sqrt(sqrt(sqrt(q)));
     double th = 1.0 / s;
     double th2 = th * th, th3 = th2 * th, th4 = th2 * th2;
     double Pf = ((1.0 + T->a2 * th2) + T->a3 * th3) + T->a4 * th4;
-    *f = (th3 * T->ic8) * Pf;
+    *f = (th3 / T->c8) * Pf;
     double dPf = ((3.0 + (5.0 * T->a2) * th2) + (6.0 * T->a3) * th3) + (7.0 * T->a4) * th4;
-    double dfdth = (th2 * T->ic8) * dPf;
+    double dfdth = (th2 / T->c8) * dPf;
     double th8 = th4 * th4, th9 = th8 * th;
-    double dthdt = (T->eta * th9) * T->i40M;
+    double dthdt = (T->eta * th9) / (40.0 * T->M);
     *fdot = dfdth * dthdt;
     double Pp = ((1.0 + T->b2 * th2) + T->b3 * th3) + T->b4 * th4;
-    double s2 = s * s;
-    double thm5 = (s2 * s2) * s;
-    *Phi = (T->m2ieta * thm5) * Pp;
+    double thm5 = 1.0 / (th4 * th);
+    *Phi = -((2.0 * thm5) * Pp) / T->eta;
     *A = pow(*f, 2.0 / 3.0);
 }
 

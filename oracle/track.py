@@ -24,10 +24,10 @@ with M = Mc eta^(-3/5) in seconds (phi_c = 0).  Readings fixed here:
 * eta^(1/5) and the 0PN cube root are formed by fixed-count Newton
   iterations so that only +, -, *, / and sqrt decide the integer outputs
   (bin index, track end, N_seg); every operation is written in a fixed
-  order, without fused multiply-add.  Per template, 1/(5M), 1/c8, 1/(40M)
-  and -2/eta are formed once; the per-time evaluation multiplies by them,
-  takes theta = 1/s with s = [eta (t_c - t)/(5M)]^(1/8), and theta^-5 = s^5,
-  so it holds one division.
+  order, without fused multiply-add, as the formulas above read: the
+  divisions by 5M, 8 pi M, 40M and eta are divisions, theta = 1/s with
+  s = [eta (t_c - t)/(5M)]^(1/8) by three square roots, and
+  theta^-5 = 1/(theta^4 theta).
 * N_seg = clamp(2^round(log2(16 (fdot0 / 1.34e-12)^(1/3))), 16, 256),
   evaluated as 16 * 2^n with n the number of thresholds
   fdot0 >= 1.34e-12 * 2^(3i - 3/2), i = 1..4 (ties round up).
@@ -122,11 +122,6 @@ class Template:
         th4 = th2 * th2
         th8 = th4 * th4
         self.tc = (5.0 * self.M) / (self.eta * th8)
-        # per-template reciprocals: the per-time evaluation multiplies by them
-        self.i5M = 1.0 / (5.0 * self.M)
-        self.ic8 = 1.0 / self.c8
-        self.i40M = 1.0 / (40.0 * self.M)
-        self.m2ieta = -2.0 / self.eta
 
     def _solve_theta0(self):
         z = self.c8 * self.f0
@@ -144,35 +139,30 @@ class Template:
             th = th - F / (th2 * dP)
         return th
 
-    def inv_theta(self, t):
-        """s = 1/theta(t) = [eta (t_c - t) / (5 M)]^(1/8) by three square roots."""
-        tau = self.tc - _t(t)
-        q = (self.eta * tau) * self.i5M
-        return crsqrt(crsqrt(crsqrt(q)))
-
     def theta(self, t):
-        """theta(t) = [eta (t_c - t) / (5 M)]^(-1/8)."""
-        return 1.0 / self.inv_theta(t)
+        """theta(t) = [eta (t_c - t) / (5 M)]^(-1/8) by three square roots."""
+        tau = self.tc - _t(t)
+        q = (self.eta * tau) / (5.0 * self.M)
+        s = crsqrt(crsqrt(crsqrt(q)))
+        return 1.0 / s
 
     def at(self, t):
         """(Phi, f, fdot, A) at times t (valid for t < t_c)."""
-        s = self.inv_theta(t)
-        th = 1.0 / s
+        th = self.theta(t)
         th2 = th * th
         th3 = th2 * th
         th4 = th2 * th2
         Pf = ((1.0 + self.a2 * th2) + self.a3 * th3) + self.a4 * th4
-        f = (th3 * self.ic8) * Pf
+        f = (th3 / self.c8) * Pf
         dPf = ((3.0 + (5.0 * self.a2) * th2) + (6.0 * self.a3) * th3) + (7.0 * self.a4) * th4
-        dfdth = (th2 * self.ic8) * dPf
+        dfdth = (th2 / self.c8) * dPf
         th8 = th4 * th4
         th9 = th8 * th
-        dthdt = (self.eta * th9) * self.i40M
+        dthdt = (self.eta * th9) / (40.0 * self.M)
         fdot = dfdth * dthdt
         Pp = ((1.0 + self.b2 * th2) + self.b3 * th3) + self.b4 * th4
-        s2 = s * s
-        thm5 = (s2 * s2) * s
-        Phi = (self.m2ieta * thm5) * Pp
+        thm5 = 1.0 / (th4 * th)
+        Phi = -((2.0 * thm5) * Pp) / self.eta
         A = torch.pow(f, 2.0 / 3.0)
         return Phi, f, fdot, A
 

@@ -32,8 +32,19 @@ enum : int { kFlagInvalid = 1, kFlagEmpty = 2, kFlagBandEnd = 4, kFlagMergeEnd =
 // ------------------------------------------------------------------ track
 struct Track {
     double eta, M, c8, a2, a3, a4, b2, b3, b4, tc, th0;
-    double i5M, ic8, i40M, m2ieta;  // 1/(5M), 1/c8, 1/(40M), -2/eta
+    double M5, M40;               // 5M and 40M, each rounded once
+    double r5M, rc8, r40M, reta;  // correctly rounded 1/(5M), 1/c8, 1/(40M), 1/eta
 };
+
+// The correctly rounded quotient a/b from yb = RN(1/b): q = RN(a yb) is within an ulp of a/b,
+// the residual a - b q is exact in one FMA, and RN(q + r yb) is RN(a/b) (Markstein's theorem for
+// binary floating point with round-to-nearest, no underflow or overflow).  Three FP64
+// operations instead of a full division, with the same result bit for bit.
+__device__ __forceinline__ double div_rn(double a, double b, double yb) {
+    const double q = a * yb;
+    const double r = fma(-b, q, a);
+    return fma(r, yb, q);
+}
 
 __device__ __forceinline__ bool params_valid(double mc, double eta, double f0, double ct, double ci) {
     if (!(mc > 0.0) || !(eta >= 0.01) || !(eta <= 0.25) || !(f0 > 0.0)) return false;
@@ -75,32 +86,36 @@ __device__ inline void track_init(Track &T, double mc, double eta, double f0) {
     double th2 = th * th, th4 = th2 * th2, th8 = th4 * th4;
     T.tc = (5.0 * T.M) / (eta * th8);
     T.th0 = th;
-    T.i5M = 1.0 / (5.0 * T.M);
-    T.ic8 = 1.0 / T.c8;
-    T.i40M = 1.0 / (40.0 * T.M);
-    T.m2ieta = -2.0 / eta;
+    T.M5 = 5.0 * T.M;
+    T.M40 = 40.0 * T.M;
+    T.r5M = 1.0 / T.M5;
+    T.rc8 = 1.0 / T.c8;
+    T.r40M = 1.0 / T.M40;
+    T.reta = 1.0 / eta;
 }
 
-// Phase Phi (rad, phi_c = 0), GW frequency f and its derivative at time t < t_c.
-// One division per call (theta = 1/s); the per-template divisors enter as their
-// reciprocals, and theta^-5 = s^5.
+// Phase Phi (rad, phi_c = 0), GW frequency f and its derivative at time t < t_c, in the
+// operation order of the formulas: q = eta (t_c - t) / (5M), theta = 1 / q^(1/8) (three square
+// roots), f = (theta^3 / (8 pi M)) P_f, fdot = ((theta^2 / (8 pi M)) P_f') (eta theta^9 / (40M)),
+// Phi = -(2 theta^-5 P_phi) / eta with theta^-5 = 1 / (theta^4 theta).  Divisions by the
+// per-template constants 5M, 8 pi M, 40M and eta are formed by div_rn (the same correctly
+// rounded quotients); 1/s and 1/(theta^4 theta) are full divisions.
 __device__ inline void track_at(const Track &T, double t, double &Phi, double &f, double &fdot) {
     double tau = T.tc - t;
-    double q = (T.eta * tau) * T.i5M;
+    double q = div_rn(T.eta * tau, T.M5, T.r5M);
     double s = sqrt(sqrt(sqrt(q)));
     double th = 1.0 / s;
     double th2 = th * th, th3 = th2 * th, th4 = th2 * th2;
     double Pf = ((1.0 + T.a2 * th2) + T.a3 * th3) + T.a4 * th4;
-    f = (th3 * T.ic8) * Pf;
+    f = div_rn(th3, T.c8, T.rc8) * Pf;
     double dPf = ((3.0 + (5.0 * T.a2) * th2) + (6.0 * T.a3) * th3) + (7.0 * T.a4) * th4;
-    double dfdth = (th2 * T.ic8) * dPf;
+    double dfdth = div_rn(th2, T.c8, T.rc8) * dPf;
     double th8 = th4 * th4, th9 = th8 * th;
-    double dthdt = (T.eta * th9) * T.i40M;
+    double dthdt = div_rn(T.eta * th9, T.M40, T.r40M);
     fdot = dfdth * dthdt;
     double Pp = ((1.0 + T.b2 * th2) + T.b3 * th3) + T.b4 * th4;
-    double s2 = s * s;
-    double thm5 = (s2 * s2) * s;
-    Phi = (T.m2ieta * thm5) * Pp;
+    double thm5 = 1.0 / (th4 * th);
+    Phi = -div_rn((2.0 * thm5) * Pp, T.eta, T.reta);
 }
 
 // Track end (paper Appendix A compactness + band edge + merger): returns 0 if

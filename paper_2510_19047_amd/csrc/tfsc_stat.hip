@@ -800,10 +800,12 @@ __device__ __forceinline__ void wave_uniform(Track &T) {
     T.b4 = wave_uniform(T.b4);
     T.tc = wave_uniform(T.tc);
     T.th0 = wave_uniform(T.th0);
-    T.i5M = wave_uniform(T.i5M);
-    T.ic8 = wave_uniform(T.ic8);
-    T.i40M = wave_uniform(T.i40M);
-    T.m2ieta = wave_uniform(T.m2ieta);
+    T.M5 = wave_uniform(T.M5);
+    T.M40 = wave_uniform(T.M40);
+    T.r5M = wave_uniform(T.r5M);
+    T.rc8 = wave_uniform(T.rc8);
+    T.r40M = wave_uniform(T.r40M);
+    T.reta = wave_uniform(T.reta);
 }
 
 template <class R>
