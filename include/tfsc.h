@@ -168,9 +168,12 @@ size_t tfsc_workspace_bytes(const tfsc_grid *grid, int64_t n_templates, const tf
  * Writes out->pix (D = X sqrt(2 dt / (M W2 mu_m S0(f_k))), X the windowed
  * DFT with the tranche start as time origin, W2 = mean(w^2); excluded
  * tranches are 0), out->inv_asd, out->tranche_w, and out->layer_scale for
- * 16-bit stores (per layer max |component|, FP32).  out->dtype may be F64
- * (x F64 only), F32, BF16 or F16; 16-bit outputs need TFSC_WS_TRANSFORM
- * workspace.                                                               */
+ * 16-bit stores (per layer max |component|, FP32).  A pixel whose PSD
+ * mu_m S0(f_k) is not positive and finite (DC and Nyquist may be given as 0
+ * or inf; they never enter the statistic) is written as 0, and so is its
+ * weight (u_k = 0, or w_m = 0 when mu_m is not positive and finite), never
+ * inf or NaN.  out->dtype may be F64 (x F64 only), F32, BF16 or F16; 16-bit
+ * outputs need TFSC_WS_TRANSFORM workspace.                                */
 tfsc_status tfsc_transform(const tfsc_grid *grid, const void *x, int x_dtype, const double *psd0,
                            const double *tranche_psd_scale, const uint8_t *tranche_keep, tfsc_pixels *out,
                            void *ws, size_t ws_bytes, void *stream);
@@ -182,8 +185,10 @@ tfsc_status tfsc_transform(const tfsc_grid *grid, const void *x, int x_dtype, co
  * D_cmk = X_cmk sqrt(2 dt / (M W2 S_m(f_k))) (0 on excluded tranches), and
  * the template weights are written as u_k = 1/sqrt(S0_k) with S0_k the mean
  * of S_m(f_k) over the tranches, w_m = 1 (0 = excluded) and
- * rho_mk = sqrt(S0_k / S_m(f_k)) into out->rho, which must be set.  Same
- * dtypes, layouts and workspace as tfsc_transform.                         */
+ * rho_mk = sqrt(S0_k / S_m(f_k)) into out->rho, which must be set.  Where
+ * S_m(f_k) (or the layer's mean S0_k) is not positive and finite, the pixel
+ * and rho_mk (or u_k) are 0.  Same dtypes, layouts and workspace as
+ * tfsc_transform.                                                          */
 tfsc_status tfsc_transform_tf(const tfsc_grid *grid, const void *x, int x_dtype, const double *psd_tf,
                               const uint8_t *tranche_keep, tfsc_pixels *out, void *ws, size_t ws_bytes,
                               void *stream);

@@ -197,8 +197,9 @@ __global__ void k_geometry(int Nt, double dT, double *__restrict__ geo, float *_
 // invariant to it; it keeps |h u|^2 inside the FP32 range (u_k ~ 1e20 in strain units).
 __global__ void k_weight_scale(int K, const double *__restrict__ inv_asd, double *__restrict__ scale_out) {
     __shared__ double sh[256];
+    // bins 1 .. K - 2 only: DC and Nyquist never enter the statistic
     double v = 0.0;
-    for (int k = threadIdx.x; k < K; k += blockDim.x) {
+    for (int k = 1 + threadIdx.x; k < K - 1; k += blockDim.x) {
         double u = inv_asd[k];
         if (isfinite(u) && u > v) v = u;
     }

@@ -14,6 +14,8 @@
 
 namespace tfsc {
 
+__device__ __forceinline__ bool psd_ok(double S) { return S > 0.0 && S < __builtin_huge_val(); }
+
 template <class R>
 __device__ __forceinline__ R tukey_w(int n, int M, double alpha) {
     if (alpha <= 0.0) return (R)1;
@@ -81,7 +83,9 @@ __global__ __launch_bounds__(256) void k_transform(TransformLaunch L, double w2)
         const double mu = L.psd_tf ? 1.0 : L.mu[m];
         for (int k = threadIdx.x; k < K; k += blockDim.x) {
             const double S = L.psd_tf ? L.psd_tf[(size_t)k * Nt + m] : L.psd0[k] * mu;
-            double sc = keep ? sqrt(2.0 * L.dt / ((double)M * w2 * S)) : 0.0;
+            // a bin whose PSD is not positive and finite (DC or Nyquist may carry 0 or inf)
+            // gets pixel 0 rather than inf or NaN; its template weight is 0 as well
+            double sc = keep && psd_ok(S) ? sqrt(2.0 * L.dt / ((double)M * w2 * S)) : 0.0;
             tile[(size_t)k * TB + tt] = cscale(src[k], (R)sc);
         }
         __syncthreads();
@@ -155,8 +159,8 @@ __global__ void k_quantize(int C, int K, int Nt, int layout, const float *__rest
 __global__ void k_weights(int K, int Nt, const double *__restrict__ psd0, const double *__restrict__ mu,
                           const uint8_t *__restrict__ keep, double *__restrict__ inv_asd, double *__restrict__ tw) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < K) inv_asd[i] = 1.0 / sqrt(psd0[i]);
-    if (i < Nt) tw[i] = keep[i] ? 1.0 / sqrt(mu[i]) : 0.0;
+    if (i < K) inv_asd[i] = psd_ok(psd0[i]) ? 1.0 / sqrt(psd0[i]) : 0.0;
+    if (i < Nt) tw[i] = keep[i] && psd_ok(mu[i]) ? 1.0 / sqrt(mu[i]) : 0.0;
 }
 
 // Template weights for a per-pixel PSD S_m(f_k) (psd[K][Nt]): one block per bin k forms
@@ -177,8 +181,12 @@ __global__ __launch_bounds__(256) void k_weights_tf(int K, int Nt, const double 
         __syncthreads();
     }
     const double S0 = part[0] / (double)Nt;
-    if (threadIdx.x == 0) inv_asd[k] = 1.0 / sqrt(S0);
-    for (int m = threadIdx.x; m < Nt; m += blockDim.x) rho[(size_t)k * Nt + m] = (float)sqrt(S0 / row[m]);
+    // a layer whose mean PSD is not positive and finite (DC or Nyquist may carry 0 or inf), or a
+    // pixel whose own PSD is not, gets weight 0 (u_k or rho_mk), as its pixel is 0
+    const bool ok0 = psd_ok(S0);
+    if (threadIdx.x == 0) inv_asd[k] = ok0 ? 1.0 / sqrt(S0) : 0.0;
+    for (int m = threadIdx.x; m < Nt; m += blockDim.x)
+        rho[(size_t)k * Nt + m] = ok0 && psd_ok(row[m]) ? (float)sqrt(S0 / row[m]) : 0.0f;
     if (k == 0)
         for (int m = threadIdx.x; m < Nt; m += blockDim.x) tw[m] = keep[m] ? 1.0 : 0.0;
 }
