@@ -48,19 +48,22 @@ def parse():
     p.add_argument("--block-waves", type=int, default=0, help="fix the launch shape (0 = autotune)")
     p.add_argument("--groups-per-cu", type=int, default=0)
     p.add_argument("--no-order", action="store_true", help="process the bank in its own order")
-    p.add_argument("--batching", action="store_true",
-                   help="also time the batching workload: 4M wide-range templates over 16 noise realisations "
-                        "replayed from one HIP graph (adds about a minute)")
-    p.add_argument("--follow-up", action="store_true",
-                   help="also run the differentiation workload: 50 Adam steps on the top 65,536 templates of "
-                        "the batching bank (implies --batching)")
+    p.add_argument("--no-batching", action="store_true",
+                   help="skip the batching workload (4M wide-range templates over 16 noise realisations replayed "
+                        "from one HIP graph) and the differentiation workload that follows it")
+    p.add_argument("--no-follow-up", action="store_true",
+                   help="skip the differentiation workload (one VJP and 50 Adam steps on the top 65,536 "
+                        "templates of the batching bank)")
+    p.add_argument("--no-precision", action="store_true",
+                   help="skip the 16-bit pixel stores (FP16, BF16) of the precision form")
+    p.add_argument("--eight-per-pass", action="store_true",
+                   help="also time the several-realisation pass (eight realisations per pass over the bank)")
     p.add_argument("--background", action="store_true",
                    help="also build the background of the batching workload: per-tile maxima of the 16 "
-                        "realisations on an 8 x 8 (Mc, f0) tile grid, power-law and Gumbel tail fits "
-                        "(implies --batching)")
+                        "realisations on an 8 x 8 (Mc, f0) tile grid, power-law and Gumbel tail fits")
     p.add_argument("--ladder", action="store_true",
                    help="also run the segment ladder N_seg 16 -> 8 -> 4 -> 2 -> 1 (20 ascent steps per stage) "
-                        "on the top 65,536 templates of the batching bank (implies --batching)")
+                        "on the top 65,536 templates of the batching bank")
     p.add_argument("--psd-tf", action="store_true",
                    help="also time the chosen form with a PSD that varies between tranches in a general way "
                         "(per-pixel whitening and weights), with sampled parity against the oracle")
@@ -69,17 +72,40 @@ def parse():
                         "2-yr grid and bank, with sampled parity against the oracle")
     p.add_argument("--copy-calibration", action="store_true",
                    help="copy 256 MiB device-to-device once, so profiler byte counters can be calibrated")
+    p.add_argument("--summarize-counters", nargs="+", metavar="DIR",
+                   help="no GPU run: write profiles/k_stat_wave_counters.txt from rocprofv3 --pmc CSV directories "
+                        "of this bench's chosen statistic launch (with --templates, --chosen-store, "
+                        "--chosen-layout, --block-waves, --groups-per-cu as profiled)")
+    p.add_argument("--fetch-factor", type=float, default=2.0,
+                   help="bytes per FETCH_SIZE KiB / 1024 from the copy calibration")
+    p.add_argument("--write-factor", type=float, default=1.0,
+                   help="bytes per WRITE_SIZE KiB / 1024 from the copy calibration")
     return p.parse_args()
 
 
 def main():
     args = parse()
+    if args.summarize_counters:
+        n = args.templates + 20
+        summarize_counters(args.summarize_counters, n, args.chosen_store, args.chosen_layout,
+                           "bank" if args.no_order else "f0 bin", f"{args.block_waves}x{args.groups_per_cu}",
+                           args.fetch_factor, args.write_factor)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (asked for {args.gpus}): templates shard across GPUs with no "
               f"exchange in the hot loop, and the benchmark measures one GPU's throughput only", file=sys.stderr)
         sys.exit(2)
     import torch
     import tfsc_inputs as ti
+    noise_jobs = None
+    if not args.no_batching:
+        # the batching workload's 16 noise realisations are drawn on the host by worker processes forked
+        # here, before this process touches the GPU; they run while the GPU works on the rest
+        import multiprocessing as mp
+        from concurrent.futures import ProcessPoolExecutor
+        workers = max(1, min(8, len(os.sched_getaffinity(0)) // 2))
+        pool = ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("fork"))
+        noise_jobs = (pool, [pool.submit(_noise_realisation, r) for r in range(16)], workers)
     import paper_2510_19047_amd as tfsc
     tfsc.lib()
     dev = torch.device("cuda:0")
@@ -196,14 +222,31 @@ def main():
     torch.cuda.synchronize()
     plain_k_ms = ev[0].elapsed_time(ev[1])
 
-    # agreement of the two forms (and of the chosen form with the FP64 path on a subsample)
+    # agreement of the two forms
     sc, sp = res_c.stat.cpu().numpy(), res_p.stat.cpu().numpy()
     rel_cp = float(np.max(np.abs(sc - sp) / np.maximum(np.abs(sp), 1.0)))
 
-    traffic, traffic_shape, valu_insts = measured_traffic(n, args.chosen_store, args.chosen_layout,
-                                                          "bank" if order is None else "f0 bin")
-    # vector-ALU issue: a wave64 VALU instruction occupies a 16-lane SIMD for 4 cycles; 1,024 SIMDs at 2.4 GHz
-    valu_frac = None if valu_insts is None else valu_insts * 4.0 / (1024 * 2.4e9) / (k_ms / 1e3)
+    # ---------------- the roofs: vector-ALU issue binds; HBM and algorithmic bytes reported beside it
+    prof = measured_profile(n, args.chosen_store, args.chosen_layout, "bank" if order is None else "f0 bin")
+    k_s = k_ms / 1e3
+    roofline = alu_roofline(prof, k_s)
+    traffic = None if prof is None else prof.get("traffic_bytes")
+    roofline.update({
+        "traffic": traffic,
+        "kernel": "k_stat_wave",
+        "kernel_ms": round(k_ms, 3),
+        "profile_launch_shape": None if prof is None else prof.get("launch_shape"),
+        "alg_bytes_per_launch": alg_bytes,
+        "alg_gbs": round(achieved, 1),
+        "alg_bytes_over_hbm_peak": round(achieved / HBM_PEAK_GBS, 4),
+        "alg_bytes_note": "algorithmic gathered bytes per launch / kernel time / 8 TB/s; the 100 MB pixel store "
+                          "is reused by the templates in flight and served from L2 and the Infinity Cache, so this "
+                          "ratio is not an HBM fraction",
+        "hbm": None if traffic is None else {
+            "beyond_l2_bytes": traffic, "gbs": round(traffic / k_s / 1e9, 1),
+            "frac_of_8tbs": round(traffic / k_s / 1e9 / HBM_PEAK_GBS, 4),
+            "note": "calibrated FETCH_SIZE + WRITE_SIZE (bytes beyond L2, Infinity-Cache hits included)"},
+    })
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -228,19 +271,7 @@ def main():
             "order": "bank" if order is None else "f0 bin",
             "step": "transform + segment layout + processing order + bank statistic",
         },
-        "roofline": {
-            "bound": "hbm",
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
-            "traffic_launch_shape": traffic_shape,
-            "valu_issue_frac": None if valu_frac is None else round(valu_frac, 4),
-            "kernel": "k_stat_wave",
-            "kernel_ms": round(k_ms, 3),
-            "alg_bytes_per_launch": alg_bytes,
-        },
+        "roofline": roofline,
         "forms": {
             "chosen": {"templates_per_s": round(value, 1), "kernel_ms": round(k_ms, 3),
                        "store": f"{args.chosen_store} {args.chosen_layout}",
@@ -250,24 +281,92 @@ def main():
                       "schedule": "thread-per-template"},
             "chosen_over_plain": round(value / plain_value, 3),
             "max_rel_diff_chosen_vs_plain": rel_cp,
-            "hbm_frac_f32_bytes": round(alg_bytes_f32 / (k_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
         },
     }
 
-    # ---------------- CPU baseline: the plain-C oracle on host cores, bounded sample
+    # ---------------- accuracy against the FP64 oracle (outside the timed region): 10k-template subsample
+    log("oracle: transform of the same data and the plain-C FP64 statistic on a 10,000-template subsample")
+    from oracle import cpu as ocpu
+    from oracle import transform as otf
+    pix_o, u_o, wm_o = otf.transform(x.astype(np.float64), g, psd, mu, keep, 0.1, "rfft")
+    sub_idx = ti.subsample_indices(n, min(10_000, n), must_include=np.arange(max(0, n - 20), n), cfg_id=13)
+    threads = len(os.sched_getaffinity(0))
+    t0 = time.perf_counter()
+    ref = ocpu.statistic(pix_o, u_o, wm_o, bank_h.subset(sub_idx), g, threads=threads)
+    log(f"oracle: {len(sub_idx)} templates in {time.perf_counter() - t0:.1f} s on {threads} threads")
+    flags_c = res_c.flags.cpu().numpy()
+    out["forms"]["chosen"]["vs_oracle"] = accuracy(sc[sub_idx], flags_c[sub_idx], ref)
+    out["forms"]["plain"]["vs_oracle"] = accuracy(sp[sub_idx], res_p.flags.cpu().numpy()[sub_idx], ref)
+    log(f"chosen vs oracle: {out['forms']['chosen']['vs_oracle']}")
+
+    # ---------------- precision form: 16-bit pixel stores with a per-layer FP32 scale
+    if not args.no_precision:
+        del pix_plain
+        out["forms"]["precision"] = precision_run(args, tfsc, grid, x_d, psd_d, mu_d, keep_d, bank, seg, order, kw,
+                                                  res_c, sub_idx, ref, value)
+
     if args.aet:
         out["aet"] = aet_run(args, tfsc, ti, g, psd_d, mu_d, keep_d, bank, bank_h, seg, order, kw, pix_cols, value,
                              k_ms)
     if args.psd_tf:
         out["psd_tf"] = psd_tf_run(args, tfsc, ti, grid, g, x, x_d, keep_d, bank, bank_h, seg, order, kw, pix_cols,
                                    value, k_ms)
-    if args.batching or args.follow_up or args.background or args.ladder:
-        del res, res_c, res_p, pix_plain
+    if not args.no_batching:
+        del res, res_c, res_p
         torch.cuda.empty_cache()
-        out["batching"] = batching_run(args, tfsc, ti, grid, g, psd_d, mu_d, keep_d, kw)
+        out["forms"]["batching"] = batching_run(args, tfsc, ti, grid, g, psd_d, mu_d, keep_d, kw, k_ms / n, noise_jobs)
+    # ---------------- CPU baseline: the oracle on host cores, bounded samples
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(g, x, psd, mu, keep, bank_h, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(g, pix_o, u_o, wm_o, bank_h, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def accuracy(stat, flags, ref):
+    """|Upsilon - Upsilon_oracle| / max(Upsilon_oracle, 1) over a sample, and whether the flags agree."""
+    r = np.abs(stat - ref.stat) / np.maximum(np.abs(ref.stat), 1.0)
+    return {"templates": int(r.size), "max_rel": float(r.max()), "p99_rel": float(np.quantile(r, 0.99)),
+            "median_rel": float(np.median(r)), "flags_equal": bool(np.array_equal(flags, ref.flags))}
+
+
+def precision_run(args, tfsc, grid, x_d, psd_d, mu_d, keep_d, bank, seg, order, kw, res_c, sub_idx, ref, value_f32):
+    """FP16 and BF16 stores (per-layer FP32 scale, FP32 accumulation, FP64 track): templates/s of the same step
+    and the error of every template of the 10k subsample against the FP64 oracle."""
+    import torch
+    out = {}
+    n = bank.n
+    for dt in ("f16", "bf16"):
+        pix = tfsc.transform(grid, x_d, psd_d, mu_d, keep_d, dtype=dt, layout=args.chosen_layout)
+
+        def step():
+            tfsc.transform(grid, x_d, psd_d, mu_d, keep_d, dtype=dt, layout=args.chosen_layout, out=pix)
+            tfsc.segment_layout(grid, bank, out=seg, read_total=False)
+            o = None if order is None else tfsc.processing_order(grid, bank, out=order)
+            return tfsc.bank_statistic(grid, pix, bank, seg, precision="f32", schedule="wave", out=res_c, order=o,
+                                       **kw)
+
+        step()
+        torch.cuda.synchronize()
+        reps = max(2, args.steps // 2)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            step()
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / reps
+        st = torch.cuda.current_stream()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(st)
+        tfsc.bank_statistic(grid, pix, bank, seg, precision="f32", schedule="wave", out=res_c, order=order, **kw)
+        ev[1].record(st)
+        torch.cuda.synchronize()
+        s = res_c.stat.cpu().numpy()
+        acc = accuracy(s[sub_idx], res_c.flags.cpu().numpy()[sub_idx], ref)
+        out[dt] = {"templates_per_s": round(n / (ms / 1e3), 1), "ms_per_step": round(ms, 3),
+                   "kernel_ms": round(ev[0].elapsed_time(ev[1]), 3), "over_f32": round(n / (ms / 1e3) / value_f32, 4),
+                   "store": f"{dt} {args.chosen_layout} + per-layer f32 scale", "arith": "f32 (track f64)",
+                   "vs_oracle": acc}
+        log(f"precision {dt}: {ms:.2f} ms/step, {n / (ms / 1e3) / 1e6:.3f} M templates/s; vs oracle {acc}")
+        del pix
+    return out
 
 
 def aet_run(args, tfsc, ti, g, psd_d, mu_d, keep_d, bank, bank_h, seg, order, kw, pix_cols, value_ae, k_ms_ae):
@@ -397,21 +496,32 @@ def psd_tf_run(args, tfsc, ti, grid, g, x, x_d, keep_d, bank, bank_h, seg, order
             "sampled_parity": {"templates": len(idx), "max_rel_vs_oracle": float(r.max())}}
 
 
-def batching_run(args, tfsc, ti, grid, g, psd_d, mu_d, keep_d, kw):
-    """4M wide-range templates x 16 realisations in one HIP graph; optionally the Adam follow-up."""
+def _noise_realisation(r):
+    """Realisation r of the full-size noise with the gaps applied, FP32 (a worker process's job)."""
+    import tfsc_inputs as ti
+    g = ti.FULL
+    return (ti.noise(g, realisation=r) * ti.sample_keep_mask(g)[None, :]).astype(np.float32)
+
+
+def batching_run(args, tfsc, ti, grid, g, psd_d, mu_d, keep_d, kw, chosen_ms_per_template, noise_jobs):
+    """4M wide-range templates x 16 realisations in one HIP graph; then the differentiation workload."""
     import torch
     from paper_2510_19047_amd import batching
     dev = psd_d.device
-    R = 16
+    pool, jobs, workers = noise_jobs
+    R = len(jobs)
     log("batching: 4M-template bank and 16 noise realisations")
     bank_h = ti.batching_bank()
     bank = tfsc.BankTensors.from_host(bank_h, dev)
     seg = tfsc.segment_layout(grid, bank)
     order = tfsc.processing_order(grid, bank)
-    keepm = ti.sample_keep_mask(g)[None, :]
     xs = torch.empty((R, g.n_channels, g.n_samples), dtype=torch.float32, device=dev)
-    for r in range(R):
-        xs[r] = torch.from_numpy((ti.noise(g, realisation=r) * keepm).astype(np.float32)).to(dev)
+    t0 = time.perf_counter()
+    for r, job in enumerate(jobs):
+        xs[r] = torch.from_numpy(job.result()).to(dev)
+    pool.shutdown()
+    log(f"batching: {R} realisations in device memory after {time.perf_counter() - t0:.1f} s more "
+        f"({workers} host processes)")
     evals = bank.n * R
 
     def timed_replay(rg, reps=3):
@@ -432,20 +542,26 @@ def batching_run(args, tfsc, ti, grid, g, psd_d, mu_d, keep_d, kw):
     wall = timed_replay(rg)
     log(f"batching: one replay {wall * 1e3:.1f} ms (median of 3), {evals / wall / 1e6:.3f} M template-realisations/s "
         f"(one statistic launch per realisation)")
-    rec = {"templates": bank.n, "realisations": R, "ms_per_replay": round(wall * 1e3, 2),
-           "template_realisations_per_s": round(evals / wall, 1), "graph": "transform + statistic x 16"}
-    # the several-realisation alternative: eight realisations per pass over the bank
-    rgm = batching.RealisationGraph(grid, xs, psd_d, mu_d, keep_d, bank, seg, store="f32", layout=args.chosen_layout,
-                                    precision="f32", order=order, multi=True, group=8, **kw)
-    wm = timed_replay(rgm, reps=1)
-    d0 = float(torch.max(torch.abs(rgm.results[0].stat - rg.results[0].stat)
-                         / torch.clamp(rg.results[0].stat.abs(), min=1.0)))
-    log(f"batching: one replay {wm * 1e3:.1f} ms, {evals / wm / 1e6:.3f} M template-realisations/s "
-        f"(eight realisations per pass over the bank); realisation 0 agrees to {d0:.1e}")
-    rec["eight_per_pass"] = {"ms_per_replay": round(wm * 1e3, 2), "template_realisations_per_s": round(evals / wm, 1),
-                             "max_rel_diff_vs_one_per_launch": d0}
-    del rgm
-    torch.cuda.empty_cache()
+    rec = {"workload": "4M templates (Mc log-U[5, 100], f0 U[5, 50] mHz, 48% merging in the window) x 16 noise "
+                       "realisations of the 2-yr A+E data",
+           "templates": bank.n, "realisations": R, "ms_per_replay": round(wall * 1e3, 2),
+           "template_realisations_per_s": round(evals / wall, 1), "graph": "transform + statistic x 16",
+           "store": f"f32 {args.chosen_layout}", "arith": "f32 (track f64)"}
+    if args.eight_per_pass:
+        # the several-realisation alternative: eight realisations per pass over the bank
+        rgm = batching.RealisationGraph(grid, xs, psd_d, mu_d, keep_d, bank, seg, store="f32",
+                                        layout=args.chosen_layout, precision="f32", order=order, multi=True, group=8,
+                                        **kw)
+        wm = timed_replay(rgm, reps=1)
+        d0 = float(torch.max(torch.abs(rgm.results[0].stat - rg.results[0].stat)
+                             / torch.clamp(rg.results[0].stat.abs(), min=1.0)))
+        log(f"batching: one replay {wm * 1e3:.1f} ms, {evals / wm / 1e6:.3f} M template-realisations/s "
+            f"(eight realisations per pass over the bank); realisation 0 agrees to {d0:.1e}")
+        rec["eight_per_pass"] = {"ms_per_replay": round(wm * 1e3, 2),
+                                 "template_realisations_per_s": round(evals / wm, 1),
+                                 "max_rel_diff_vs_one_per_launch": d0}
+        del rgm
+        torch.cuda.empty_cache()
     if args.background:
         from paper_2510_19047_amd import background as bg
         n_m, n_f = 8, 8
@@ -484,7 +600,7 @@ def batching_run(args, tfsc, ti, grid, g, psd_d, mu_d, keep_d, kw):
             f"Upsilon_1 median {np.median(u1):.2f}")
         rec["ladder"] = {"templates": 65536, "steps_per_stage": 20, "wall_s": round(wall, 3), "stages": stages,
                          "upsilon1_median": round(float(np.median(u1)), 3), "upsilon1_p90": round(float(np.quantile(u1, 0.9)), 3)}
-    if args.follow_up:
+    if not args.no_follow_up:
         stat0 = rg.results[0].stat
         top = torch.topk(torch.nan_to_num(stat0, nan=-1.0), 65536).indices
         sub = tfsc.BankTensors(*(getattr(bank, k)[top].contiguous() for k in tfsc.BankTensors.FIELDS))
@@ -507,6 +623,8 @@ def batching_run(args, tfsc, ti, grid, g, psd_d, mu_d, keep_d, kw):
         log(f"follow-up candidates: statistic {f_ms:.1f} ms, VJP {v_ms:.1f} ms for 65536 templates "
             f"({65536 / v_ms * 1e3 / 1e6:.3f} M templates/s)")
         rec["vjp"] = {"templates": 65536, "statistic_ms": round(f_ms, 3), "vjp_ms": round(v_ms, 3),
+                      "vjp_over_statistic": round(v_ms / f_ms, 3),
+                      "vjp_over_chosen_per_template": round(v_ms / 65536 / chosen_ms_per_template, 3),
                       "vjp_templates_per_s": round(65536 / v_ms * 1e3, 1), "arith": "f64"}
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -516,65 +634,210 @@ def batching_run(args, tfsc, ti, grid, g, psd_d, mu_d, keep_d, kw):
         gain = (best - first).cpu().numpy()
         log(f"follow-up: 50 Adam steps on 65536 templates in {wall:.2f} s; gain median {np.median(gain):.2f}, "
             f"p90 {np.quantile(gain, 0.9):.2f}")
-        rec["follow_up"] = {"templates": 65536, "steps": 50, "wall_s": round(wall, 3),
+        rec["follow_up"] = {"workload": "top 65,536 templates of realisation 0 of the batching workload",
+                            "templates": 65536, "steps": 50, "wall_s": round(wall, 3),
                             "gain_median": round(float(np.median(gain)), 3),
                             "gain_p90": round(float(np.quantile(gain, 0.9)), 3),
                             "start_median": round(float(first.median().item()), 3)}
     return rec
 
 
-def measured_traffic(n, store, layout, order):
-    """Calibrated bytes beyond L2 (and VALU instructions) per k_stat_wave launch from the committed rocprofv3
-    counter runs.
+PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "k_stat_wave_counters.txt")
+STAT_SOURCES = ("tfsc_stat.hip", "tfsc_device.hpp", "tfsc_kernels.hpp")
+SIMDS = 1024                  # 256 CUs x 4 SIMDs
+NOMINAL_CLOCK_HZ = 2.4e9
+CYCLES_PER_VALU = 4           # a wave64 instruction on a 16-lane SIMD
 
-    Only valid while the kernel source, the bank, the store, its layout and the processing order are the ones
-    that were profiled; otherwise None.  The launch shape the counters were taken with is returned
-    beside it (the autotuner's choice can differ between boxes by timings within noise).
-    """
+
+def stat_source_sha256():
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
-    path = os.path.join(root, "profiles", "k_stat_wave_traffic.txt")
-    if not os.path.exists(path):
-        return None, None, None
+    h = hashlib.sha256()
+    for f in STAT_SOURCES:
+        with open(os.path.join(root, "paper_2510_19047_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_profile(n, store, layout, order):
+    """Per-launch hardware counters of the chosen k_stat_wave launch from the committed rocprofv3 runs
+    (written by ``bench.py --summarize-counters``): calibrated bytes beyond L2, VALU instructions, the shader
+    clock (GRBM_GUI_ACTIVE over the dispatch time) and the FP32/FP64 operation counts.
+
+    Only valid while the kernel source, the bank, the store, its layout and the processing order are the ones
+    that were profiled; otherwise None.
+    """
+    if not os.path.exists(PROFILE):
+        return None
     rec = {}
-    with open(path) as fh:
+    with open(PROFILE) as fh:
         for line in fh:
             if line.strip() and not line.startswith("#") and ":" in line:
                 k, v = line.split(":", 1)
                 rec[k.strip()] = v.strip()
-    h = hashlib.sha256()
-    for f in ("tfsc_stat.hip", "tfsc_device.hpp", "tfsc_kernels.hpp"):
-        with open(os.path.join(root, "paper_2510_19047_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    same = (rec.get("source_sha256") == h.hexdigest() and rec.get("n_templates") == str(n)
-            and rec.get("pixel_store") == store and rec.get("pixel_layout", "layer") == layout
-            and rec.get("order") == order)
+    same = (rec.get("source_sha256") == stat_source_sha256() and rec.get("n_templates") == str(n)
+            and rec.get("pixel_store") == store and rec.get("pixel_layout") == layout and rec.get("order") == order)
     if not same:
-        return None, None, None
-    valu = float(rec["valu_insts"]) if "valu_insts" in rec else None
-    return float(rec["traffic_bytes"]), rec.get("launch_shape"), valu
+        return None
+    out = {}
+    for k, v in rec.items():
+        try:
+            out[k] = float(v)
+        except ValueError:
+            out[k] = v
+    return out
 
 
-def cpu_baseline(g, x, psd, mu, keep, bank_h, seconds):
+def alu_roofline(prof, k_s):
+    """The binding roof of the chosen kernel: vector-ALU issue.  achieved = VALU wave instructions per launch
+    (counters of the same source and workload) / the launch time measured here; peak = 1,024 SIMDs x clock /
+    4 cycles per wave64 instruction, with the shader clock measured in the counter run (GRBM_GUI_ACTIVE per
+    dispatch time).  The FP32/FP64 operation counts give the arithmetic rate beside it against the non-packed
+    vector peak (64 FMA lanes per CU and cycle for FP32 and FP64 alike: 78.6 TFLOP/s at 2.4 GHz)."""
+    rec = {"bound": "alu", "unit": "G VALU instr/s", "achieved": None, "peak": None, "frac": None}
+    if prof is None or "valu_insts" not in prof:
+        rec["note"] = "no counter profile of this kernel source and workload; run the rocprofv3 passes"
+        return rec
+    clock = prof.get("clock_hz", NOMINAL_CLOCK_HZ)
+    peak = SIMDS * clock / CYCLES_PER_VALU
+    ach = prof["valu_insts"] / k_s
+    rec.update({"achieved": round(ach / 1e9, 2), "peak": round(peak / 1e9, 2), "frac": round(ach / peak, 4),
+                "clock_ghz": round(clock / 1e9, 4),
+                "peak_nominal_2p4ghz": round(SIMDS * NOMINAL_CLOCK_HZ / CYCLES_PER_VALU / 1e9, 2),
+                "valu_insts_per_launch": prof["valu_insts"]})
+    if "valu_active_frac" in prof:
+        rec["valu_busy_frac_counter_run"] = prof["valu_active_frac"]
+    if "flops" in prof:
+        tf = prof["flops"] / k_s / 1e12
+        peak_tf = SIMDS * 16 * 2 * clock / 1e12
+        rec["flops"] = {"per_launch": prof["flops"], "tflops": round(tf, 3), "peak_tflops": round(peak_tf, 2),
+                        "frac": round(tf / peak_tf, 4),
+                        "note": "64 x (ADD + MUL + 2 FMA + TRANS) over the FP32 and FP64 VALU instructions"}
+    return rec
+
+
+def summarize_counters(dirs, n, store, layout, order, shape, fetch_factor, write_factor):
+    """Write profiles/k_stat_wave_counters.txt from rocprofv3 --pmc CSV outputs (one directory per pass):
+    the median per dispatch of each counter over the chosen k_stat_wave launches after the first."""
+    import csv
+    import glob
+    vals = {}
+    durs = []
+    for d in dirs:
+        for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(path) as fh:
+                rows = list(csv.DictReader(fh))
+            by_disp = {}
+            for row in rows:
+                name = row.get("Kernel_Name", "")
+                if "k_stat_wave<2, float, float, 2, false>" not in name:
+                    continue
+                by_disp.setdefault(int(row["Dispatch_Id"]), []).append(row)
+            for disp in sorted(by_disp)[1:]:
+                for row in by_disp[disp]:
+                    vals.setdefault(row["Counter_Name"], []).append(float(row["Counter_Value"]))
+                r0 = by_disp[disp][0]
+                if "Start_Timestamp" in r0 and "End_Timestamp" in r0:
+                    durs.append(float(r0["End_Timestamp"]) - float(r0["Start_Timestamp"]))
+    med = {k: float(np.median(v)) for k, v in vals.items()}
+    lines = ["# Read by bench.py: per-launch counters of the chosen k_stat_wave launch (median over the dispatches",
+             "# after the first), valid only for this kernel source and workload; written by",
+             "# python bench.py --summarize-counters <rocprofv3 --pmc output directories>",
+             "kernel: k_stat_wave<2, float, float, 2, false>",
+             f"source_sha256: {stat_source_sha256()}", f"n_templates: {n}", f"pixel_store: {store}",
+             f"pixel_layout: {layout}", f"order: {order}", f"launch_shape: {shape}"]
+    for k in sorted(med):
+        lines.append(f"{k}: {med[k]:.6e}")
+    if durs:
+        dur = float(np.median(durs))
+        lines.append(f"dispatch_ns_counter_run: {dur:.6e}")
+        if "GRBM_GUI_ACTIVE" in med:
+            clk = med["GRBM_GUI_ACTIVE"] / (dur * 1e-9)
+            # GRBM_GUI_ACTIVE is summed over the eight XCDs when the profiler reports it per device
+            if clk > 4e9:
+                clk /= 8.0
+            lines.append(f"clock_hz: {clk:.6e}")
+            if "SQ_ACTIVE_INST_VALU" in med:
+                lines.append(f"valu_active_frac: {med['SQ_ACTIVE_INST_VALU'] * 4 / SIMDS / (clk * dur * 1e-9):.4f}")
+    if "SQ_INSTS_VALU" in med:
+        lines.append(f"valu_insts: {med['SQ_INSTS_VALU']:.6e}")
+    if "FETCH_SIZE" in med and "WRITE_SIZE" in med:
+        tb = med["FETCH_SIZE"] * 1024 * fetch_factor + med["WRITE_SIZE"] * 1024 * write_factor
+        lines += [f"fetch_factor: {fetch_factor:.3f}", f"write_factor: {write_factor:.3f}", f"traffic_bytes: {tb:.6e}"]
+    ops = [k for k in med if k.startswith("SQ_INSTS_VALU_") and (k.endswith("_F32") or k.endswith("_F64"))]
+    if ops:
+        fl = 0.0
+        for k in ops:
+            w = 2.0 if "_FMA_" in k else 1.0
+            fl += 64.0 * w * med[k]
+        lines.append(f"flops: {fl:.6e}")
+    with open(PROFILE, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(g, pix, u, wm, bank_h, seconds):
+    """The FP64 oracle on the host: the plain-C O2 statistic on all cores and on one core (the paper's own CPU
+    comparison is one core), on bounded samples of the same bank, and O1 (the definition: time-domain
+    synthesis and direct DFT) on two templates over a 256-tranche span, extrapolated by samples."""
+    import torch
     from oracle import cpu as ocpu
-    from oracle import transform as otf
     import tfsc_inputs as ti
-    log("cpu baseline: oracle transform of the same data")
-    pix, u, wm = otf.transform(x.astype(np.float64), g, psd, mu, keep, 0.1, "rfft")
     threads = len(os.sched_getaffinity(0))
-    idx = ti.subsample_indices(len(bank_h), 256, cfg_id=12)
+
+    def timed(n_s, nthreads, cfg_id):
+        idx = ti.subsample_indices(len(bank_h), n_s, cfg_id=cfg_id)
+        t0 = time.perf_counter()
+        ocpu.statistic(pix, u, wm, bank_h.subset(idx), g, threads=nthreads)
+        return time.perf_counter() - t0
+
+    t_cal = timed(256, threads, 12)
+    n_all = int(min(len(bank_h), max(256, 256 * seconds / max(t_cal, 1e-3))))
+    log(f"cpu baseline: {n_all} templates on {threads} threads")
+    t_all = timed(n_all, threads, 12)
+    n_one = int(max(16, 256 * (seconds / 3) / max(t_cal * threads, 1e-3)))
+    log(f"cpu baseline: {n_one} templates on 1 thread")
+    t_one = timed(n_one, 1, 14)
+    # O1 on a 256-tranche span of the same grid (its cost grows with the samples synthesised)
+    from oracle import o1
+    from oracle import track as otrk
+    span = 256
+    gs = ti.GridSpec("full-span", g.cfg_id, g.n_channels, g.dt, g.tranche_len, span, g.modulated, g.gapped)
+    idx = ti.subsample_indices(len(bank_h), 2, cfg_id=15)
+    sub = bank_h.subset(idx)
+    lay = otrk.Layout(sub, gs)
     t0 = time.perf_counter()
-    ocpu.statistic(pix, u, wm, bank_h.subset(idx), g, threads=threads)
-    t_cal = time.perf_counter() - t0
-    n_s = int(min(len(bank_h), max(256, 256 * seconds / max(t_cal, 1e-3))))
-    idx = ti.subsample_indices(len(bank_h), n_s, cfg_id=12)
-    log(f"cpu baseline: {n_s} templates on {threads} threads")
-    t0 = time.perf_counter()
-    ocpu.statistic(pix, u, wm, bank_h.subset(idx), g, threads=threads)
-    t = time.perf_counter() - t0
-    return {"value": round(n_s / t, 1), "unit": "templates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n_s} templates drawn from the same bank (seeded permutation), plain-C FP64 oracle with "
-                      f"OpenMP over templates, statistic only (pixels from the oracle's own transform), {t:.1f} s"}
+    for i in range(len(idx)):
+        Y = o1.template_pixels(sub, i, gs, u, wm[:span])
+        o1.statistic_from_pixels(pix[:, :, :span], Y, o1.bin_mask(gs, lay, i), int(lay.nseg[i]), span)
+    t_o1 = (time.perf_counter() - t0) / len(idx)
+    per_tpl_o1 = t_o1 * g.n_tranches / span
+    return {"value": round(n_all / t_all, 1), "unit": "templates/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"{n_all} templates drawn from the same bank (seeded permutation), plain-C FP64 O2 oracle with "
+                      f"OpenMP over templates, statistic only (pixels from the oracle's own transform), {t_all:.1f} s",
+            "one_core": {"value": round(n_one / t_one, 2), "unit": "templates/s", "cores": 1,
+                         "us_per_template": round(1e6 * t_one / n_one, 1),
+                         "sample": f"{n_one} other templates of the same bank on one thread, {t_one:.1f} s"},
+            "o1_definition": {"s_per_template": round(per_tpl_o1, 2), "threads": torch.get_num_threads(),
+                              "sample": f"2 templates, time-domain synthesis of A and E plus direct DFT over the "
+                                        f"first {span} of {g.n_tranches} tranches ({t_o1:.2f} s each), scaled by "
+                                        f"{g.n_tranches / span:.0f} to the 2-yr span"},
+            "paper_context": "paper: 1-10 us per statistic evaluation on one A100 (about 1e5-1e6 per s), 2680 tiles x "
+                             "1e8 evaluations in 11 days on 4 A100 (about 7e4 per s per GPU end to end), a search "
+                             "within a day on about 40 GPUs; its CPU comparison is one core of a 2.4 GHz Xeon "
+                             "Platinum"}
 
 
 if __name__ == "__main__":
