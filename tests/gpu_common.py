@@ -9,6 +9,8 @@ import torch
 
 import tfsc_inputs as ti
 from oracle import cpu as ocpu
+from oracle import o2
+from oracle import track as otrk
 from oracle import transform as otf
 
 
@@ -80,3 +82,33 @@ def store_from_oracle(d, dtype="f64", layout="layer"):
 def rel(a, b):
     a, b = np.asarray(a, np.float64), np.asarray(b, np.float64)
     return np.abs(a - b) / np.maximum(np.abs(b), 1.0)
+
+
+@functools.lru_cache(maxsize=1)
+def full_injected():
+    """The full-size data (2-yr A+E, gaps, modulated PSD; noise stream 0) with the 20 injections of the full-size
+    configuration added in the pixel domain (the oracle's own template pixels, phase-shifted and scaled to their
+    target SNR): oracle pixels, weights and the injection parameters."""
+    g = ti.FULL
+    note("full-size data: noise + 20 pixel-domain injections")
+    x = ti.noise(g) * ti.sample_keep_mask(g)[None, :]
+    psd, mu, keep = ti.psd_on_bins(g), ti.tranche_psd_scale(g), ti.tranche_keep(g)
+    pix, u, wm = otf.transform(x, g, psd, mu, keep, 0.1, "rfft")
+    inj, snr = ti.full_injections()
+    lay = otrk.Layout(inj, g)
+    K = g.tranche_len // 2 + 1
+    with torch.no_grad():
+        for i in range(len(inj)):
+            if lay.flags[i] & (otrk.FLAG_INVALID | otrk.FLAG_EMPTY):
+                continue
+            m, kc, k, valid, Y = o2.template_pixels(inj.mc[i], inj.eta[i], inj.f0[i], inj.cos_theta[i], inj.phi[i],
+                                                    inj.psi[i], inj.cos_iota[i], lay.m_end[i], g, u, wm)
+            Y = Y.numpy() * np.exp(1j * inj.phase[i])
+            rho = np.sqrt(2.0 * np.sum(np.abs(Y) ** 2))
+            Y *= snr[i] / rho
+            kk = np.clip(k.numpy(), 0, K - 1)
+            mm = np.broadcast_to(m.numpy()[:, None], kk.shape)
+            v = valid.numpy()
+            for c in range(g.n_channels):
+                np.add.at(pix[c], (kk[v], mm[v]), Y[c][v])
+    return dict(grid=g, pix=pix, u=u, wm=wm, inj=inj, snr=snr)

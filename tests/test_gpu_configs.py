@@ -1,0 +1,214 @@
+"""Oracle parity at each workload's own size, through the C ABI (2-yr A+E grid, Nt = 6144 x M = 2048):
+
+* the batching bank (4M templates, Mc log-U[5, 100] Msun, f0 U[5, 50] mHz, about half merging in the window,
+  tracks of 59 to 5,964 tranches) in the chosen form (GPU transform, FP32 channel-interleaved store, wave
+  schedule, f0-bin order) against the FP64 oracle on 1,200 sampled templates that include the shortest and
+  longest tracks and templates merging in the window;
+* the FP64 VJP on 16 of the top 65,536 candidates of that bank (the differentiation workload's inputs)
+  against the oracle's float64 autograd;
+* the detection-ranking rule on the full-size bank with 20 injections: the top 1,000 keep their order for
+  every pair whose oracle values differ by more than 2 tol Upsilon; the set above the noise-only 1 - 1e-4
+  quantile of the batching bank's realisations is the oracle's; the argmax near each injection is the
+  oracle's.
+
+The data are the seeded synthetic stand-ins of the paper's two-year data set (Sec. "Searching the Yorsh
+dataset"; the statistic of Eq. (Upsilon-seg); false-alarm thresholds from noise-only realisations, Sec.
+"Injected and recovered signals").
+"""
+import functools
+
+import numpy as np
+import pytest
+import torch
+
+import tfsc_inputs as ti
+from oracle import cpu as ocpu
+from oracle import o2
+from oracle import track as otrk
+from oracle import transform as otf
+
+from gpu_common import dev, full_injected, gridspec, lib, note, rel
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4  # the chosen form's bar against the FP64 oracle
+
+
+@functools.lru_cache(maxsize=1)
+def batching_r0():
+    """Realisation 0 of the batching workload's noise (gaps applied, FP32 as the chosen form reads it), the
+    oracle's pixels of the same FP32 series, and the chosen form's statistic over the whole 4M bank."""
+    tfsc = lib()
+    g = ti.FULL
+    note("batching workload: realisation 0 and the 4M-template bank")
+    x32 = (ti.noise(g, realisation=0) * ti.sample_keep_mask(g)[None, :]).astype(np.float32)
+    psd, mu, keep = ti.psd_on_bins(g), ti.tranche_psd_scale(g), ti.tranche_keep(g)
+    pix, u, wm = otf.transform(x32.astype(np.float64), g, psd, mu, keep, 0.1, "rfft")
+    bank = ti.batching_bank()
+    grid = gridspec(g)
+    st = tfsc.transform(grid, dev(x32), dev(psd), dev(mu), dev(keep), dtype="f32", layout="layer_ci")
+    bt = tfsc.BankTensors.from_host(bank)
+    seg = tfsc.segment_layout(grid, bt)
+    res = tfsc.bank_statistic(grid, st, bt, seg, precision="f32", schedule="wave",
+                              order=tfsc.processing_order(grid, bt), want_active=True)
+    out = dict(grid=g, pix=pix, u=u, wm=wm, bank=bank, stat=res.stat.cpu().numpy(),
+               flags=res.flags.cpu().numpy(), n_active=res.n_active.cpu().numpy())
+    del st, bt, seg, res
+    torch.cuda.empty_cache()
+    return out
+
+
+def test_batching_bank_chosen_form_against_oracle():
+    d = batching_r0()
+    stat, flags, nact = d["stat"], d["flags"], d["n_active"]
+    n = stat.size
+    rng = np.random.default_rng(41)
+    live = np.nonzero(nact > 0)[0]
+    by_len = live[np.argsort(nact[live], kind="stable")]
+    # merging inside the window: coalescence before the end of the span (most of these tracks end one
+    # tranche earlier by the compactness condition, as the chirp accelerates)
+    b = d["bank"]
+    tc = otrk.Template(torch.as_tensor(b.mc), torch.as_tensor(b.eta), torch.as_tensor(b.f0)).tc.numpy()
+    span = d["grid"].n_tranches * d["grid"].tranche_dur
+    merging = np.nonzero((tc < span) & (nact > 0))[0]
+    band = np.nonzero((flags & otrk.FLAG_BAND_END) != 0)[0]
+    idx = np.unique(np.concatenate([
+        by_len[:150], by_len[-150:],                        # shortest and longest active tracks
+        rng.choice(merging, 300, replace=False),            # merging inside the window
+        rng.choice(band, 100, replace=False),               # ended by the band or compactness rule
+        np.argsort(-stat, kind="stable")[:100],             # the loudest
+        rng.choice(n, 400, replace=False)]))
+    note(f"batching bank: {merging.size} of {n} merge in the window; {idx.size} sampled templates, active "
+         f"tranches {nact[idx].min()}..{nact[idx].max()}, {np.count_nonzero(tc[idx] < span)} merging")
+    assert idx.size >= 1000
+    ref = ocpu.statistic(d["pix"], d["u"], d["wm"], d["bank"].subset(idx), d["grid"])
+    r = rel(stat[idx], ref.stat)
+    note(f"  max rel {r.max():.2e}  p99 {np.quantile(r, 0.99):.2e}  median {np.median(r):.2e}")
+    assert np.array_equal(flags[idx], ref.flags)
+    assert r.max() < TOL
+
+
+def test_vjp_on_top_candidates_full_size():
+    """FP64 forward and VJP (oracle pixels in an FP64 store) on 16 of the top 65,536 candidates of the batching
+    bank, against float64 autograd of the oracle; the bars of the small-grid VJP test."""
+    tfsc = lib()
+    d = batching_r0()
+    g = d["grid"]
+    top = np.argsort(-np.nan_to_num(d["stat"], nan=-1.0), kind="stable")[:65536]
+    rng = np.random.default_rng(43)
+    pick = np.concatenate([top[:8], rng.choice(top[8:], 8, replace=False)])
+    sub = d["bank"].subset(pick)
+    note(f"vjp at full size: candidates {pick.tolist()}")
+    grid = gridspec(g)
+    store = tfsc.PixelStore.from_complex(dev(d["pix"]), dev(d["u"]), dev(d["wm"]), dtype="f64", layout="layer")
+    bt = tfsc.BankTensors.from_host(sub)
+    seg = tfsc.segment_layout(grid, bt)
+    res = tfsc.bank_statistic(grid, store, bt, seg, precision="f64", schedule="wave", want_zn=True)
+    gp = tfsc.statistic_vjp(grid, store, bt, seg, res.seg_zn,
+                            g_stat=torch.ones(bt.n, dtype=torch.float64, device="cuda")).cpu().numpy()
+    ups = res.stat.cpu().numpy()
+    lay = otrk.Layout(sub, g)
+    ref = np.zeros((len(pick), 5))
+    for r in range(len(pick)):
+        ref[r], _ = o2.gradient(d["pix"], d["u"], d["wm"], sub, g, r, layout=lay)
+    floor = 1e-3 * np.max(np.abs(ref), axis=0, keepdims=True)
+    err = np.abs(gp - ref) / np.maximum(np.abs(ref), floor)
+    T = g.n_tranches * g.tranche_dur
+    df0 = 0.1 / (T / lay.nseg.astype(np.float64))
+    s = np.empty((len(pick), 5))
+    s[:, 0] = df0 / ((5.0 / 3.0) * np.abs(lay.fdot0) * T)
+    s[:, 1] = df0
+    s[:, 2:] = 0.05
+    cell = np.abs(gp - ref) * s / np.maximum(ups, 1.0)[:, None]
+    for r in range(len(pick)):
+        note(f"  #{pick[r]}: Upsilon {ups[r]:.1f}, N_seg {lay.nseg[r]}, rel {np.array2string(err[r], precision=2)}")
+    note(f"  rel max {err.max():.2e}, per cell max {cell.max():.2e}")
+    assert err.max() < 2e-5
+    assert cell.max() < 1e-7
+
+
+@functools.lru_cache(maxsize=1)
+def noise_threshold(n_real=4):
+    """The noise-only 1 - 1e-4 quantile of the chosen form's statistic over the batching bank in the first
+    n_real realisations of the batching workload (n_real x 4M values)."""
+    tfsc = lib()
+    g = ti.FULL
+    grid = gridspec(g)
+    psd, mu, keep = ti.psd_on_bins(g), ti.tranche_psd_scale(g), ti.tranche_keep(g)
+    bt = tfsc.BankTensors.from_host(ti.batching_bank())
+    seg = tfsc.segment_layout(grid, bt)
+    order = tfsc.processing_order(grid, bt)
+    vals = []
+    for r in range(n_real):
+        note(f"noise-only threshold: realisation {r}")
+        x32 = (ti.noise(g, realisation=r) * ti.sample_keep_mask(g)[None, :]).astype(np.float32)
+        st = tfsc.transform(grid, dev(x32), dev(psd), dev(mu), dev(keep), dtype="f32", layout="layer_ci")
+        res = tfsc.bank_statistic(grid, st, bt, seg, precision="f32", schedule="wave", order=order)
+        vals.append(res.stat.cpu().numpy())
+    v = np.concatenate(vals)
+    return float(np.quantile(v[np.isfinite(v)], 1.0 - 1e-4))
+
+
+def test_detection_ranking_rule():
+    tfsc = lib()
+    d = full_injected()
+    g = d["grid"]
+    bank = ti.full_bank(1_000_000)
+    n = len(bank)
+    grid = gridspec(g)
+    store = tfsc.PixelStore.from_complex(dev(d["pix"]), dev(d["u"]), dev(d["wm"]), dtype="f32", layout="layer_ci")
+    bt = tfsc.BankTensors.from_host(bank)
+    seg = tfsc.segment_layout(grid, bt)
+    stat = tfsc.bank_statistic(grid, store, bt, seg, precision="f32", schedule="wave",
+                               order=tfsc.processing_order(grid, bt)).stat.cpu().numpy()
+    desc = np.argsort(-stat, kind="stable")
+
+    # (1) the top 1,000 by the oracle: evaluated on the top 1,500 of the chosen form, which contain them
+    cand = desc[:1500]
+    ref = ocpu.statistic(d["pix"], d["u"], d["wm"], bank.subset(cand), g).stat
+    err = rel(stat[cand], ref)
+    emax = float(err.max())
+    note(f"ranking: top-1500 candidates, max rel vs oracle {emax:.2e}")
+    assert emax < TOL
+    o_desc = np.argsort(-ref, kind="stable")
+    top = o_desc[:1000]
+    # any template outside the candidates has chosen <= stat[cand[-1]], hence oracle below this bound
+    outside_bound = stat[cand[-1]] + TOL * max(stat[cand[-1]], 1.0)
+    assert ref[top[-1]] > outside_bound, (ref[top[-1]], outside_bound)
+    ro, so = ref[top], stat[cand][top]
+    sep = (ro[:, None] - ro[None, :]) > 2.0 * TOL * np.maximum(ro[:, None], 1.0)
+    bad = sep & ~(so[:, None] > so[None, :])
+    note(f"  top 1000: {int(sep.sum())} separated pairs, {int(bad.sum())} out of order")
+    assert not bad.any()
+
+    # (3) the argmax near each injection: the exact-parameter template and the 64 bank templates nearest to it
+    inj = d["inj"]
+    T = g.n_tranches * g.tranche_dur
+    near_sets = []
+    for i in range(len(inj)):
+        lay_i = otrk.Layout(inj.subset([i]), g)
+        df0 = 0.1 / (T / lay_i.nseg[0])
+        dln = df0 / ((5.0 / 3.0) * abs(lay_i.fdot0[0]) * T)
+        dist = (((bank.f0[:1_000_000] - inj.f0[i]) / df0) ** 2
+                + ((np.log(bank.mc[:1_000_000]) - np.log(inj.mc[i])) / dln) ** 2)
+        near_sets.append(np.concatenate([np.argsort(dist)[:64], [1_000_000 + i]]))
+    allnear = np.unique(np.concatenate(near_sets))
+    ref_near = dict(zip(allnear.tolist(), ocpu.statistic(d["pix"], d["u"], d["wm"], bank.subset(allnear), g).stat))
+    for i, s_i in enumerate(near_sets):
+        a_gpu = s_i[int(np.argmax(stat[s_i]))]
+        a_ref = s_i[int(np.argmax([ref_near[int(j)] for j in s_i]))]
+        assert a_gpu == a_ref, (i, a_gpu, a_ref)
+    note(f"  argmax near each of the {len(inj)} injections: identical")
+
+    # (2) the set above the noise-only 1 - 1e-4 quantile of the batching workload's realisations
+    thr = noise_threshold()
+    c2 = np.nonzero(stat > thr * (1.0 - 2.0 * TOL) - 2.0 * TOL)[0]
+    ref2 = ocpu.statistic(d["pix"], d["u"], d["wm"], bank.subset(c2), g).stat
+    e2 = float(rel(stat[c2], ref2).max()) if c2.size else 0.0
+    above_gpu = set(c2[stat[c2] > thr].tolist())
+    above_ref = set(c2[ref2 > thr].tolist())
+    # templates whose oracle value lies within the form's measured error of the threshold are near-ties
+    tie = set(c2[np.abs(ref2 - thr) <= e2 * np.maximum(ref2, 1.0)].tolist())
+    note(f"  threshold {thr:.2f}: {len(above_ref)} templates above it (oracle), {len(above_gpu)} (chosen form), "
+         f"{len(tie)} within the form's error {e2:.1e} of it")
+    assert above_gpu - tie == above_ref - tie
+    assert len(above_ref) > 0

@@ -18,7 +18,7 @@ from oracle import o2
 from oracle import track as otrk
 from oracle import transform as otf
 
-from gpu_common import dev, gridspec, lib, note
+from gpu_common import dev, full_injected, gridspec, lib, note
 
 pytestmark = pytest.mark.gpu
 
@@ -27,34 +27,15 @@ N_FULL = 1_000_000
 
 @functools.lru_cache(maxsize=1)
 def data():
-    g = ti.FULL
-    note("precision data: full-size noise + 20 pixel-domain injections")
-    x = ti.noise(g) * ti.sample_keep_mask(g)[None, :]
-    psd, mu, keep = ti.psd_on_bins(g), ti.tranche_psd_scale(g), ti.tranche_keep(g)
-    pix, u, wm = otf.transform(x, g, psd, mu, keep, 0.1, "rfft")
-    inj, snr = ti.full_injections()
-    lay = otrk.Layout(inj, g)
-    K, Nt = g.tranche_len // 2 + 1, g.n_tranches
-    with torch.no_grad():
-        for i in range(len(inj)):
-            if lay.flags[i] & (otrk.FLAG_INVALID | otrk.FLAG_EMPTY):
-                continue
-            m, kc, k, valid, Y = o2.template_pixels(inj.mc[i], inj.eta[i], inj.f0[i], inj.cos_theta[i], inj.phi[i],
-                                                    inj.psi[i], inj.cos_iota[i], lay.m_end[i], g, u, wm)
-            Y = Y.numpy() * np.exp(1j * inj.phase[i])
-            rho = np.sqrt(2.0 * np.sum(np.abs(Y) ** 2))
-            Y *= snr[i] / rho
-            kk = np.clip(k.numpy(), 0, K - 1)
-            mm = np.broadcast_to(m.numpy()[:, None], kk.shape)
-            v = valid.numpy()
-            for c in range(g.n_channels):
-                np.add.at(pix[c], (kk[v], mm[v]), Y[c][v])
+    d = dict(full_injected())
+    g = d["grid"]
     bank = ti.full_bank(N_FULL)
     idx = ti.subsample_indices(len(bank), 10_000, must_include=np.arange(N_FULL, N_FULL + 20), cfg_id=13)
     sub = bank.subset(idx)
     note("precision data: FP64 oracle on the 10,000-template subsample")
-    ref = ocpu.statistic(pix, u, wm, sub, g)
-    return dict(grid=g, pix=pix, u=u, wm=wm, bank=sub, ref=ref)
+    d["ref"] = ocpu.statistic(d["pix"], d["u"], d["wm"], sub, g)
+    d["bank"] = sub
+    return d
 
 
 def _store(tfsc, d, dtype):
