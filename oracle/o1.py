@@ -35,33 +35,53 @@ from .transform import tranche_dft
 
 
 def strain_callback(tpl: trk.Template, cos_iota: float, t_stop: float, phase: float = 0.0,
-                    analytic: bool = False, amp: float = 1.0):
+                    analytic: bool = False, amp: float = 1.0, harmonics=None):
+    """(h+, hx) at delayed times.  ``harmonics`` = (h[H], a[H]): the strain sum_h a_h A e^{i (h/2) Phi} over
+    harmonics of the orbital phase (Sec. "Outlook"), each with the dominant harmonic's polarisation pattern;
+    None is the dominant harmonic alone (h = 2, a = 1)."""
     ci = float(cos_iota)
     ap = (1.0 + ci * ci) / 2.0
+    hs = [(1.0, 1.0 + 0.0j)] if harmonics is None else [(0.5 * float(h), complex(a)) for h, a in zip(*harmonics)]
 
     def hfun(tq):
         on = tq < t_stop
         tsafe = torch.where(on, tq, torch.zeros_like(tq))
         Phi, f, fdot, A = tpl.at(tsafe)
-        Phi = Phi + phase
         A = torch.where(on, A * amp, torch.zeros_like(A))
+        if harmonics is None:
+            Phi = Phi + phase
+            if analytic:
+                e = torch.polar(torch.ones_like(Phi), Phi)
+                return A * ap * e, A * torch.complex(torch.zeros_like(Phi), -ci * torch.ones_like(Phi)) * e
+            return A * ap * torch.cos(Phi), A * ci * torch.sin(Phi)
+        w = torch.zeros(Phi.shape, dtype=torch.complex128)
+        for s, a in hs:
+            ph = s * Phi + phase
+            w = w + a * torch.polar(torch.ones_like(ph), ph)
+        hp = A * ap * w
+        hx = A * torch.complex(torch.zeros_like(Phi), -ci * torch.ones_like(Phi)) * w
         if analytic:
-            e = torch.polar(torch.ones_like(Phi), Phi)
-            return A * ap * e, A * torch.complex(torch.zeros_like(Phi), -ci * torch.ones_like(Phi)) * e
-        return A * ap * torch.cos(Phi), A * ci * torch.sin(Phi)
+            return hp, hx
+        return hp.real, hx.real
 
     return hfun
 
 
 def synthesize(bank, i: int, grid, analytic: bool = False, t_stop: float | None = None,
-               amp: float = 1.0, chunk: int = 1 << 18) -> np.ndarray:
-    """TDI [C][N] time series of source i of ``bank`` (phase offset from bank.phase if set)."""
+               amp: float = 1.0, chunk: int = 1 << 18, harmonics=None) -> np.ndarray:
+    """TDI [C][N] time series of source i of ``bank`` (phase offset from bank.phase if set).  ``harmonics`` =
+    (h[H], a[H]) synthesises a multi-harmonic source; it then stops where the highest harmonic's track ends."""
     lay = trk.Layout(bank.subset([i]), grid)
     tpl = lay.template(0)
     if t_stop is None:
-        t_stop = float(lay.m_end[0]) * grid.tranche_dur
+        if harmonics is None:
+            t_stop = float(lay.m_end[0]) * grid.tranche_dur
+        else:
+            from .harmonics import track_end
+            m_end, _, _ = track_end(bank.subset([i]), grid, harmonics[0], layout=lay)
+            t_stop = float(m_end[0]) * grid.tranche_dur
     phase = 0.0 if bank.phase is None else float(bank.phase[i])
-    hfun = strain_callback(tpl, bank.cos_iota[i], t_stop, phase, analytic, amp)
+    hfun = strain_callback(tpl, bank.cos_iota[i], t_stop, phase, analytic, amp, harmonics)
     N = grid.n_samples
     dtype = np.complex128 if analytic else np.float64
     out = np.zeros((grid.n_channels, N), dtype=dtype)
@@ -77,13 +97,13 @@ def synthesize(bank, i: int, grid, analytic: bool = False, t_stop: float | None 
     return out
 
 
-def template_pixels(bank, i: int, grid, u, wm, alpha: float = 0.0) -> np.ndarray:
+def template_pixels(bank, i: int, grid, u, wm, alpha: float = 0.0, harmonics=None) -> np.ndarray:
     """Y[C][K][Nt] = DFT of the analytic TD template (window alpha) times u_k w_m, times dt.
 
     The factor dt makes the DFT approximate the continuous transform, which is
     the normalisation of the Fresnel-kernel spectrum of O2.
     """
-    x = synthesize(bank, i, grid, analytic=True)
+    x = synthesize(bank, i, grid, analytic=True, harmonics=harmonics)
     M = grid.tranche_len
     Y = np.empty((grid.n_channels, M // 2 + 1, grid.n_tranches), dtype=np.complex128)
     for c in range(grid.n_channels):
