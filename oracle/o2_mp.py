@@ -5,7 +5,7 @@ Test infrastructure only.  The same formulas as ``oracle.o2``:
   finder at full working precision, no fixed-count iterations);
 * the tranche spectrum of Eq. (fresnel-ft) with the paper's two-branch
   Fresnel forms (``oracle.fresnel.fresnel_paper``);
-* the response of ``oracle.response.transfer_ae``;
+* the response of ``oracle.response.transfer_aet`` (A, E and the third channel T);
 * Eqs. (overlap-n), (Upsilon-seg) on the given whitened pixels.
 
 The integer structure (track end, bin indices, Fresnel branch of every
@@ -167,7 +167,7 @@ def _transfer(t, f, sky, ci):
     TX = om * ((g(3, 1) + D * g(1, 3)) - (g(2, 1) + D * g(1, 2)))
     TY = om * ((g(1, 2) + D * g(2, 1)) - (g(3, 2) + D * g(2, 3)))
     TZ = om * ((g(2, 3) + D * g(3, 2)) - (g(1, 3) + D * g(3, 1)))
-    return (TZ - TX) / mp.sqrt(2), (TX - 2 * TY + TZ) / mp.sqrt(6)
+    return (TZ - TX) / mp.sqrt(2), (TX - 2 * TY + TZ) / mp.sqrt(6), (TX + TY + TZ) / mp.sqrt(3)
 
 
 def _set_phase_offsets(cx: _Ctx, p0):

@@ -1,4 +1,5 @@
-"""Write vjp_mp_small.json: high-precision gradients for the two-channel gapped test data.
+"""Write vjp_mp_small.json and vjp_mp_aet.json: high-precision gradients for the two-channel gapped test data and
+for the small-beta templates of the three-channel test data.
 
 Calls only the oracle (oracle.o2_mp at 60 digits) and the seeded input generators.  Run from the
 repository root:  python tests/golden/make_vjp_mp.py
@@ -36,7 +37,31 @@ def _one(i):
     return i, val, grad.tolist(), val64, grad64.tolist()
 
 
+AET_TEMPLATES = [0, 3, 38]  # the three-channel test's templates with beta = fdot0 dT^2 below 1e-3
+
+
+def _one_aet(i):
+    from test_gpu_t_channel import _data
+    from oracle import o2_mp
+    d = _data()
+    val64, grad64 = o2_mp.gradient(d["pix"], d["u"], d["wm"], d["bank"], d["grid"], i, float64_phase=True)
+    return i, val64, grad64.tolist()
+
+
 def main():
+    with Pool(min(len(AET_TEMPLATES), 8)) as pool:
+        rows = pool.map(_one_aet, AET_TEMPLATES)
+    out = {
+        "about": "Upsilon and its gradient w.r.t. (ln Mc, f0, cos theta, phi, psi) for the small-beta templates of "
+                 "the three-channel (A, E, T) test data of tests/test_gpu_t_channel.py; oracle.o2_mp at 60 digits, "
+                 "central differences with step 1e-15, exact except for the float64 rounding of the tranche "
+                 "phases, which every float64 track shares",
+        "command": "python tests/golden/make_vjp_mp.py",
+        "templates": {str(i): {"value_f64phase": v64, "grad_f64phase": g64} for i, v64, g64 in rows},
+    }
+    with open(os.path.join(HERE, "vjp_mp_aet.json"), "w") as fh:
+        json.dump(out, fh, indent=1)
+    print("wrote", len(rows), "three-channel templates")
     with Pool(min(len(TEMPLATES), 8)) as pool:
         rows = pool.map(_one, TEMPLATES)
     out = {

@@ -1,6 +1,8 @@
 """Three channels (TDI A, E and T) through the C ABI against the oracle: transform, statistic on both
 schedules and all layouts, the VJP, and the several-realisation call that refuses C = 3."""
 import functools
+import json
+import os
 
 import numpy as np
 import pytest
@@ -136,7 +138,18 @@ def test_vjp_three_channels_against_oracle_autograd():
     floor = 1e-3 * np.max(np.abs(ref), axis=0, keepdims=True)
     err = np.abs(gp[idx] - ref) / np.maximum(np.abs(ref), floor)
     note(f"  max rel vs oracle autograd {err.max():.2e}")
-    assert err.max() < 2e-5
+    # The float64 autograd of the literal oracle loses digits at small beta = fdot dT^2 (template 38 has
+    # beta = 6.6e-6: its d/d ln Mc is 3.2e-5 off the 60-digit reference); the bar against it is set by that
+    # measured loss, and the small-beta templates are held to 1e-6 against the 60-digit reference.
+    assert err.max() < 5e-5
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "vjp_mp_aet.json")) as fh:
+        golden = json.load(fh)
+    for key, row in golden["templates"].items():
+        i = int(key)
+        ref_mp = np.array(row["grad_f64phase"])
+        r_mp = np.abs(gp[i] - ref_mp) / np.abs(ref_mp)
+        note(f"  #{i} vs 60-digit reference: rel {np.array2string(r_mp, precision=2)}")
+        assert r_mp.max() < 1e-6, i
 
 
 def test_three_channels_refused_by_multi():
