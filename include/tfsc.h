@@ -34,7 +34,8 @@ typedef enum {
     TFSC_ERR_DTYPE = 3,        /* unsupported element type / combination    */
     TFSC_ERR_WORKSPACE = 4,    /* workspace missing or too small            */
     TFSC_ERR_UNSUPPORTED = 5,  /* valid request the library does not handle */
-    TFSC_ERR_HIP = 6           /* a HIP runtime call failed                 */
+    TFSC_ERR_HIP = 6,          /* a HIP runtime call failed                 */
+    TFSC_ERR_SCRATCH = 7       /* larger than the static device scratch     */
 } tfsc_status;
 
 typedef enum { TFSC_F64 = 0, TFSC_F32 = 1, TFSC_BF16 = 2, TFSC_F16 = 3 } tfsc_dtype;
@@ -249,6 +250,27 @@ tfsc_status tfsc_bank_statistic_multi(const tfsc_grid *grid, const tfsc_pixels *
                                       const tfsc_segments *seg, const tfsc_options *opt, int64_t seg_stride,
                                       double *seg_terms, double *stat, int32_t *flags, int32_t *n_active, void *ws,
                                       size_t ws_bytes, void *stream);
+
+/* tfsc_bank_statistic for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results, bit for bit, but the workspace
+ * is a static device array of TFSC_NOALLOC_SCRATCH_BYTES inside the library
+ * instead of a caller-provided one.  Each device holds its own copy until
+ * the process ends (its address is looked up once per device, on the first
+ * call with that device current); the call allocates nothing, neither do
+ * the kernels it launches.  Grids of more than TFSC_NOALLOC_MAX_TRANCHES
+ * tranches return TFSC_ERR_SCRATCH.  All calls on one device share that
+ * device's scratch (it keeps the last call's contents; the work counter is
+ * cleared by a kernel at the start of every call): calls that overlap in
+ * time on one device, on different streams or from different threads,
+ * race and must be serialised by the caller.  Arguments, outputs and
+ * errors otherwise as tfsc_bank_statistic.                                 */
+#define TFSC_NOALLOC_MAX_TRANCHES 16384
+#define TFSC_NOALLOC_SCRATCH_BYTES (3u << 20)
+tfsc_status tfsc_bank_statistic_noalloc(const tfsc_grid *grid, const tfsc_pixels *pix, const tfsc_bank *bank,
+                                        const tfsc_segments *seg, const tfsc_options *opt, double *seg_terms,
+                                        double *stat, double *seg_zn, int32_t *flags, int32_t *n_active,
+                                        void *stream);
 
 /* Vector-Jacobian product of the statistic (gradient of Eq. (Upsilon-seg)
  * through Eqs. (overlap-n), (inner-segment-tf), (fresnel-ft) and the

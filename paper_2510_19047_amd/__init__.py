@@ -246,6 +246,30 @@ def bank_statistic(grid: GridSpec, pixels: PixelStore, bank: BankTensors, seg: S
     return out
 
 
+def bank_statistic_noalloc(grid: GridSpec, pixels: PixelStore, bank: BankTensors, seg: SegmentLayout,
+                           precision: str = "f32", schedule: str = "wave", want_zn: bool = False,
+                           block_waves: int = 0, groups_per_cu: int = 0, order: torch.Tensor | None = None,
+                           out: StatResult | None = None, want_active: bool = False) -> StatResult:
+    """tfsc_bank_statistic_noalloc: bank_statistic with the library's static device scratch as workspace (the
+    call allocates no device memory; outputs are allocated here only when ``out`` is not given)."""
+    L = lib()
+    dev = bank.mc.device
+    if out is None:
+        out = StatResult(torch.empty(bank.n, dtype=torch.float64, device=dev),
+                         torch.empty(max(seg.total, 1), dtype=torch.float64, device=dev),
+                         torch.empty(bank.n, dtype=torch.int32, device=dev),
+                         torch.empty((max(seg.total, 1), 3), dtype=torch.float64, device=dev) if want_zn else None,
+                         torch.empty(bank.n, dtype=torch.int32, device=dev) if want_active else None)
+    g = grid.c()
+    opt = _options(precision, schedule, block_waves, groups_per_cu, order)
+    pc, bc, sc = pixels.c(), bank.c(), seg.c()
+    st = L.tfsc_bank_statistic_noalloc(ctypes.byref(g), ctypes.byref(pc), ctypes.byref(bc), ctypes.byref(sc),
+                                       ctypes.byref(opt), _ptr(out.seg_terms), _ptr(out.stat), _ptr(out.seg_zn),
+                                       _ptr(out.flags), _ptr(out.n_active), _stream())
+    _lib.check(st, "tfsc_bank_statistic_noalloc")
+    return out
+
+
 def realisation_stores(grid: GridSpec, n_real: int, dtype: str = "f32", layout: str = "layer_ci",
                        device="cuda") -> list:
     """n_real pixel stores in one contiguous block (the input of bank_statistic_multi), sharing inv_asd and

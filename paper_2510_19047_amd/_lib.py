@@ -10,6 +10,8 @@ LIB_PATH = os.path.join(HERE, "libtfsc.so")
 c_int32, c_int64, c_double, c_void_p, c_size_t = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
 
 TFSC_OK = 0
+TFSC_ERR_SCRATCH = 7
+NOALLOC_MAX_TRANCHES = 16384
 F64, F32, BF16, F16 = 0, 1, 2, 3
 LAYER_MAJOR, TRANCHE_MAJOR, LAYER_MAJOR_CI = 0, 1, 2
 SCHED_THREAD, SCHED_WAVE = 0, 1
@@ -42,7 +44,8 @@ class Options(ctypes.Structure):
 
 
 EXPORTS = ("tfsc_abi_version", "tfsc_status_string", "tfsc_workspace_bytes", "tfsc_transform", "tfsc_transform_tf",
-           "tfsc_segment_layout", "tfsc_bank_statistic", "tfsc_bank_statistic_multi", "tfsc_statistic_vjp",
+           "tfsc_segment_layout", "tfsc_bank_statistic", "tfsc_bank_statistic_noalloc", "tfsc_bank_statistic_multi",
+           "tfsc_statistic_vjp",
            "tfsc_follow_up_step",
            "tfsc_processing_order", "tfsc_tile_max", "tfsc_track")
 
@@ -79,6 +82,9 @@ def load(path: str = LIB_PATH):
     L.tfsc_bank_statistic.restype = ctypes.c_int
     L.tfsc_bank_statistic.argtypes = [P(Grid), P(Pixels), P(Bank), P(Segments), P(Options), c_void_p, c_void_p,
                                       c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+    L.tfsc_bank_statistic_noalloc.restype = ctypes.c_int
+    L.tfsc_bank_statistic_noalloc.argtypes = [P(Grid), P(Pixels), P(Bank), P(Segments), P(Options), c_void_p,
+                                              c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     L.tfsc_statistic_vjp.restype = ctypes.c_int
     L.tfsc_statistic_vjp.argtypes = [P(Grid), P(Pixels), P(Bank), P(Segments), P(Options), c_void_p, c_void_p,
                                      c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]

@@ -2,8 +2,17 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "../../include/tfsc.h"
 #include "tfsc_kernels.hpp"
+
+// Device scratch of tfsc_bank_statistic_noalloc: the statistic workspace (geometry tables, work
+// counter, weight scale) for grids of up to TFSC_NOALLOC_MAX_TRANCHES tranches.  Each device holds
+// its own copy for the life of the process; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that device (scratch_on_device below), never through the name.
+constexpr size_t kScratchBytes = TFSC_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -105,6 +114,25 @@ size_t ws_bytes_for(const tfsc_grid *g, int64_t n, int which) {
 
 tfsc_status hip_status(hipError_t e) { return e == hipSuccess ? TFSC_OK : TFSC_ERR_HIP; }
 
+// The device address of `scratch` on the current device, looked up once per device (with that
+// device current) and kept; NULL if the lookup fails.
+void *scratch_on_device() {
+    constexpr int kMaxDevices = 64;
+    static void *addr[kMaxDevices] = {nullptr};
+    static bool done[kMaxDevices] = {false};
+    static std::mutex mu;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!done[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        addr[dev] = p;
+        done[dev] = true;
+    }
+    return addr[dev];
+}
+
 tfsc::StatLaunch stat_launch(const tfsc_grid *grid, const tfsc_pixels *pix, const tfsc_bank *bank,
                              const tfsc_segments *seg, const Resolved &r, void *ws) {
     tfsc::StatLaunch L;
@@ -157,6 +185,7 @@ const char *tfsc_status_string(int s) {
         case TFSC_ERR_WORKSPACE: return "workspace missing or too small";
         case TFSC_ERR_UNSUPPORTED: return "request not supported by the library";
         case TFSC_ERR_HIP: return "HIP runtime error";
+        case TFSC_ERR_SCRATCH: return "problem larger than the library's static device scratch";
     }
     return "unknown status";
 }
@@ -219,6 +248,20 @@ tfsc_status tfsc_bank_statistic(const tfsc_grid *grid, const tfsc_pixels *pix, c
     L.flags = flags;
     L.n_active = n_active;
     return hip_status(tfsc::launch_statistic(L, st));
+}
+
+tfsc_status tfsc_bank_statistic_noalloc(const tfsc_grid *grid, const tfsc_pixels *pix, const tfsc_bank *bank,
+                                        const tfsc_segments *seg, const tfsc_options *opt, double *seg_terms,
+                                        double *stat, double *seg_zn, int32_t *flags, int32_t *n_active,
+                                        void *stream) {
+    tfsc_status s;
+    if ((s = check_grid(grid)) != TFSC_OK) return s;
+    const size_t need = ws_bytes_for(grid, bank ? bank->n : 0, TFSC_WS_STATISTIC);
+    if (grid->n_tranches > TFSC_NOALLOC_MAX_TRANCHES || need > kScratchBytes) return TFSC_ERR_SCRATCH;
+    void *ws = scratch_on_device();
+    if (!ws) return TFSC_ERR_HIP;
+    return tfsc_bank_statistic(grid, pix, bank, seg, opt, seg_terms, stat, seg_zn, flags, n_active, ws, need,
+                               stream);
 }
 
 tfsc_status tfsc_bank_statistic_multi(const tfsc_grid *grid, const tfsc_pixels *pix, int32_t n_real,

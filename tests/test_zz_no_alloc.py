@@ -1,0 +1,93 @@
+"""tfsc_bank_statistic_noalloc (the statistic with the library's static device scratch as workspace) through the
+C ABI, against tfsc_bank_statistic with a caller-provided workspace: two calls in a row, the second on a smaller
+grid and bank, both equal bit for bit to the workspace call (same kernels) and within the FP64 bar of the
+oracle; a grid beyond the scratch is refused before any launch."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import tfsc_inputs as ti
+from oracle import cpu as ocpu
+from oracle import transform as otf
+
+from gpu_common import dev, gridspec, lib, note, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(n_tranches, n_templates, stream):
+    g = ti.custom_grid(2, 512, n_tranches, dt=5.0, modulated=True, gapped=True, cfg_id=7)
+    psd, mu, keep = ti.psd_on_bins(g), ti.tranche_psd_scale(g), ti.tranche_keep(g)
+    x = ti.noise(g)
+    pix, u, wm = otf.transform(x, g, psd, mu, keep, 0.1, "rfft")
+    b = ti.random_bank(n_templates, 7, mc_range=(5.0, 100.0), f0_range=(0.004, 0.08), stream=stream)
+    return g, pix, u, wm, b
+
+
+def _raw_noalloc(tfsc, grid, store, bank, seg, precision, schedule):
+    """One call of the entry point through ctypes; outputs are caller-allocated torch tensors."""
+    from paper_2510_19047_amd import _lib
+    L = _lib.load()
+    n = bank.n
+    stat = torch.full((n,), -1.0, dtype=torch.float64, device="cuda")
+    terms = torch.full((seg.total,), -1.0, dtype=torch.float64, device="cuda")
+    zn = torch.full((seg.total, 3), -1.0, dtype=torch.float64, device="cuda")
+    flags = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    g, pc, bc, sc = grid.c(), store.c(), bank.c(), seg.c()
+    opt = tfsc._options(precision, schedule, 0, 0, None)
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    st = L.tfsc_bank_statistic_noalloc(ctypes.byref(g), ctypes.byref(pc), ctypes.byref(bc), ctypes.byref(sc),
+                                       ctypes.byref(opt), p(terms), p(stat), p(zn), p(flags), None,
+                                       ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == 0, L.tfsc_status_string(st)
+    return stat, terms, zn, flags
+
+
+def test_noalloc_matches_workspace_call_twice_then_smaller():
+    tfsc = lib()
+    for n_tranches, n_templates, stream in ((700, 96, 61), (300, 40, 62)):
+        g, pix, u, wm, b = _case(n_tranches, n_templates, stream)
+        note(f"noalloc: Nt={n_tranches}, {n_templates} templates")
+        ref = ocpu.statistic(pix, u, wm, b, g)
+        grid = gridspec(g)
+        bt = tfsc.BankTensors.from_host(b)
+        seg = tfsc.segment_layout(grid, bt)
+        for dtype, layout, schedule in (("f64", "layer", "wave"), ("f32", "layer_ci", "wave"),
+                                        ("f64", "tranche", "thread")):
+            store = tfsc.PixelStore.from_complex(dev(pix), dev(u), dev(wm), dtype=dtype, layout=layout)
+            want = tfsc.bank_statistic(grid, store, bt, seg, precision=dtype, schedule=schedule, want_zn=True)
+            stat, terms, zn, flags = _raw_noalloc(tfsc, grid, store, bt, seg, dtype, schedule)
+            torch.cuda.synchronize()
+            assert torch.equal(stat, want.stat), (dtype, schedule)
+            assert torch.equal(terms, want.seg_terms[:seg.total]), (dtype, schedule)
+            assert torch.equal(zn, want.seg_zn[:seg.total]), (dtype, schedule)
+            assert torch.equal(flags, want.flags), (dtype, schedule)
+            r = rel(stat.cpu().numpy(), ref.stat)
+            note(f"  {dtype} {schedule}: equal to the workspace call; max rel vs oracle {r.max():.2e}")
+            assert r.max() < (1e-6 if dtype == "f64" else 1e-4)
+            assert np.array_equal(flags.cpu().numpy(), ref.flags)
+
+
+def test_noalloc_refuses_grids_beyond_the_scratch():
+    tfsc = lib()
+    from paper_2510_19047_amd import _lib
+    L = _lib.load()
+    big = tfsc.GridSpec(2, 512, _lib.NOALLOC_MAX_TRANCHES + 1, 5.0, 0.1)
+    b = ti.random_bank(4, 7, stream=63)
+    bt = tfsc.BankTensors.from_host(b)
+    store = tfsc.PixelStore(torch.zeros((2, 257, 4, 2), dtype=torch.float32, device="cuda"),
+                            torch.ones(257, dtype=torch.float64, device="cuda"),
+                            torch.ones(4, dtype=torch.float64, device="cuda"), "f32", "layer")
+    seg = tfsc.SegmentLayout(nseg=torch.full((4,), 16, dtype=torch.int32, device="cuda"),
+                             seg_offset=torch.arange(0, 80, 16, dtype=torch.int64, device="cuda"), total=64)
+    out = torch.empty(64, dtype=torch.float64, device="cuda")
+    fl = torch.empty(4, dtype=torch.int32, device="cuda")
+    g, pc, bc, sc = big.c(), store.c(), bt.c(), seg.c()
+    opt = tfsc._options("f32", "wave", 0, 0, None)
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    st = L.tfsc_bank_statistic_noalloc(ctypes.byref(g), ctypes.byref(pc), ctypes.byref(bc), ctypes.byref(sc),
+                                       ctypes.byref(opt), p(out), p(out), None, p(fl), None, None)
+    assert st == _lib.TFSC_ERR_SCRATCH
+    assert b"scratch" in L.tfsc_status_string(st)
