@@ -689,24 +689,30 @@ def measured_profile(n, store, layout, order):
 
 
 def alu_roofline(prof, k_s):
-    """The binding roof of the chosen kernel: vector-ALU issue.  achieved = VALU wave instructions per launch
-    (counters of the same source and workload) / the launch time measured here; peak = 1,024 SIMDs x clock /
-    4 cycles per wave64 instruction, with the shader clock measured in the counter run (GRBM_GUI_ACTIVE per
-    dispatch time).  The FP32/FP64 operation counts give the arithmetic rate beside it against the non-packed
-    vector peak (64 FMA lanes per CU and cycle for FP32 and FP64 alike: 78.6 TFLOP/s at 2.4 GHz)."""
+    """The binding roof of the chosen kernel: vector-ALU issue.
+
+    achieved = VALU wave instructions per launch outside the transcendental pipe (counters of the same source
+    and workload) / the launch time measured here; peak = 1,024 SIMDs x clock / 4 cycles per wave64
+    instruction, with the shader clock measured in the counter run (GRBM_GUI_ACTIVE, summed over the eight
+    XCDs, per dispatch time; SQ_BUSY_CYCLES over the 32 shader engines gives the same clock).  Counting every
+    VALU instruction at 4 cycles exceeds the cycles the launch had (reported as valu_all_over_peak), so the
+    transcendental instructions (rcp, rsq, sqrt, sin, cos, exp, log) overlap the others and are left out of
+    the issue count.  The FP32/FP64 operation rate is reported beside it against the non-packed vector peak
+    (64 FMA lanes per CU and cycle for FP32 and FP64 alike: 78.6 TFLOP/s at 2.4 GHz)."""
     rec = {"bound": "alu", "unit": "G VALU instr/s", "achieved": None, "peak": None, "frac": None}
     if prof is None or "valu_insts" not in prof:
         rec["note"] = "no counter profile of this kernel source and workload; run the rocprofv3 passes"
         return rec
     clock = prof.get("clock_hz", NOMINAL_CLOCK_HZ)
     peak = SIMDS * clock / CYCLES_PER_VALU
-    ach = prof["valu_insts"] / k_s
+    issue = prof.get("valu_nontrans_insts", prof["valu_insts"])
+    ach = issue / k_s
     rec.update({"achieved": round(ach / 1e9, 2), "peak": round(peak / 1e9, 2), "frac": round(ach / peak, 4),
                 "clock_ghz": round(clock / 1e9, 4),
                 "peak_nominal_2p4ghz": round(SIMDS * NOMINAL_CLOCK_HZ / CYCLES_PER_VALU / 1e9, 2),
-                "valu_insts_per_launch": prof["valu_insts"]})
-    if "valu_active_frac" in prof:
-        rec["valu_busy_frac_counter_run"] = prof["valu_active_frac"]
+                "valu_insts_per_launch": prof["valu_insts"], "valu_issue_insts_per_launch": issue,
+                "valu_all_over_peak": round(prof["valu_insts"] / k_s / peak, 4),
+                "issue_note": "issue count excludes the transcendental VALU instructions, which overlap the others"})
     if "flops" in prof:
         tf = prof["flops"] / k_s / 1e12
         peak_tf = SIMDS * 16 * 2 * clock / 1e12
@@ -723,6 +729,7 @@ def summarize_counters(dirs, n, store, layout, order, shape, fetch_factor, write
     import glob
     vals = {}
     durs = []
+    copy = {}
     for d in dirs:
         for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
             with open(path) as fh:
@@ -730,6 +737,10 @@ def summarize_counters(dirs, n, store, layout, order, shape, fetch_factor, write
             by_disp = {}
             for row in rows:
                 name = row.get("Kernel_Name", "")
+                if "copyBuffer" in name and row["Counter_Name"] in ("FETCH_SIZE", "WRITE_SIZE"):
+                    # the 256 MiB device copy of --copy-calibration (the largest copy dispatch): bytes per KiB
+                    k = row["Counter_Name"]
+                    copy[k] = max(copy.get(k, 0.0), float(row["Counter_Value"]))
                 if "k_stat_wave<2, float, float, 2, false>" not in name:
                     continue
                 by_disp.setdefault(int(row["Dispatch_Id"]), []).append(row)
@@ -757,10 +768,16 @@ def summarize_counters(dirs, n, store, layout, order, shape, fetch_factor, write
             if clk > 4e9:
                 clk /= 8.0
             lines.append(f"clock_hz: {clk:.6e}")
-            if "SQ_ACTIVE_INST_VALU" in med:
-                lines.append(f"valu_active_frac: {med['SQ_ACTIVE_INST_VALU'] * 4 / SIMDS / (clk * dur * 1e-9):.4f}")
     if "SQ_INSTS_VALU" in med:
         lines.append(f"valu_insts: {med['SQ_INSTS_VALU']:.6e}")
+        if "SQ_INSTS_VALU_TRANS_F32" in med and "SQ_INSTS_VALU_TRANS_F64" in med:
+            nt = med["SQ_INSTS_VALU"] - med["SQ_INSTS_VALU_TRANS_F32"] - med["SQ_INSTS_VALU_TRANS_F64"]
+            lines.append(f"valu_nontrans_insts: {nt:.6e}")
+    if copy.get("FETCH_SIZE", 0) > 0 and copy.get("WRITE_SIZE", 0) > 0:
+        fetch_factor = 268435456.0 / (copy["FETCH_SIZE"] * 1024.0)
+        write_factor = 268435456.0 / (copy["WRITE_SIZE"] * 1024.0)
+        lines += [f"copy_calibration_fetch_kib: {copy['FETCH_SIZE']:.6e}",
+                  f"copy_calibration_write_kib: {copy['WRITE_SIZE']:.6e}"]
     if "FETCH_SIZE" in med and "WRITE_SIZE" in med:
         tb = med["FETCH_SIZE"] * 1024 * fetch_factor + med["WRITE_SIZE"] * 1024 * write_factor
         lines += [f"fetch_factor: {fetch_factor:.3f}", f"write_factor: {write_factor:.3f}", f"traffic_bytes: {tb:.6e}"]
