@@ -43,7 +43,7 @@ def _bins(f_m: torch.Tensor, dT: float, M: int):
 
 
 def template_pixels(mc, eta, f0, cos_theta, phi, psi, cos_iota, m_end: int, grid, u, wm,
-                    exact_fresnel: bool = False, weight_tf=None):
+                    exact_fresnel: bool = False, weight_tf=None, orbit=None):
     """Whitened template pixels of one template on its active tranches.
 
     Parameters may be 0-d tensors carrying autograd.  Returns (m, kc, k, valid, Y)
@@ -51,6 +51,8 @@ def template_pixels(mc, eta, f0, cos_theta, phi, psi, cos_iota, m_end: int, grid
     weight_tf: optional per-pixel weights [K][Nt] (1/sqrt(S_m(f_k)), 0 on excluded
     tranches) for a PSD that varies between tranches in a general way; u and wm
     are then not used.
+    orbit: optional spacecraft positions [3][3][Nt] at the tranche starts (light-seconds), the caller's orbit
+    in place of the analytic one.
     """
     dT = float(grid.tranche_dur)
     M = grid.tranche_len
@@ -61,7 +63,10 @@ def template_pixels(mc, eta, f0, cos_theta, phi, psi, cos_iota, m_end: int, grid
     kc, k, valid = _bins(f, dT, M)
     fk = k.to(torch.float64) / dT
     h = tranche_spectrum(Phi[:, None], f[:, None], fdot[:, None], A[:, None], fk, dT, exact=exact_fresnel)
-    T = list(transfer_aet(tm, f, cos_theta, phi, psi, cos_iota))[: grid.n_channels]
+    pos = None
+    if orbit is not None:
+        pos = torch.as_tensor(np.asarray(orbit), dtype=torch.float64)[:, :, m].permute(2, 0, 1)
+    T = list(transfer_aet(tm, f, cos_theta, phi, psi, cos_iota, pos))[: grid.n_channels]
     if weight_tf is not None:
         wt = torch.as_tensor(np.asarray(weight_tf), dtype=torch.float64)
         wkm = wt[k.clamp(0, M // 2), m[:, None]]
@@ -106,13 +111,14 @@ class Result:
 
 
 def statistic(pix, u, wm, bank, grid, layout: trk.Layout | None = None, exact_fresnel: bool = False,
-              idx=None, weight_tf=None) -> Result:
+              idx=None, weight_tf=None, orbit=None) -> Result:
     """Upsilon and its per-segment terms for every template of ``bank``.
 
     pix: complex [C][K][Nt] whitened data pixels (numpy), u: [K], wm: [Nt].
     idx: optional subset of template indices (others are left at zero).
     weight_tf: optional per-pixel template weights [K][Nt] in place of u_k w_m
     (``transform.transform_tf``); u and wm must then be None.
+    orbit: optional spacecraft positions [3][3][Nt] at the tranche starts (a caller's orbit).
     """
     if weight_tf is not None and (u is not None or wm is not None):
         raise ValueError("give either (u, wm) or weight_tf")
@@ -130,7 +136,7 @@ def statistic(pix, u, wm, bank, grid, layout: trk.Layout | None = None, exact_fr
                 continue
             m, kc, k, valid, Y = template_pixels(
                 bank.mc[i], bank.eta[i], bank.f0[i], bank.cos_theta[i], bank.phi[i], bank.psi[i],
-                bank.cos_iota[i], layout.m_end[i], grid, u, wm, exact_fresnel, weight_tf)
+                bank.cos_iota[i], layout.m_end[i], grid, u, wm, exact_fresnel, weight_tf, orbit)
             z, N = _segment_sums(pix_t, m, k, valid, Y, layout.nseg[i], grid.n_tranches)
             ups = _upsilon(z, N)
             o = layout.seg_offset[i]

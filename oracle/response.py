@@ -8,7 +8,8 @@ tranche frequency (Eq. (tdi2)) and applied to the whole tranche spectrum.
 The single-link transfer functions the paper cites are not printed in it;
 the reconstruction used here is the standard one and is stated in full:
 
-* Orbits (first order in the eccentricity e = L / (2 sqrt(3) R), R = 1 AU),
+* Orbits (first order in the eccentricity e = L / (2 sqrt(3) R), R = 1 AU; or a caller's table of
+  positions at the tranche starts, as the Outlook's numerical orbits),
   a = 2 pi t / yr, b_i = 2 pi i / 3 (i = 0, 1, 2):
     p_i = R (cos a, sin a, 0) + (e R / 2) (cos(2a - b_i) - 3 cos b_i,
           sin(2a - b_i) - 3 sin b_i, -2 sqrt(3) cos(a - b_i))       [seconds]
@@ -102,23 +103,28 @@ def transfer_ae(t, f, cos_theta, phi, psi, cos_iota):
     return TA, TE
 
 
-def transfer_aet(t, f, cos_theta, phi, psi, cos_iota):
+def transfer_aet(t, f, cos_theta, phi, psi, cos_iota, pos=None):
     """(T_A, T_E, T_T): the third channel T = (X + Y + Z) / sqrt 3 completes A and E to an orthonormal
-    combination of X, Y, Z (so |T_A|^2 + |T_E|^2 + |T_T|^2 = |T_X|^2 + |T_Y|^2 + |T_Z|^2)."""
-    TX, TY, TZ = transfer_xyz(t, f, cos_theta, phi, psi, cos_iota)
+    combination of X, Y, Z (so |T_A|^2 + |T_E|^2 + |T_T|^2 = |T_X|^2 + |T_Y|^2 + |T_Z|^2).  ``pos``: spacecraft
+    positions [..., 3, 3] at the times t (a caller's orbit), None for the analytic orbit."""
+    TX, TY, TZ = transfer_xyz(t, f, cos_theta, phi, psi, cos_iota, pos)
     TA = (TZ - TX) / math.sqrt(2.0)
     TE = (TX - 2.0 * TY + TZ) / math.sqrt(6.0)
     TT = (TX + TY + TZ) / math.sqrt(3.0)
     return TA, TE, TT
 
 
-def transfer_xyz(t, f, cos_theta, phi, psi, cos_iota):
-    """Per-tranche transfer of the Michelson combinations (T_X, T_Y, T_Z) that A, E and T are formed from."""
+def transfer_xyz(t, f, cos_theta, phi, psi, cos_iota, pos=None):
+    """Per-tranche transfer of the Michelson combinations (T_X, T_Y, T_Z) that A, E and T are formed from.
+
+    ``pos``: spacecraft positions [..., 3 spacecraft, 3 coordinates] (light-seconds) at the times t, for an
+    orbit other than the analytic one (Sec. "Outlook": numerical or generic orbits); the arm directions come
+    from them, the arm length of the link transfer and the TDI delays stays L."""
     t = t if torch.is_tensor(t) else torch.as_tensor(t, dtype=torch.float64)
     f = f if torch.is_tensor(f) else torch.as_tensor(f, dtype=torch.float64)
     ci = cos_iota if torch.is_tensor(cos_iota) else torch.as_tensor(cos_iota, dtype=torch.float64)
     k, ep, ex = sky_frame(cos_theta, phi, psi)
-    p = orbits(t)
+    p = orbits(t) if pos is None else torch.as_tensor(pos, dtype=torch.float64)
     ap = (1.0 + ci * ci) / 2.0
     G = {}
     for (s, r) in LINKS:
