@@ -76,6 +76,10 @@ def parse():
                    help="no GPU run: write profiles/k_stat_wave_counters.txt from rocprofv3 --pmc CSV directories "
                         "of this bench's chosen statistic launch (with --templates, --chosen-store, "
                         "--chosen-layout, --block-waves, --groups-per-cu as profiled)")
+    p.add_argument("--vjp-profile", action="store_true",
+                   help="only the differentiation kernels, for profiling: on the 2-yr grid, the first 65,536 "
+                        "templates of the bench's bank, one FP32 statistic (with z_n) and --steps launches each of "
+                        "the statistic, the FP64 VJP and the FP32 VJP; prints one JSON line of event timings")
     p.add_argument("--fetch-factor", type=float, default=2.0,
                    help="bytes per FETCH_SIZE KiB / 1024 from the copy calibration")
     p.add_argument("--write-factor", type=float, default=1.0,
@@ -111,6 +115,9 @@ def main():
     dev = torch.device("cuda:0")
     g = ti.FULL
     grid = tfsc.GridSpec(g.n_channels, g.tranche_len, g.n_tranches, g.dt, 0.1)
+    if args.vjp_profile:
+        vjp_profile_run(args, tfsc, ti, g, grid, dev)
+        return
 
     log("generating synthetic data (noise, gaps, modulation) and bank")
     x = (ti.noise(g) * ti.sample_keep_mask(g)[None, :]).astype(np.float32)
@@ -319,6 +326,48 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, pix_o, u_o, wm_o, bank_h, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+
+
+def vjp_profile_run(args, tfsc, ti, g, grid, dev):
+    """Statistic and both VJP arithmetics on 65,536 templates of the 2-yr workload, timed with events on the
+    launch stream (the run rocprofv3 profiles for the VJP kernel)."""
+    import torch
+    x = (ti.noise(g) * ti.sample_keep_mask(g)[None, :]).astype(np.float32)
+    psd, mu, keep = ti.psd_on_bins(g), ti.tranche_psd_scale(g), ti.tranche_keep(g)
+    pix = tfsc.transform(grid, torch.from_numpy(x).to(dev), torch.from_numpy(psd).to(dev),
+                         torch.from_numpy(mu).to(dev), torch.from_numpy(keep).to(dev), dtype="f32", layout="layer_ci")
+    bank = tfsc.BankTensors.from_host(ti.full_bank(65536 - 20), dev)
+    seg = tfsc.segment_layout(grid, bank)
+    fw = tfsc.bank_statistic(grid, pix, bank, seg, precision="f32", want_zn=True)
+    ones = torch.ones(bank.n, dtype=torch.float64, device=dev)
+    g64 = tfsc.statistic_vjp(grid, pix, bank, seg, fw.seg_zn, g_stat=ones, precision="f64")
+    g32 = tfsc.statistic_vjp(grid, pix, bank, seg, fw.seg_zn, g_stat=ones, precision="f32")
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    t = {"statistic": [], "vjp_f64": [], "vjp_f32": []}
+    for i in range(args.steps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        ev[0].record(st)
+        tfsc.bank_statistic(grid, pix, bank, seg, precision="f32", want_zn=True, out=fw)
+        ev[1].record(st)
+        tfsc.statistic_vjp(grid, pix, bank, seg, fw.seg_zn, g_stat=ones, precision="f64", out=g64)
+        ev[2].record(st)
+        tfsc.statistic_vjp(grid, pix, bank, seg, fw.seg_zn, g_stat=ones, precision="f32", out=g32)
+        ev[3].record(st)
+        torch.cuda.synchronize()
+        for k, (a, b) in zip(t, ((0, 1), (1, 2), (2, 3))):
+            t[k].append(ev[a].elapsed_time(ev[b]))
+        log(f"vjp profile step {i + 1}/{args.steps}: statistic {t['statistic'][-1]:.2f} ms, VJP FP64 "
+            f"{t['vjp_f64'][-1]:.2f} ms, FP32 {t['vjp_f32'][-1]:.2f} ms")
+    med = {k: float(np.median(v)) for k, v in t.items()}
+    a, b = g64.cpu().numpy(), g32.cpu().numpy()
+    floor = 1e-3 * np.max(np.abs(a), axis=0, keepdims=True)
+    r = np.abs(b - a) / np.maximum(np.abs(a), np.maximum(floor, 1e-300))
+    print(json.dumps({"workload": "2-yr A+E, first 65,536 templates of the bench bank", "templates": bank.n,
+                      "median_ms": med, "f64_over_statistic": round(med["vjp_f64"] / med["statistic"], 3),
+                      "f32_over_statistic": round(med["vjp_f32"] / med["statistic"], 3),
+                      "f32_vs_f64_max_rel": float(r.max()), "f32_vs_f64_median_rel": float(np.median(r))}),
+          flush=True)
 
 
 def accuracy(stat, flags, ref):
@@ -611,31 +660,44 @@ def batching_run(args, tfsc, ti, grid, g, psd_d, mu_d, keep_d, kw, chosen_ms_per
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         fw = tfsc.bank_statistic(grid, store0, sub, sseg, precision="f32", want_zn=True)
         ones = torch.ones(sub.n, dtype=torch.float64, device=dev)
-        gp = tfsc.statistic_vjp(grid, store0, sub, sseg, fw.seg_zn, g_stat=ones)
+        gp = tfsc.statistic_vjp(grid, store0, sub, sseg, fw.seg_zn, g_stat=ones, precision="f64")
+        gp32 = tfsc.statistic_vjp(grid, store0, sub, sseg, fw.seg_zn, g_stat=ones, precision="f32")
         torch.cuda.synchronize()
         ev[0].record(st)
         tfsc.bank_statistic(grid, store0, sub, sseg, precision="f32", want_zn=True, out=fw)
         ev[1].record(st)
-        tfsc.statistic_vjp(grid, store0, sub, sseg, fw.seg_zn, g_stat=ones, out=gp)
+        tfsc.statistic_vjp(grid, store0, sub, sseg, fw.seg_zn, g_stat=ones, precision="f64", out=gp)
         ev[2].record(st)
+        tfsc.statistic_vjp(grid, store0, sub, sseg, fw.seg_zn, g_stat=ones, precision="f32", out=gp32)
+        ev[3].record(st)
         torch.cuda.synchronize()
-        f_ms, v_ms = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2])
-        log(f"follow-up candidates: statistic {f_ms:.1f} ms, VJP {v_ms:.1f} ms for 65536 templates "
-            f"({65536 / v_ms * 1e3 / 1e6:.3f} M templates/s)")
-        rec["vjp"] = {"templates": 65536, "statistic_ms": round(f_ms, 3), "vjp_ms": round(v_ms, 3),
-                      "vjp_over_statistic": round(v_ms / f_ms, 3),
-                      "vjp_over_chosen_per_template": round(v_ms / 65536 / chosen_ms_per_template, 3),
-                      "vjp_templates_per_s": round(65536 / v_ms * 1e3, 1), "arith": "f64"}
+        f_ms, v_ms, v32_ms = ev[0].elapsed_time(ev[1]), ev[1].elapsed_time(ev[2]), ev[2].elapsed_time(ev[3])
+        # the FP32 VJP against the FP64 one, per component relative to max(|g|, 1e-3 x the column's largest |g|)
+        g64 = gp.cpu().numpy()
+        floor = 1e-3 * np.max(np.abs(g64), axis=0, keepdims=True)
+        rel32 = np.abs(gp32.cpu().numpy() - g64) / np.maximum(np.abs(g64), np.maximum(floor, 1e-300))
+        log(f"follow-up candidates: statistic {f_ms:.1f} ms, VJP {v_ms:.1f} ms FP64 and {v32_ms:.1f} ms FP32 for "
+            f"65536 templates; FP32 vs FP64 gradient max rel {rel32.max():.2e}, median {np.median(rel32):.2e}")
+        rec["vjp"] = {"templates": 65536, "statistic_ms": round(f_ms, 3),
+                      "f64": {"vjp_ms": round(v_ms, 3), "vjp_over_statistic": round(v_ms / f_ms, 3),
+                              "vjp_over_chosen_per_template": round(v_ms / 65536 / chosen_ms_per_template, 3),
+                              "vjp_templates_per_s": round(65536 / v_ms * 1e3, 1)},
+                      "f32": {"vjp_ms": round(v32_ms, 3), "vjp_over_statistic": round(v32_ms / f_ms, 3),
+                              "vjp_over_chosen_per_template": round(v32_ms / 65536 / chosen_ms_per_template, 3),
+                              "vjp_templates_per_s": round(65536 / v32_ms * 1e3, 1),
+                              "vs_f64": {"max_rel": float(rel32.max()), "median_rel": float(np.median(rel32))}}}
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        first, best, _ = tfsc.follow_up(grid, store0, sub, steps=50, lr_scale=0.5, precision="f32")
+        first, best, _ = tfsc.follow_up(grid, store0, sub, steps=50, lr_scale=0.5, precision="f32",
+                                        vjp_precision="f32")
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         gain = (best - first).cpu().numpy()
         log(f"follow-up: 50 Adam steps on 65536 templates in {wall:.2f} s; gain median {np.median(gain):.2f}, "
             f"p90 {np.quantile(gain, 0.9):.2f}")
         rec["follow_up"] = {"workload": "top 65,536 templates of realisation 0 of the batching workload",
-                            "templates": 65536, "steps": 50, "wall_s": round(wall, 3),
+                            "templates": 65536, "steps": 50, "wall_s": round(wall, 3), "statistic": "f32",
+                            "vjp": "f32",
                             "gain_median": round(float(np.median(gain)), 3),
                             "gain_p90": round(float(np.quantile(gain, 0.9)), 3),
                             "start_median": round(float(first.median().item()), 3)}
@@ -643,7 +705,7 @@ def batching_run(args, tfsc, ti, grid, g, psd_d, mu_d, keep_d, kw, chosen_ms_per
 
 
 PROFILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "k_stat_wave_counters.txt")
-STAT_SOURCES = ("tfsc_stat.hip", "tfsc_device.hpp", "tfsc_kernels.hpp")
+STAT_SOURCES = ("tfsc_stat.hip", "tfsc_stat_common.hpp", "tfsc_device.hpp", "tfsc_kernels.hpp")
 SIMDS = 1024                  # 256 CUs x 4 SIMDs
 NOMINAL_CLOCK_HZ = 2.4e9
 CYCLES_PER_VALU = 4           # a wave64 instruction on a 16-lane SIMD

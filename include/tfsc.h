@@ -25,7 +25,7 @@
 extern "C" {
 #endif
 
-#define TFSC_ABI_VERSION 2
+#define TFSC_ABI_VERSION 3
 
 typedef enum {
     TFSC_OK = 0,
@@ -81,7 +81,18 @@ typedef struct {
  * writes it.  Read by tfsc_bank_statistic (THREAD schedule: every pixel
  * type; WAVE schedule: F64 or F32 pixels with the same arithmetic, or F32
  * pixels with F64 arithmetic), by tfsc_statistic_vjp (every pixel type) and
- * by tfsc_bank_statistic_multi (one rho for all realisations).             */
+ * by tfsc_bank_statistic_multi (one rho for all realisations).
+ *
+ * orbit: NULL for the rigid analytic orbit (first order in the eccentricity
+ * L / (2 sqrt3 R), paper Sec. "Implementation details").  Else the
+ * spacecraft positions of the caller's orbit (paper Sec. "Outlook": numerical
+ * or generic orbits at no extra cost), orbit[(3 i + x) Nt + m] = coordinate x
+ * of spacecraft i at t_m = m dT in light-seconds, FP64 [3][3][Nt], device
+ * memory owned by the caller.  The arm directions come from these positions;
+ * the link transfer and the TDI-1.5 combination keep the equal arm length
+ * L = 2.5e9 m.  tfsc_orbit_positions writes the analytic orbit in this
+ * layout (a table equal to it gives the same results bit for bit).  Read by
+ * every statistic call and the VJP.                                        */
 typedef struct {
     tfsc_dtype dtype;
     tfsc_layout layout;
@@ -90,15 +101,22 @@ typedef struct {
     double *inv_asd;
     double *tranche_w;
     float *rho;
+    const double *orbit;
 } tfsc_pixels;
 
 /* Template bank, structure of arrays, n templates, FP64:
  * mc [Msun] chirp mass; eta symmetric mass ratio (0.01..0.25); f0 [Hz] GW
  * frequency at t = 0; cos_theta, phi source direction (polar, azimuth);
- * psi polarisation angle; cos_iota inclination.  Track: 2PN TaylorT3.       */
+ * psi polarisation angle; cos_iota inclination.  Track: 2PN TaylorT3.
+ * The chirp mass is given either as mc or as ln_mc = ln(Mc / Msun) (the
+ * differentiable parameter of tfsc_statistic_vjp); exactly one of the two
+ * pointers is non-NULL (else TFSC_ERR_ARG).  With ln_mc the device forms
+ * Mc = exp(ln_mc) in FP64 (within an ulp of the host's exp), and
+ * tfsc_follow_up_step steps ln_mc in place.                                 */
 typedef struct {
     int64_t n;
     const double *mc, *eta, *f0, *cos_theta, *phi, *psi, *cos_iota;
+    const double *ln_mc;
 } tfsc_bank;
 
 /* Segment layout.  nseg_fixed > 0 gives every template that many segments;
@@ -129,14 +147,31 @@ typedef struct {
  * block (1..4) and resident blocks per compute unit (1..64); 0 = default
  * (4, 4); larger values return TFSC_ERR_ARG.  order: optional [n] permutation of template indices giving the
  * processing order (NULL = bank order); results are written at the
- * template's own index whatever the order.                                 */
+ * template's own index whatever the order.
+ * fresnel: TFSC_FRESNEL_PAPER -- the paper's Fresnel approximations (its
+ *            rational forms for |z| <= 6, one-term asymptotic forms above;
+ *            paper Sec. "Time-frequency waveform representation");
+ *          TFSC_FRESNEL_ACCURATE -- the Fresnel integrals themselves to
+ *            FP64 rounding in Eq. (fresnel-ft) (series, continued fraction
+ *            and asymptotic series of the auxiliary functions), every bin in
+ *            the general form: tfsc_bank_statistic with F64 pixels and F64
+ *            precision or F32 pixels and F32 precision, no rho (else
+ *            TFSC_ERR_UNSUPPORTED); the other calls accept only the paper's
+ *            forms.
+ * tune_key: NULL, or a key given to tfsc_tune_statistic earlier in this
+ *            process; with block_waves and groups_per_cu both 0 the WAVE
+ *            schedule then takes the launch shape tuned under that key
+ *            (the defaults if the key was never tuned).                    */
 enum { TFSC_SCHED_THREAD = 0, TFSC_SCHED_WAVE = 1 };
+enum { TFSC_FRESNEL_PAPER = 0, TFSC_FRESNEL_ACCURATE = 1 };
 typedef struct {
     int32_t precision;
     int32_t schedule;
     int32_t block_waves;
     int32_t groups_per_cu;
     const int32_t *order;
+    int32_t fresnel;
+    const char *tune_key;
 } tfsc_options;
 
 /* Per-template flag bits written by tfsc_bank_statistic. */
@@ -281,10 +316,13 @@ tfsc_status tfsc_bank_statistic_noalloc(const tfsc_grid *grid, const tfsc_pixels
  * almost-everywhere derivative).  The track, spectra and response are
  * recomputed with forward-mode tangents; nothing per pixel is stored.
  * seg_zn is the forward's output (tfsc_bank_statistic) for the same inputs;
- * g_stat[n] and/or g_seg[seg_offset[n]] may be NULL (not both).  Arithmetic
- * is FP64 for every pixel type and either layout; opt->precision, schedule
- * and order are ignored, block_waves and groups_per_cu set the launch.
- * Invalid and empty templates get 0.  Needs TFSC_WS_VJP workspace.         */
+ * g_stat[n] and/or g_seg[seg_offset[n]] may be NULL (not both).
+ * opt->precision TFSC_F64 (also opt == NULL): every tangent in FP64;
+ * TFSC_F32: spectra, response, pixel sums and their tangents in FP32, the
+ * track, its tangents, the phases and every integer decision in FP64 (as in
+ * the FP32 statistic); either arithmetic takes every pixel type and layout.
+ * schedule and order are ignored, block_waves and groups_per_cu set the
+ * launch.  Invalid and empty templates get 0.  Needs TFSC_WS_VJP workspace. */
 tfsc_status tfsc_statistic_vjp(const tfsc_grid *grid, const tfsc_pixels *pix, const tfsc_bank *bank,
                                const tfsc_segments *seg, const tfsc_options *opt, const double *seg_zn,
                                const double *g_stat, const double *g_seg, double *g_params, void *ws,
@@ -332,6 +370,51 @@ tfsc_status tfsc_follow_up_step(const tfsc_grid *grid, tfsc_bank *bank, const tf
  * into a HIP graph.  n = 0 is allowed; n_tiles >= 1.                       */
 tfsc_status tfsc_tile_max(const double *stat, const int32_t *tile, int64_t n, int32_t n_tiles, double *tile_max,
                           int64_t *tile_arg, void *stream);
+
+/* Multi-harmonic templates (paper Sec. "Outlook": the time-frequency
+ * representation extends to several harmonics by computing {A, f, fdot,
+ * phi} for each harmonic and applying the Fresnel expressions to each).
+ * harmonics[n_harm] (host memory, 1 <= n_harm <= TFSC_MAX_HARMONICS) are
+ * distinct harmonic numbers h = 1..8 of the orbital phase: harmonic h has
+ * phase (h/2) Phi, frequency (h/2) f and chirp (h/2) fdot of the template's
+ * TaylorT3 track, amplitude a_h f^(2/3) with amp[(i n_harm + q) 2 + {0, 1}]
+ * = (Re, Im) a_h of template i (device, FP64 [n][n_harm][2]), the
+ * polarisation pattern of the dominant harmonic and its own TDI transfer
+ * T_c(t_m, f_h).  Each harmonic fills its own 21 bins around
+ * ceil(f_h dT); a bin in several windows (low frequencies) holds the sum.
+ * The track ends at the merger condition or where the highest harmonic
+ * violates the band or compactness condition.  Upsilon, segment terms,
+ * (z_n, N_n), flags and n_active as in tfsc_bank_statistic.  WAVE schedule,
+ * LAYER_MAJOR or LAYER_MAJOR_CI, F64 pixels with F64 precision or F32 with
+ * F32 (else TFSC_ERR_DTYPE), no rho, the paper's Fresnel forms (else
+ * TFSC_ERR_UNSUPPORTED).  h = {2}, a = 1 is tfsc_bank_statistic's template.
+ * Needs TFSC_WS_STATISTIC workspace.                                       */
+#define TFSC_MAX_HARMONICS 4
+tfsc_status tfsc_bank_statistic_harmonics(const tfsc_grid *grid, const tfsc_pixels *pix, const tfsc_bank *bank,
+                                          const tfsc_segments *seg, const tfsc_options *opt, int32_t n_harm,
+                                          const int32_t *harmonics, const double *amp, double *seg_terms,
+                                          double *stat, double *seg_zn, int32_t *flags, int32_t *n_active, void *ws,
+                                          size_t ws_bytes, void *stream);
+
+/* The rigid analytic orbit's spacecraft positions at the tranche starts,
+ * out[(3 i + x) Nt + m] (light-seconds, FP64 [3][3][Nt], device), in the
+ * layout of tfsc_pixels.orbit (paper Sec. "Implementation details").        */
+tfsc_status tfsc_orbit_positions(const tfsc_grid *grid, double *out, void *stream);
+
+/* Launch-shape autotuner of the WAVE statistic (paper Sec. "Hardware
+ * acceleration and computational cost": large batches per launch): times
+ * tfsc_bank_statistic on the given (tuning) bank for eight launch shapes
+ * (waves per block x resident blocks per CU: 4x4, 4x3, 4x2, 2x8, 2x6, 2x4,
+ * 1x12, 1x8), the fastest of two launches each, after one warm-up launch;
+ * stores the fastest under tune_key for the rest of the process and writes
+ * it to *block_waves, *groups_per_cu.  Blocks the calling thread until the
+ * timed launches on `stream` are done.  opt as for tfsc_bank_statistic (its
+ * schedule, launch shape and tune_key are ignored); the outputs and the
+ * workspace are overwritten.                                               */
+tfsc_status tfsc_tune_statistic(const tfsc_grid *grid, const tfsc_pixels *pix, const tfsc_bank *bank,
+                                const tfsc_segments *seg, const tfsc_options *opt, const char *tune_key,
+                                double *seg_terms, double *stat, int32_t *flags, void *ws, size_t ws_bytes,
+                                void *stream, int32_t *block_waves, int32_t *groups_per_cu);
 
 /* The FP64 track behind every statistic call, for inspection: out[n][Nt][4]
  * holds (Phi_m, f_m, fdot_m, code_m) at each tranche start t_m = m dT, with

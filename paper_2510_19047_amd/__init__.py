@@ -16,14 +16,17 @@ from . import _lib
 from ._lib import TfscError
 
 __all__ = ["GridSpec", "PixelStore", "BankTensors", "SegmentLayout", "StatResult", "transform", "transform_tf", "segment_layout",
-           "bank_statistic", "bank_statistic_multi", "realisation_stores", "MultiResult", "statistic_vjp", "track",
-           "tile_max", "TFSCStatistic", "lib", "TfscError"]
+           "bank_statistic", "bank_statistic_multi", "bank_statistic_harmonics", "realisation_stores", "MultiResult",
+           "statistic_vjp", "track", "tile_max", "orbit_positions", "tune_statistic", "TFSCStatistic", "lib",
+           "TfscError"]
 
 _DTYPE = {"f64": _lib.F64, "f32": _lib.F32, "bf16": _lib.BF16, "f16": _lib.F16}
 _TORCH_STORE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
+_STORE16 = ("bf16", "f16")
 _LAYOUT = {"layer": _lib.LAYER_MAJOR, "tranche": _lib.TRANCHE_MAJOR, "layer_ci": _lib.LAYER_MAJOR_CI}
 _SCHED = {"thread": _lib.SCHED_THREAD, "wave": _lib.SCHED_WAVE}
 _PREC = {"f64": _lib.F64, "f32": _lib.F32}
+_FRESNEL = {"paper": _lib.FRESNEL_PAPER, "accurate": _lib.FRESNEL_ACCURATE}
 
 
 def lib():
@@ -73,12 +76,13 @@ class PixelStore:
     tranche_w: torch.Tensor           # [Nt] f64
     dtype: str = "f32"
     layout: str = "layer"
-    layer_scale: torch.Tensor | None = None  # [C][K] f32 for 16-bit stores
+    layer_scale: torch.Tensor | None = None  # [C][K] f32 for 16-bit stores (bf16, f16)
     rho: torch.Tensor | None = None   # [K][Nt] f32 per-pixel weight factor of a general per-tranche PSD
+    orbit: torch.Tensor | None = None  # [3][3][Nt] f64 spacecraft positions (light-seconds), None = analytic orbit
 
     def c(self) -> _lib.Pixels:
         return _lib.Pixels(_DTYPE[self.dtype], _LAYOUT[self.layout], _ptr(self.pix), _ptr(self.layer_scale),
-                           _ptr(self.inv_asd), _ptr(self.tranche_w), _ptr(self.rho))
+                           _ptr(self.inv_asd), _ptr(self.tranche_w), _ptr(self.rho), _ptr(self.orbit))
 
     @staticmethod
     def from_complex(pix: torch.Tensor, inv_asd: torch.Tensor, tranche_w: torch.Tensor, dtype: str = "f64",
@@ -96,20 +100,26 @@ class PixelStore:
 
 @dataclass
 class BankTensors:
-    """Template parameters as FP64 device tensors (see tfsc_bank)."""
-    mc: torch.Tensor
+    """Template parameters as FP64 device tensors (see tfsc_bank).  The chirp mass is given either as ``mc`` or
+    as ``ln_mc`` (then ``mc`` is None and the library forms exp(ln_mc) on the device)."""
+    mc: torch.Tensor | None
     eta: torch.Tensor
     f0: torch.Tensor
     cos_theta: torch.Tensor
     phi: torch.Tensor
     psi: torch.Tensor
     cos_iota: torch.Tensor
+    ln_mc: torch.Tensor | None = None
 
     FIELDS = ("mc", "eta", "f0", "cos_theta", "phi", "psi", "cos_iota")
 
     @property
     def n(self) -> int:
-        return int(self.mc.numel())
+        return int((self.mc if self.mc is not None else self.ln_mc).numel())
+
+    @property
+    def device(self):
+        return (self.mc if self.mc is not None else self.ln_mc).device
 
     @staticmethod
     def from_host(bank, device="cuda") -> "BankTensors":
@@ -118,7 +128,7 @@ class BankTensors:
                              for k in BankTensors.FIELDS))
 
     def c(self) -> _lib.Bank:
-        return _lib.Bank(self.n, *(_ptr(getattr(self, k)) for k in self.FIELDS))
+        return _lib.Bank(self.n, *(_ptr(getattr(self, k)) for k in self.FIELDS), _ptr(self.ln_mc))
 
 
 @dataclass
@@ -141,8 +151,10 @@ class StatResult:
     n_active: torch.Tensor | None = None  # [n] int32
 
 
-def _options(precision="f32", schedule="wave", block_waves=0, groups_per_cu=0, order=None) -> _lib.Options:
-    return _lib.Options(_PREC[precision], _SCHED[schedule], int(block_waves), int(groups_per_cu), _ptr(order))
+def _options(precision="f32", schedule="wave", block_waves=0, groups_per_cu=0, order=None, fresnel="paper",
+             tune_key: str | None = None) -> _lib.Options:
+    return _lib.Options(_PREC[precision], _SCHED[schedule], int(block_waves), int(groups_per_cu), _ptr(order),
+                        _FRESNEL[fresnel], None if tune_key is None else tune_key.encode())
 
 
 def transform(grid: GridSpec, x: torch.Tensor, psd0: torch.Tensor, mu: torch.Tensor, keep: torch.Tensor,
@@ -158,11 +170,11 @@ def transform(grid: GridSpec, x: torch.Tensor, psd0: torch.Tensor, mu: torch.Ten
         out = PixelStore(torch.empty(shape, dtype=_TORCH_STORE[dtype], device=dev),
                          torch.empty(K, dtype=torch.float64, device=dev), torch.empty(Nt, dtype=torch.float64, device=dev),
                          dtype, layout,
-                         torch.empty((C, K), dtype=torch.float32, device=dev) if dtype in ("bf16", "f16") else None)
+                         torch.empty((C, K), dtype=torch.float32, device=dev) if dtype in _STORE16 else None)
     g = grid.c()
     xd = _lib.F64 if x.dtype == torch.float64 else _lib.F32
     nb = L.tfsc_workspace_bytes(ctypes.byref(g), 0, None, _lib.WS_TRANSFORM)
-    ws = _ws(nb, dev) if dtype in ("bf16", "f16") else None
+    ws = _ws(nb, dev) if dtype in _STORE16 else None
     pc = out.c()
     st = L.tfsc_transform(ctypes.byref(g), _ptr(x), xd, _ptr(psd0), _ptr(mu), _ptr(keep), ctypes.byref(pc),
                           _ptr(ws), nb if ws is not None else 0, _stream())
@@ -186,14 +198,14 @@ def transform_tf(grid: GridSpec, x: torch.Tensor, psd_tf: torch.Tensor, keep: to
         out = PixelStore(torch.empty(shape, dtype=_TORCH_STORE[dtype], device=dev),
                          torch.empty(K, dtype=torch.float64, device=dev), torch.empty(Nt, dtype=torch.float64, device=dev),
                          dtype, layout,
-                         torch.empty((C, K), dtype=torch.float32, device=dev) if dtype in ("bf16", "f16") else None,
+                         torch.empty((C, K), dtype=torch.float32, device=dev) if dtype in _STORE16 else None,
                          torch.empty((K, Nt), dtype=torch.float32, device=dev))
     elif out.rho is None:
         raise TfscError("transform_tf needs a store with a rho tensor")
     g = grid.c()
     xd = _lib.F64 if x.dtype == torch.float64 else _lib.F32
     nb = L.tfsc_workspace_bytes(ctypes.byref(g), 0, None, _lib.WS_TRANSFORM)
-    ws = _ws(nb, dev) if dtype in ("bf16", "f16") else None
+    ws = _ws(nb, dev) if dtype in _STORE16 else None
     pc = out.c()
     st = L.tfsc_transform_tf(ctypes.byref(g), _ptr(x), xd, _ptr(psd_tf), _ptr(keep), ctypes.byref(pc), _ptr(ws),
                              nb if ws is not None else 0, _stream())
@@ -205,7 +217,7 @@ def segment_layout(grid: GridSpec, bank: BankTensors, nseg_fixed: int = 0, out: 
                    read_total: bool = True) -> SegmentLayout:
     """tfsc_segment_layout: N_seg per template and CSR offsets (reads the total back unless told not to)."""
     L = lib()
-    dev = bank.mc.device
+    dev = bank.device
     seg = out if out is not None else SegmentLayout(torch.empty(bank.n, dtype=torch.int32, device=dev),
                                                     torch.empty(bank.n + 1, dtype=torch.int64, device=dev), nseg_fixed)
     g = grid.c()
@@ -223,10 +235,12 @@ def segment_layout(grid: GridSpec, bank: BankTensors, nseg_fixed: int = 0, out: 
 def bank_statistic(grid: GridSpec, pixels: PixelStore, bank: BankTensors, seg: SegmentLayout,
                    precision: str = "f32", schedule: str = "wave", want_zn: bool = False, block_waves: int = 0,
                    groups_per_cu: int = 0, order: torch.Tensor | None = None, out: StatResult | None = None,
-                   ws: torch.Tensor | None = None, want_active: bool = False) -> StatResult:
-    """tfsc_bank_statistic: Upsilon, per-segment terms and flags for every template."""
+                   ws: torch.Tensor | None = None, want_active: bool = False, fresnel: str = "paper",
+                   tune_key: str | None = None) -> StatResult:
+    """tfsc_bank_statistic: Upsilon, per-segment terms and flags for every template (``fresnel``: "paper" for the
+    paper's Fresnel forms, "accurate" for the Fresnel integrals)."""
     L = lib()
-    dev = bank.mc.device
+    dev = bank.device
     if out is None:
         out = StatResult(torch.empty(bank.n, dtype=torch.float64, device=dev),
                          torch.empty(max(seg.total, 1), dtype=torch.float64, device=dev),
@@ -234,7 +248,7 @@ def bank_statistic(grid: GridSpec, pixels: PixelStore, bank: BankTensors, seg: S
                          torch.empty((max(seg.total, 1), 3), dtype=torch.float64, device=dev) if want_zn else None,
                          torch.empty(bank.n, dtype=torch.int32, device=dev) if want_active else None)
     g = grid.c()
-    opt = _options(precision, schedule, block_waves, groups_per_cu, order)
+    opt = _options(precision, schedule, block_waves, groups_per_cu, order, fresnel, tune_key)
     nb = L.tfsc_workspace_bytes(ctypes.byref(g), bank.n, ctypes.byref(opt), _lib.WS_STATISTIC)
     if ws is None or ws.numel() < nb:
         ws = _ws(nb, dev)
@@ -253,7 +267,7 @@ def bank_statistic_noalloc(grid: GridSpec, pixels: PixelStore, bank: BankTensors
     """tfsc_bank_statistic_noalloc: bank_statistic with the library's static device scratch as workspace (the
     call allocates no device memory; outputs are allocated here only when ``out`` is not given)."""
     L = lib()
-    dev = bank.mc.device
+    dev = bank.device
     if out is None:
         out = StatResult(torch.empty(bank.n, dtype=torch.float64, device=dev),
                          torch.empty(max(seg.total, 1), dtype=torch.float64, device=dev),
@@ -268,6 +282,72 @@ def bank_statistic_noalloc(grid: GridSpec, pixels: PixelStore, bank: BankTensors
                                        _ptr(out.flags), _ptr(out.n_active), _stream())
     _lib.check(st, "tfsc_bank_statistic_noalloc")
     return out
+
+
+def bank_statistic_harmonics(grid: GridSpec, pixels: PixelStore, bank: BankTensors, seg: SegmentLayout,
+                             harmonics, amp: torch.Tensor, precision: str = "f32", want_zn: bool = False,
+                             block_waves: int = 0, groups_per_cu: int = 0, order: torch.Tensor | None = None,
+                             out: StatResult | None = None, want_active: bool = False) -> StatResult:
+    """tfsc_bank_statistic_harmonics: the statistic of templates made of harmonics h (of the orbital phase) with
+    complex factors amp [n][H] (complex128, or float64 [n][H][2]) per template and harmonic."""
+    L = lib()
+    dev = bank.device
+    hs = [int(h) for h in harmonics]
+    H = len(hs)
+    if amp.dtype == torch.complex128:
+        amp = torch.view_as_real(amp.contiguous())
+    if tuple(amp.shape) != (bank.n, H, 2) or amp.dtype != torch.float64:
+        raise TfscError(f"amp must be complex128 [{bank.n}, {H}] or float64 [{bank.n}, {H}, 2]")
+    amp = amp.contiguous()
+    if out is None:
+        out = StatResult(torch.empty(bank.n, dtype=torch.float64, device=dev),
+                         torch.empty(max(seg.total, 1), dtype=torch.float64, device=dev),
+                         torch.empty(bank.n, dtype=torch.int32, device=dev),
+                         torch.empty((max(seg.total, 1), 3), dtype=torch.float64, device=dev) if want_zn else None,
+                         torch.empty(bank.n, dtype=torch.int32, device=dev) if want_active else None)
+    g = grid.c()
+    opt = _options(precision, "wave", block_waves, groups_per_cu, order)
+    nb = L.tfsc_workspace_bytes(ctypes.byref(g), bank.n, ctypes.byref(opt), _lib.WS_STATISTIC)
+    ws = _ws(nb, dev)
+    harr = (ctypes.c_int32 * max(H, 1))(*hs)
+    pc, bc, sc = pixels.c(), bank.c(), seg.c()
+    st = L.tfsc_bank_statistic_harmonics(ctypes.byref(g), ctypes.byref(pc), ctypes.byref(bc), ctypes.byref(sc),
+                                         ctypes.byref(opt), H, harr, _ptr(amp), _ptr(out.seg_terms), _ptr(out.stat),
+                                         _ptr(out.seg_zn), _ptr(out.flags), _ptr(out.n_active), _ptr(ws), ws.numel(),
+                                         _stream())
+    _lib.check(st, "tfsc_bank_statistic_harmonics")
+    return out
+
+
+def orbit_positions(grid: GridSpec, device="cuda") -> torch.Tensor:
+    """tfsc_orbit_positions: the analytic orbit's spacecraft positions [3][3][Nt] (light-seconds, FP64)."""
+    L = lib()
+    out = torch.empty((3, 3, grid.n_tranches), dtype=torch.float64, device=device)
+    g = grid.c()
+    _lib.check(L.tfsc_orbit_positions(ctypes.byref(g), _ptr(out), _stream()), "tfsc_orbit_positions")
+    return out
+
+
+def tune_statistic(grid: GridSpec, pixels: PixelStore, bank: BankTensors, seg: SegmentLayout, tune_key: str,
+                   precision: str = "f32", order: torch.Tensor | None = None) -> tuple[int, int]:
+    """tfsc_tune_statistic: the library's launch-shape autotuner on a tuning bank; returns (block_waves,
+    groups_per_cu), also kept by the library under ``tune_key`` for bank_statistic(..., tune_key=...)."""
+    L = lib()
+    dev = bank.device
+    res = StatResult(torch.empty(bank.n, dtype=torch.float64, device=dev),
+                     torch.empty(max(seg.total, 1), dtype=torch.float64, device=dev),
+                     torch.empty(bank.n, dtype=torch.int32, device=dev))
+    g = grid.c()
+    opt = _options(precision, "wave", 0, 0, order)
+    nb = L.tfsc_workspace_bytes(ctypes.byref(g), bank.n, ctypes.byref(opt), _lib.WS_STATISTIC)
+    ws = _ws(nb, dev)
+    pc, bc, sc = pixels.c(), bank.c(), seg.c()
+    bw, gpc = ctypes.c_int32(0), ctypes.c_int32(0)
+    st = L.tfsc_tune_statistic(ctypes.byref(g), ctypes.byref(pc), ctypes.byref(bc), ctypes.byref(sc),
+                               ctypes.byref(opt), tune_key.encode(), _ptr(res.seg_terms), _ptr(res.stat),
+                               _ptr(res.flags), _ptr(ws), ws.numel(), _stream(), ctypes.byref(bw), ctypes.byref(gpc))
+    _lib.check(st, "tfsc_tune_statistic")
+    return int(bw.value), int(gpc.value)
 
 
 def realisation_stores(grid: GridSpec, n_real: int, dtype: str = "f32", layout: str = "layer_ci",
@@ -304,7 +384,7 @@ def bank_statistic_multi(grid: GridSpec, stores: list, bank: BankTensors, seg: S
     or any stores laid out at one stride in one block), ``group`` realisations (1, 2, 4, 8; 0 = 8) per pass
     over the bank."""
     L = lib()
-    dev = bank.mc.device
+    dev = bank.device
     R = len(stores)
     if R == 0:
         raise TfscError("no realisations")
@@ -334,14 +414,15 @@ def bank_statistic_multi(grid: GridSpec, stores: list, bank: BankTensors, seg: S
 
 
 def statistic_vjp(grid: GridSpec, pixels: PixelStore, bank: BankTensors, seg: SegmentLayout, seg_zn: torch.Tensor,
-                  g_stat: torch.Tensor | None = None, g_seg: torch.Tensor | None = None, precision: str = "f32",
+                  g_stat: torch.Tensor | None = None, g_seg: torch.Tensor | None = None, precision: str = "f64",
                   block_waves: int = 0, groups_per_cu: int = 0, out: torch.Tensor | None = None) -> torch.Tensor:
-    """tfsc_statistic_vjp: [n][5] gradient w.r.t. (ln Mc, f0, cos theta, phi, psi), computed in FP64.
+    """tfsc_statistic_vjp: [n][5] gradient w.r.t. (ln Mc, f0, cos theta, phi, psi).
 
-    ``precision`` is accepted for symmetry with bank_statistic and does not change the arithmetic.
+    ``precision`` "f64" computes every tangent in FP64; "f32" computes spectra, response and tangents in FP32
+    (the track, phases and integer decisions stay FP64), for any pixel type.
     """
     L = lib()
-    dev = bank.mc.device
+    dev = bank.device
     if out is None:
         out = torch.empty((bank.n, 5), dtype=torch.float64, device=dev)
     g = grid.c()
@@ -359,7 +440,7 @@ def statistic_vjp(grid: GridSpec, pixels: PixelStore, bank: BankTensors, seg: Se
 def processing_order(grid: GridSpec, bank: BankTensors, out: torch.Tensor | None = None) -> torch.Tensor:
     """tfsc_processing_order: an int32 permutation grouping templates by the frequency bin of f0."""
     L = lib()
-    dev = bank.mc.device
+    dev = bank.device
     if out is None:
         out = torch.empty(max(bank.n, 1), dtype=torch.int32, device=dev)
     g, bc = grid.c(), bank.c()
@@ -381,15 +462,16 @@ def follow_up_step(grid: GridSpec, bank: BankTensors, seg: SegmentLayout, stat: 
 
 
 def follow_up(grid: GridSpec, pixels: PixelStore, bank: BankTensors, steps: int = 50, lr_scale: float = 0.5,
-              nseg_fixed: int = 0, precision: str = "f32"):
+              nseg_fixed: int = 0, precision: str = "f32", vjp_precision: str = "f64"):
     """Gradient-ascent follow-up of a candidate set: ``steps`` rounds of statistic, VJP and Adam step.
 
-    The segment layout is fixed at the candidates' initial parameters.  Returns (initial Upsilon, best
-    Upsilon, best parameters [n][5] = (mc, f0, cos theta, phi, psi)).  ``bank`` is not modified.
+    ``precision`` is the statistic's arithmetic and ``vjp_precision`` the VJP's.  The segment layout is fixed
+    at the candidates' initial parameters.  Returns (initial Upsilon, best Upsilon, best parameters [n][5] =
+    (mc, f0, cos theta, phi, psi)).  ``bank`` is not modified.
     """
-    dev = bank.mc.device
-    work = BankTensors(*(t.clone() for t in (bank.mc, bank.eta, bank.f0, bank.cos_theta, bank.phi, bank.psi,
-                                             bank.cos_iota)))
+    dev = bank.device
+    work = BankTensors(*(None if getattr(bank, k) is None else getattr(bank, k).clone() for k in BankTensors.FIELDS),
+                       ln_mc=None if bank.ln_mc is None else bank.ln_mc.clone())
     seg = segment_layout(grid, work, nseg_fixed)
     state = torch.empty((work.n, 16), dtype=torch.float64, device=dev)
     ones = torch.ones(work.n, dtype=torch.float64, device=dev)
@@ -403,7 +485,7 @@ def follow_up(grid: GridSpec, pixels: PixelStore, bank: BankTensors, steps: int 
         if step == steps + 1:
             follow_up_step(grid, work, seg, res.stat, gp, state, 0.0, step)  # record the last point only
             break
-        statistic_vjp(grid, pixels, work, seg, res.seg_zn, g_stat=ones, out=gp)
+        statistic_vjp(grid, pixels, work, seg, res.seg_zn, g_stat=ones, precision=vjp_precision, out=gp)
         follow_up_step(grid, work, seg, res.stat, gp, state, lr_scale, step)
     return first, state[:, 10].clone(), state[:, 11:16].clone()
 
@@ -426,7 +508,7 @@ def tile_max(stat: torch.Tensor, tile: torch.Tensor, n_tiles: int, out: tuple | 
 def track(grid: GridSpec, bank: BankTensors) -> torch.Tensor:
     """tfsc_track: [n][Nt][4] = (Phi, f, fdot, end code) at every tranche start (FP64)."""
     L = lib()
-    out = torch.empty((bank.n, grid.n_tranches, 4), dtype=torch.float64, device=bank.mc.device)
+    out = torch.empty((bank.n, grid.n_tranches, 4), dtype=torch.float64, device=bank.device)
     g, bc = grid.c(), bank.c()
     _lib.check(L.tfsc_track(ctypes.byref(g), ctypes.byref(bc), _ptr(out), _stream()), "tfsc_track")
     return out
@@ -436,14 +518,15 @@ class TFSCStatistic(torch.autograd.Function):
     """Upsilon as a differentiable function of (ln Mc, f0, cos theta, phi, psi); the backward is the HIP VJP.
 
     forward(ctx, ln_mc, f0, cos_theta, phi, psi, fixed) with ``fixed`` a dict holding grid, pixels, eta,
-    cos_iota, nseg_fixed and precision.  The segment layout is recomputed for the given parameters.
+    cos_iota, nseg_fixed, precision (the forward's) and vjp_precision (the backward's, "f64" by default).
+    The segment layout is recomputed for the given parameters.
     """
 
     @staticmethod
     def forward(ctx, ln_mc, f0, cos_theta, phi, psi, fixed):
         grid, pixels = fixed["grid"], fixed["pixels"]
-        bank = BankTensors(torch.exp(ln_mc).contiguous(), fixed["eta"], f0.contiguous(), cos_theta.contiguous(),
-                           phi.contiguous(), psi.contiguous(), fixed["cos_iota"])
+        bank = BankTensors(None, fixed["eta"], f0.contiguous(), cos_theta.contiguous(), phi.contiguous(),
+                           psi.contiguous(), fixed["cos_iota"], ln_mc=ln_mc.contiguous())
         seg = segment_layout(grid, bank, fixed.get("nseg_fixed", 0))
         res = bank_statistic(grid, pixels, bank, seg, precision=fixed.get("precision", "f32"), want_zn=True)
         ctx.fixed = fixed
@@ -454,5 +537,5 @@ class TFSCStatistic(torch.autograd.Function):
     def backward(ctx, g):
         fixed = ctx.fixed
         gp = statistic_vjp(fixed["grid"], fixed["pixels"], ctx.bank, ctx.seg, ctx.zn,
-                           g_stat=g.contiguous().to(torch.float64), precision=fixed.get("precision", "f32"))
+                           g_stat=g.contiguous().to(torch.float64), precision=fixed.get("vjp_precision", "f64"))
         return gp[:, 0], gp[:, 1], gp[:, 2], gp[:, 3], gp[:, 4], None

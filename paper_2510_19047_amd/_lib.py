@@ -11,6 +11,9 @@ c_int32, c_int64, c_double, c_void_p, c_size_t = ctypes.c_int32, ctypes.c_int64,
 
 TFSC_OK = 0
 TFSC_ERR_SCRATCH = 7
+ABI_VERSION = 3
+MAX_HARMONICS = 4
+FRESNEL_PAPER, FRESNEL_ACCURATE = 0, 1
 NOALLOC_MAX_TRANCHES = 16384
 F64, F32, BF16, F16 = 0, 1, 2, 3
 LAYER_MAJOR, TRANCHE_MAJOR, LAYER_MAJOR_CI = 0, 1, 2
@@ -26,12 +29,12 @@ class Grid(ctypes.Structure):
 
 class Pixels(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int), ("layout", ctypes.c_int), ("pix", c_void_p), ("layer_scale", c_void_p),
-                ("inv_asd", c_void_p), ("tranche_w", c_void_p), ("rho", c_void_p)]
+                ("inv_asd", c_void_p), ("tranche_w", c_void_p), ("rho", c_void_p), ("orbit", c_void_p)]
 
 
 class Bank(ctypes.Structure):
     _fields_ = [("n", c_int64), ("mc", c_void_p), ("eta", c_void_p), ("f0", c_void_p), ("cos_theta", c_void_p),
-                ("phi", c_void_p), ("psi", c_void_p), ("cos_iota", c_void_p)]
+                ("phi", c_void_p), ("psi", c_void_p), ("cos_iota", c_void_p), ("ln_mc", c_void_p)]
 
 
 class Segments(ctypes.Structure):
@@ -40,14 +43,15 @@ class Segments(ctypes.Structure):
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("schedule", c_int32), ("block_waves", c_int32), ("groups_per_cu", c_int32),
-                ("order", c_void_p)]
+                ("order", c_void_p), ("fresnel", c_int32), ("tune_key", ctypes.c_char_p)]
 
 
 EXPORTS = ("tfsc_abi_version", "tfsc_status_string", "tfsc_workspace_bytes", "tfsc_transform", "tfsc_transform_tf",
            "tfsc_segment_layout", "tfsc_bank_statistic", "tfsc_bank_statistic_noalloc", "tfsc_bank_statistic_multi",
            "tfsc_statistic_vjp",
            "tfsc_follow_up_step",
-           "tfsc_processing_order", "tfsc_tile_max", "tfsc_track")
+           "tfsc_processing_order", "tfsc_tile_max", "tfsc_track", "tfsc_bank_statistic_harmonics",
+           "tfsc_orbit_positions", "tfsc_tune_statistic")
 
 _lib = None
 
@@ -102,6 +106,16 @@ def load(path: str = LIB_PATH):
     L.tfsc_tile_max.argtypes = [c_void_p, c_void_p, ctypes.c_int64, ctypes.c_int32, c_void_p, c_void_p, c_void_p]
     L.tfsc_track.restype = ctypes.c_int
     L.tfsc_track.argtypes = [P(Grid), P(Bank), c_void_p, c_void_p]
+    L.tfsc_bank_statistic_harmonics.restype = ctypes.c_int
+    L.tfsc_bank_statistic_harmonics.argtypes = [P(Grid), P(Pixels), P(Bank), P(Segments), P(Options), c_int32,
+                                                P(c_int32), c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                                c_void_p, c_void_p, c_size_t, c_void_p]
+    L.tfsc_orbit_positions.restype = ctypes.c_int
+    L.tfsc_orbit_positions.argtypes = [P(Grid), c_void_p, c_void_p]
+    L.tfsc_tune_statistic.restype = ctypes.c_int
+    L.tfsc_tune_statistic.argtypes = [P(Grid), P(Pixels), P(Bank), P(Segments), P(Options), ctypes.c_char_p,
+                                      c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p, P(c_int32),
+                                      P(c_int32)]
     _lib = L
     return L
 

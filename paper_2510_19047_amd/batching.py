@@ -4,8 +4,8 @@ Paper Sec. "Hardware acceleration and computational cost": the method evaluates 
 parameter sets per launch.  Here that is one persistent launch over the whole bank, with
 
 * ``autotune``: the WAVE schedule's launch shape (waves per block, resident blocks per compute unit)
-  chosen by timing candidates with HIP events on a tuning bank, cached in a JSON file keyed by the
-  device and the workload's shape;
+  chosen by the library's tuner (tfsc_tune_statistic: candidates timed with HIP events on a tuning
+  bank), cached in a JSON file keyed by the device and the workload's shape;
 * ``RealisationGraph``: the sequence transform(r) -> bank_statistic(r) for R noise realisations of
   the same grid, captured once into a HIP graph (torch.cuda.CUDAGraph) and replayed.  Every kernel
   in it is a launch (work counters are cleared by a fill kernel, never by a memset node).
@@ -20,9 +20,7 @@ import os
 import torch
 
 from . import (BankTensors, GridSpec, PixelStore, SegmentLayout, StatResult, bank_statistic, bank_statistic_multi,
-               realisation_stores, transform)
-
-CANDIDATES = ((4, 4), (4, 3), (4, 2), (2, 8), (2, 6), (2, 4), (1, 12), (1, 8))
+               realisation_stores, transform, tune_statistic)
 
 
 def _cache_path(path: str | None) -> str:
@@ -40,11 +38,11 @@ def _key(grid: GridSpec, pixels: PixelStore, precision: str) -> str:
 
 
 def autotune(grid: GridSpec, pixels: PixelStore, bank: BankTensors, seg: SegmentLayout, precision: str = "f32",
-             order: torch.Tensor | None = None, candidates=CANDIDATES, reps: int = 2, cache: str | None = None,
-             refresh: bool = False) -> tuple[int, int]:
+             order: torch.Tensor | None = None, cache: str | None = None, refresh: bool = False) -> tuple[int, int]:
     """(block_waves, groups_per_cu) with the shortest WAVE statistic launch on ``bank`` (a tuning bank).
 
-    The result is cached under the device name and workload shape; ``refresh`` re-times it.
+    The timing is the library's own tuner (tfsc_tune_statistic, eight launch shapes); the result is also cached
+    on disk under the device name and workload shape, and ``refresh`` re-times it.
     """
     path = _cache_path(cache)
     key = _key(grid, pixels, precision)
@@ -58,22 +56,8 @@ def autotune(grid: GridSpec, pixels: PixelStore, bank: BankTensors, seg: Segment
     if key in table and not refresh:
         bw, gpc = table[key]["shape"]
         return int(bw), int(gpc)
-    res = bank_statistic(grid, pixels, bank, seg, precision=precision, schedule="wave", order=order)
-    ws = torch.empty(1 << 22, dtype=torch.uint8, device=bank.mc.device)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    timings = {}
-    for bw, gpc in candidates:
-        ts = []
-        for _ in range(reps):
-            ev[0].record()
-            bank_statistic(grid, pixels, bank, seg, precision=precision, schedule="wave", order=order, out=res,
-                           ws=ws, block_waves=bw, groups_per_cu=gpc)
-            ev[1].record()
-            torch.cuda.synchronize()
-            ts.append(ev[0].elapsed_time(ev[1]))
-        timings[f"{bw}x{gpc}"] = min(ts)
-    best = min(candidates, key=lambda c: timings[f"{c[0]}x{c[1]}"])
-    table[key] = {"shape": list(best), "ms": timings, "tuning_templates": bank.n}
+    best = tune_statistic(grid, pixels, bank, seg, key, precision=precision, order=order)
+    table[key] = {"shape": list(best), "tuning_templates": bank.n}
     try:
         os.makedirs(os.path.dirname(path), exist_ok=True)
         with open(path, "w") as fh:
@@ -102,7 +86,7 @@ class RealisationGraph:
         self.shape = dict(block_waves=block_waves, groups_per_cu=groups_per_cu)
         self.multi, self.group = multi, group
         R = xs.shape[0]
-        dev = bank.mc.device
+        dev = bank.device
         if multi:
             self.stores = realisation_stores(grid, R, dtype=store, layout=layout, device=dev)
             for r in range(R):

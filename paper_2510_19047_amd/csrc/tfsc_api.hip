@@ -2,7 +2,9 @@
 #include <math.h>
 #include <string.h>
 
+#include <map>
 #include <mutex>
+#include <string>
 
 #include "../../include/tfsc.h"
 #include "tfsc_kernels.hpp"
@@ -48,8 +50,9 @@ tfsc_status check_grid(const tfsc_grid *g) {
 tfsc_status check_bank(const tfsc_bank *b) {
     if (!b) return TFSC_ERR_ARG;
     if (b->n < 0 || b->n > 0x7fffffffLL) return TFSC_ERR_SHAPE;
-    if (b->n > 0 && (!b->mc || !b->eta || !b->f0 || !b->cos_theta || !b->phi || !b->psi || !b->cos_iota))
-        return TFSC_ERR_ARG;
+    // exactly one of mc and ln_mc
+    if (b->n > 0 && ((!b->mc) == (!b->ln_mc))) return TFSC_ERR_ARG;
+    if (b->n > 0 && (!b->eta || !b->f0 || !b->cos_theta || !b->phi || !b->psi || !b->cos_iota)) return TFSC_ERR_ARG;
     return TFSC_OK;
 }
 
@@ -65,9 +68,19 @@ tfsc_status check_pixels(const tfsc_pixels *p, bool need_data) {
 }
 
 struct Resolved {
-    int precision, schedule, block_waves, groups_per_cu;
+    int precision, schedule, block_waves, groups_per_cu, fresnel;
     const int32_t *order;
 };
+
+// Launch shapes chosen by tfsc_tune_statistic, per tune key, for the life of the process.
+struct TuneTable {
+    std::mutex mu;
+    std::map<std::string, std::pair<int, int>> shape;
+};
+TuneTable &tune_table() {
+    static TuneTable t;
+    return t;
+}
 
 tfsc_status resolve_options(const tfsc_options *o, const tfsc_pixels *p, Resolved &r) {
     r.precision = o ? o->precision : TFSC_F64;
@@ -75,6 +88,17 @@ tfsc_status resolve_options(const tfsc_options *o, const tfsc_pixels *p, Resolve
     r.block_waves = (o && o->block_waves > 0) ? o->block_waves : 4;
     r.groups_per_cu = (o && o->groups_per_cu > 0) ? o->groups_per_cu : 4;
     r.order = o ? o->order : nullptr;
+    r.fresnel = o ? o->fresnel : TFSC_FRESNEL_PAPER;
+    if (o && o->tune_key && o->block_waves <= 0 && o->groups_per_cu <= 0) {
+        TuneTable &t = tune_table();
+        std::lock_guard<std::mutex> lock(t.mu);
+        auto it = t.shape.find(o->tune_key);
+        if (it != t.shape.end()) {
+            r.block_waves = it->second.first;
+            r.groups_per_cu = it->second.second;
+        }
+    }
+    if (r.fresnel != TFSC_FRESNEL_PAPER && r.fresnel != TFSC_FRESNEL_ACCURATE) return TFSC_ERR_ARG;
     if (r.precision != TFSC_F64 && r.precision != TFSC_F32) return TFSC_ERR_DTYPE;
     if (r.schedule != TFSC_SCHED_THREAD && r.schedule != TFSC_SCHED_WAVE) return TFSC_ERR_ARG;
     // the WAVE and VJP kernels are compiled for at most 256 threads (4 waves) per block
@@ -161,6 +185,7 @@ tfsc::StatLaunch stat_launch(const tfsc_grid *grid, const tfsc_pixels *pix, cons
     L.phi = bank->phi;
     L.psi = bank->psi;
     L.ci = bank->cos_iota;
+    L.ln_mc = bank->ln_mc;
     L.nseg = seg->nseg;
     L.seg_offset = seg->seg_offset;
     L.order = r.order;
@@ -211,6 +236,7 @@ tfsc_status tfsc_segment_layout(const tfsc_grid *grid, const tfsc_bank *bank, tf
     L.f0 = bank->f0;
     L.ct = bank->cos_theta;
     L.ci = bank->cos_iota;
+    L.ln_mc = bank->ln_mc;
     L.nseg_fixed = seg->nseg_fixed;
     L.nseg = seg->nseg;
     L.seg_offset = seg->seg_offset;
@@ -234,9 +260,13 @@ tfsc_status tfsc_bank_statistic(const tfsc_grid *grid, const tfsc_pixels *pix, c
     if (r.schedule == TFSC_SCHED_WAVE && pixel_store_bytes(grid, pix) > 0xffffffffull) return TFSC_ERR_UNSUPPORTED;
     if (pix->rho && r.schedule == TFSC_SCHED_WAVE && pix->dtype != TFSC_F64 && pix->dtype != TFSC_F32)
         return TFSC_ERR_UNSUPPORTED;
+    if (r.fresnel == TFSC_FRESNEL_ACCURATE &&
+        (pix->rho || !((pix->dtype == TFSC_F64 && r.precision == TFSC_F64) ||
+                       (pix->dtype == TFSC_F32 && r.precision == TFSC_F32))))
+        return TFSC_ERR_UNSUPPORTED;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (bank->n == 0) return TFSC_OK;
-    hipError_t e = tfsc::launch_geometry(grid->n_tranches, (double)grid->tranche_len * grid->dt,
+    hipError_t e = tfsc::launch_geometry(grid->n_tranches, (double)grid->tranche_len * grid->dt, pix->orbit,
                                          reinterpret_cast<double *>(ws), st);
     if (e != hipSuccess) return TFSC_ERR_HIP;
     tfsc::StatLaunch L = stat_launch(grid, pix, bank, seg, r, ws);
@@ -247,6 +277,7 @@ tfsc_status tfsc_bank_statistic(const tfsc_grid *grid, const tfsc_pixels *pix, c
     L.seg_zn = seg_zn;
     L.flags = flags;
     L.n_active = n_active;
+    if (r.fresnel == TFSC_FRESNEL_ACCURATE) return hip_status(tfsc::launch_statistic_accurate(L, st));
     return hip_status(tfsc::launch_statistic(L, st));
 }
 
@@ -278,7 +309,8 @@ tfsc_status tfsc_bank_statistic_multi(const tfsc_grid *grid, const tfsc_pixels *
     if (group != 0 && group != 1 && group != 2 && group != 4 && group != 8) return TFSC_ERR_ARG;
     Resolved r;
     if ((s = resolve_options(opt, pix, r)) != TFSC_OK) return s;
-    if (r.schedule != TFSC_SCHED_WAVE || pix->layout == TFSC_TRANCHE_MAJOR || grid->n_channels == 3)
+    if (r.schedule != TFSC_SCHED_WAVE || pix->layout == TFSC_TRANCHE_MAJOR || grid->n_channels == 3 ||
+        r.fresnel != TFSC_FRESNEL_PAPER)
         return TFSC_ERR_UNSUPPORTED;
     if (!(pix->dtype == TFSC_F32 && r.precision == TFSC_F32) && !(pix->dtype == TFSC_F64 && r.precision == TFSC_F64))
         return TFSC_ERR_DTYPE;
@@ -289,7 +321,7 @@ tfsc_status tfsc_bank_statistic_multi(const tfsc_grid *grid, const tfsc_pixels *
     if (!ws || ws_bytes < ws_bytes_for(grid, bank->n, TFSC_WS_STATISTIC)) return TFSC_ERR_WORKSPACE;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (bank->n == 0) return TFSC_OK;
-    hipError_t e = tfsc::launch_geometry(grid->n_tranches, (double)grid->tranche_len * grid->dt,
+    hipError_t e = tfsc::launch_geometry(grid->n_tranches, (double)grid->tranche_len * grid->dt, pix->orbit,
                                          reinterpret_cast<double *>(ws), st);
     if (e != hipSuccess) return TFSC_ERR_HIP;
     tfsc::StatLaunch L = stat_launch(grid, pix, bank, seg, r, ws);
@@ -315,15 +347,15 @@ tfsc_status tfsc_statistic_vjp(const tfsc_grid *grid, const tfsc_pixels *pix, co
     if ((s = check_bank(bank)) != TFSC_OK) return s;
     if ((s = check_pixels(pix, bank->n > 0)) != TFSC_OK) return s;
     if (!seg || (bank->n > 0 && (!seg->nseg || !seg->seg_offset))) return TFSC_ERR_ARG;
-    // The VJP computes in FP64 for every pixel type and layout; only the launch shape is taken
-    // from the options.
+    // Either arithmetic reads every pixel type and layout (no pixel check against the precision).
     Resolved r;
     if ((s = resolve_options(opt, nullptr, r)) != TFSC_OK) return s;
+    if (r.fresnel != TFSC_FRESNEL_PAPER) return TFSC_ERR_UNSUPPORTED;
     if (bank->n > 0 && (!seg_zn || !g_params || (!g_stat && !g_seg))) return TFSC_ERR_ARG;
     if (!ws || ws_bytes < ws_bytes_for(grid, bank->n, TFSC_WS_VJP)) return TFSC_ERR_WORKSPACE;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (bank->n == 0) return TFSC_OK;
-    hipError_t e = tfsc::launch_geometry(grid->n_tranches, (double)grid->tranche_len * grid->dt,
+    hipError_t e = tfsc::launch_geometry(grid->n_tranches, (double)grid->tranche_len * grid->dt, pix->orbit,
                                          reinterpret_cast<double *>(ws), st);
     if (e != hipSuccess) return TFSC_ERR_HIP;
     tfsc::VjpLaunch V;
@@ -353,6 +385,7 @@ tfsc_status tfsc_processing_order(const tfsc_grid *grid, const tfsc_bank *bank, 
     L.f0 = bank->f0;
     L.ct = bank->cos_theta;
     L.ci = bank->cos_iota;
+    L.ln_mc = bank->ln_mc;
     L.order = order;
     L.ws = reinterpret_cast<uint32_t *>(ws);
     return hip_status(tfsc::launch_order(L, reinterpret_cast<hipStream_t>(stream)));
@@ -372,6 +405,7 @@ tfsc_status tfsc_follow_up_step(const tfsc_grid *grid, tfsc_bank *bank, const tf
     L.dT = (double)grid->tranche_len * grid->dt;
     L.n = bank->n;
     L.mc = const_cast<double *>(bank->mc);
+    L.ln_mc = const_cast<double *>(bank->ln_mc);
     L.f0 = const_cast<double *>(bank->f0);
     L.ct = const_cast<double *>(bank->cos_theta);
     L.phi = const_cast<double *>(bank->phi);
@@ -461,9 +495,116 @@ tfsc_status tfsc_track(const tfsc_grid *grid, const tfsc_bank *bank, double *out
     if ((s = check_grid(grid)) != TFSC_OK) return s;
     if ((s = check_bank(bank)) != TFSC_OK) return s;
     if (bank->n > 0 && !out) return TFSC_ERR_ARG;
-    return hip_status(tfsc::launch_track(bank->n, grid->tranche_len, grid->n_tranches, grid->dt, bank->mc, bank->eta,
-                                         bank->f0, bank->cos_theta, bank->cos_iota, out,
+    return hip_status(tfsc::launch_track(bank->n, grid->tranche_len, grid->n_tranches, grid->dt, bank->mc,
+                                         bank->ln_mc, bank->eta, bank->f0, bank->cos_theta, bank->cos_iota, out,
                                          reinterpret_cast<hipStream_t>(stream)));
+}
+
+tfsc_status tfsc_orbit_positions(const tfsc_grid *grid, double *out, void *stream) {
+    tfsc_status s;
+    if ((s = check_grid(grid)) != TFSC_OK) return s;
+    if (!out) return TFSC_ERR_ARG;
+    return hip_status(tfsc::launch_orbit_positions(grid->n_tranches, (double)grid->tranche_len * grid->dt, out,
+                                                   reinterpret_cast<hipStream_t>(stream)));
+}
+
+tfsc_status tfsc_bank_statistic_harmonics(const tfsc_grid *grid, const tfsc_pixels *pix, const tfsc_bank *bank,
+                                          const tfsc_segments *seg, const tfsc_options *opt, int32_t n_harm,
+                                          const int32_t *harmonics, const double *amp, double *seg_terms,
+                                          double *stat, double *seg_zn, int32_t *flags, int32_t *n_active, void *ws,
+                                          size_t ws_bytes, void *stream) {
+    tfsc_status s;
+    if ((s = check_grid(grid)) != TFSC_OK) return s;
+    if ((s = check_bank(bank)) != TFSC_OK) return s;
+    if ((s = check_pixels(pix, bank->n > 0)) != TFSC_OK) return s;
+    if (!seg || (bank->n > 0 && (!seg->nseg || !seg->seg_offset))) return TFSC_ERR_ARG;
+    if (n_harm < 1 || n_harm > TFSC_MAX_HARMONICS || !harmonics) return TFSC_ERR_ARG;
+    for (int q = 0; q < n_harm; ++q) {
+        if (harmonics[q] < 1 || harmonics[q] > 8) return TFSC_ERR_ARG;
+        for (int r2 = 0; r2 < q; ++r2)
+            if (harmonics[r2] == harmonics[q]) return TFSC_ERR_ARG;
+    }
+    Resolved r;
+    if ((s = resolve_options(opt, pix, r)) != TFSC_OK) return s;
+    if (r.schedule != TFSC_SCHED_WAVE || r.fresnel != TFSC_FRESNEL_PAPER || pix->rho) return TFSC_ERR_UNSUPPORTED;
+    if (!((pix->dtype == TFSC_F64 && r.precision == TFSC_F64) || (pix->dtype == TFSC_F32 && r.precision == TFSC_F32)))
+        return TFSC_ERR_DTYPE;
+    if (bank->n > 0 && (!seg_terms || !stat || !flags || !amp)) return TFSC_ERR_ARG;
+    if (!ws || ws_bytes < ws_bytes_for(grid, bank->n, TFSC_WS_STATISTIC)) return TFSC_ERR_WORKSPACE;
+    if (pixel_store_bytes(grid, pix) > 0xffffffffull) return TFSC_ERR_UNSUPPORTED;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (bank->n == 0) return TFSC_OK;
+    hipError_t e = tfsc::launch_geometry(grid->n_tranches, (double)grid->tranche_len * grid->dt, pix->orbit,
+                                         reinterpret_cast<double *>(ws), st);
+    if (e != hipSuccess) return TFSC_ERR_HIP;
+    tfsc::StatLaunch L = stat_launch(grid, pix, bank, seg, r, ws);
+    e = tfsc::launch_weight_scale(grid->tranche_len / 2 + 1, pix->inv_asd, const_cast<double *>(L.u_scale), st);
+    if (e != hipSuccess) return TFSC_ERR_HIP;
+    L.seg_terms = seg_terms;
+    L.stat = stat;
+    L.seg_zn = seg_zn;
+    L.flags = flags;
+    L.n_active = n_active;
+    int h[TFSC_MAX_HARMONICS];
+    for (int q = 0; q < n_harm; ++q) h[q] = harmonics[q];
+    return hip_status(tfsc::launch_statistic_harmonics(L, n_harm, h, amp, st));
+}
+
+tfsc_status tfsc_tune_statistic(const tfsc_grid *grid, const tfsc_pixels *pix, const tfsc_bank *bank,
+                                const tfsc_segments *seg, const tfsc_options *opt, const char *tune_key,
+                                double *seg_terms, double *stat, int32_t *flags, void *ws, size_t ws_bytes,
+                                void *stream, int32_t *block_waves, int32_t *groups_per_cu) {
+    static const int kCand[][2] = {{4, 4}, {4, 3}, {4, 2}, {2, 8}, {2, 6}, {2, 4}, {1, 12}, {1, 8}};
+    if (!tune_key || !block_waves || !groups_per_cu) return TFSC_ERR_ARG;
+    tfsc_options o;
+    memset(&o, 0, sizeof(o));
+    if (opt) o = *opt;
+    o.schedule = TFSC_SCHED_WAVE;
+    o.tune_key = nullptr;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return TFSC_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return TFSC_ERR_HIP;
+    }
+    // warm-up launch, with the full argument checks
+    tfsc_status s = tfsc_bank_statistic(grid, pix, bank, seg, &o, seg_terms, stat, nullptr, flags, nullptr, ws,
+                                        ws_bytes, stream);
+    float best = 0.0f;
+    int bw = 0, gpc = 0;
+    for (size_t c = 0; s == TFSC_OK && c < sizeof(kCand) / sizeof(kCand[0]); ++c) {
+        o.block_waves = kCand[c][0];
+        o.groups_per_cu = kCand[c][1];
+        float t = 0.0f;
+        for (int rep = 0; rep < 2 && s == TFSC_OK; ++rep) {
+            if (hipEventRecord(e0, st) != hipSuccess) s = TFSC_ERR_HIP;
+            if (s == TFSC_OK)
+                s = tfsc_bank_statistic(grid, pix, bank, seg, &o, seg_terms, stat, nullptr, flags, nullptr, ws,
+                                        ws_bytes, stream);
+            if (s == TFSC_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+                s = TFSC_ERR_HIP;
+            float ms = 0.0f;
+            if (s == TFSC_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) s = TFSC_ERR_HIP;
+            if (s == TFSC_OK && (rep == 0 || ms < t)) t = ms;
+        }
+        if (s == TFSC_OK && (bw == 0 || t < best)) {
+            best = t;
+            bw = kCand[c][0];
+            gpc = kCand[c][1];
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s != TFSC_OK) return s;
+    {
+        TuneTable &t = tune_table();
+        std::lock_guard<std::mutex> lock(t.mu);
+        t.shape[tune_key] = std::make_pair(bw, gpc);
+    }
+    *block_waves = bw;
+    *groups_per_cu = gpc;
+    return TFSC_OK;
 }
 
 }  // extern "C"

@@ -387,6 +387,65 @@ __device__ __forceinline__ void fresnel_fg(R av, bool rational, R &f, R &g) {
     }
 }
 
+// Fresnel modes of the tranche spectrum: the paper's two-branch forms, or the Fresnel integrals themselves.
+enum : int { kFresnelPaper = 0, kFresnelAccurate = 1 };
+
+// The auxiliary functions f(z), g(z) of the Fresnel integrals, C(z) + i S(z) = (1+i)/2 - (g + i f) e^{i pi z^2/2}
+// for z >= 0, to FP64 rounding (for the accurate Fresnel mode):
+// * z <= 1.8: the power series of C and S (terms z x^k / k!, x = pi z^2 / 2, 40 terms), then
+//   f = (1/2 - S) cos x - (1/2 - C) sin x and g = (1/2 - C) cos x + (1/2 - S) sin x;
+// * 1.8 < z < 6: g + i f = (1+i)/2 e^{w^2} erfc(w) at w = (sqrt(pi)/2)(1 - i) z, with e^{w^2} erfc(w) from its
+//   continued fraction 1 / (sqrt(pi) (w + (1/2) / (w + 1 / (w + (3/2) / (w + ...))))), 64 levels;
+// * z >= 6: the asymptotic series f ~ (1/(pi z)) sum (-1)^m (4m-1)!! / (pi z^2)^(2m),
+//   g ~ (1/(pi^2 z^3)) sum (-1)^m (4m+1)!! / (pi z^2)^(2m), nine terms.
+__device__ inline void fresnel_fg_accurate(double z, double &f, double &g) {
+    if (z <= 1.8) {
+        const double x = 0.5 * kPi * z * z;
+        double t = z, C = 0.0, S = 0.0;
+#pragma unroll 4
+        for (int k = 0; k < 40; ++k) {
+            const double term = t / (double)(2 * k + 1);
+            const double sg = ((k >> 1) & 1) ? -1.0 : 1.0;
+            if (k & 1)
+                S += sg * term;
+            else
+                C += sg * term;
+            t *= x / (double)(k + 1);
+        }
+        double sx, cx_;
+        sincos(x, &sx, &cx_);
+        f = (0.5 - S) * cx_ - (0.5 - C) * sx;
+        g = (0.5 - C) * cx_ + (0.5 - S) * sx;
+    } else if (z < 6.0) {
+        const double a = 0.8862269254527580 * z;  // sqrt(pi)/2 z: w = a - i a
+        double dr = a, di = -a;
+        for (int n = 64; n >= 1; --n) {
+            const double q = (0.5 * n) / (dr * dr + di * di);
+            const double nr = a + q * dr, ni = -a - q * di;  // w + (n/2) / d
+            dr = nr;
+            di = ni;
+        }
+        // e = 1 / (sqrt(pi) d); (g + i f) = (1 + i)/2 e
+        const double den = 1.7724538509055160 * (dr * dr + di * di);
+        const double er = dr / den, ei = -di / den;
+        g = 0.5 * (er - ei);
+        f = 0.5 * (er + ei);
+    } else {
+        const double pz2 = kPi * z * z;
+        const double y = 1.0 / (pz2 * pz2);
+        double cf = 1.0, cg = 1.0, sf = 1.0, sg = 1.0, ym = 1.0;
+        for (int m = 1; m <= 8; ++m) {
+            cf *= (double)((4 * m - 3) * (4 * m - 1));
+            cg *= (double)((4 * m - 1) * (4 * m + 1));
+            ym *= -y;
+            sf += cf * ym;
+            sg += cg * ym;
+        }
+        f = sf / (kPi * z);
+        g = sg / (kPi * pz2 * z);
+    }
+}
+
 template <class R>
 __device__ __forceinline__ R sgn(R v) {
     return v > (R)0 ? (R)1 : (v < (R)0 ? (R)-1 : (R)0);
@@ -413,16 +472,27 @@ __device__ __forceinline__ cx<R> bin_fast(const TrancheSpec<R> &ts, R xj) {
     return {-ts.Q * im, ts.Q * re};
 }
 
-// General form, valid for every bin j (both Fresnel branches, stationary-phase term).
-template <class R>
+// General form, valid for every bin j (both Fresnel branches, stationary-phase term).  FR = kFresnelAccurate
+// takes the Fresnel integrals' own f, g (FP64) in place of the paper's forms.
+template <class R, int FR = kFresnelPaper>
 __device__ __forceinline__ cx<R> bin_full(const TrancheSpec<R> &ts, R xj, int j) {
 #pragma clang fp contract(fast)
     R xj1 = xj + ts.beta;
     R v0 = ts.s * xj, v1 = ts.s * xj1;
     R sg0 = sgn(v0), sg1 = sgn(v1);
     R f0, g0, f1, g1;
-    fresnel_fg(fabs(v0), j >= ts.j0lo && j <= ts.j0hi, f0, g0);
-    fresnel_fg(fabs(v1), j >= ts.j1lo && j <= ts.j1hi, f1, g1);
+    if constexpr (FR == kFresnelAccurate) {
+        double a, b;
+        fresnel_fg_accurate((double)fabs(v0), a, b);
+        f0 = (R)a;
+        g0 = (R)b;
+        fresnel_fg_accurate((double)fabs(v1), a, b);
+        f1 = (R)a;
+        g1 = (R)b;
+    } else {
+        fresnel_fg(fabs(v0), j >= ts.j0lo && j <= ts.j0hi, f0, g0);
+        fresnel_fg(fabs(v1), j >= ts.j1lo && j <= ts.j1hi, f1, g1);
+    }
     cx<R> t0 = cmul(cx<R>{sg0 * g0, sg0 * f0}, ts.E0);
     cx<R> t1 = cmul(cx<R>{sg1 * g1, sg1 * f1}, ts.E1);
     cx<R> h = csub(t0, t1);
@@ -459,12 +529,12 @@ __device__ __forceinline__ cx<R> bin_fast_weighted(const TrancheSpec<R> &ts, R x
 }
 
 // h_j w for bin k_c + j: asymptotic form where both Fresnel arguments exceed 6 and no bin
-// frequency is crossed, the general form otherwise.
-template <class R>
+// frequency is crossed, the general form otherwise (always, in the accurate Fresnel mode).
+template <class R, int FR = kFresnelPaper>
 __device__ __forceinline__ cx<R> tranche_bin_weighted(const TrancheSpec<R> &ts, int j, R w) {
     R xj = ts.x - (R)j;
-    if (bin_is_fast(ts, j)) return bin_fast_weighted(ts, xj, w);
-    const cx<R> h = bin_full(ts, xj, j);
+    if (FR == kFresnelPaper && bin_is_fast(ts, j)) return bin_fast_weighted(ts, xj, w);
+    const cx<R> h = bin_full<R, FR>(ts, xj, j);
     return {h.re * w, h.im * w};
 }
 
@@ -476,9 +546,12 @@ __device__ __forceinline__ cx<R> tranche_spectrum_bin(const TrancheSpec<R> &ts, 
 }
 
 // Tranche constants from the FP64 track.  Returns k_c.  Bin index, offset and
-// phases come from FP64; the rest is formed in R.
+// phases come from FP64; the rest is formed in R.  The amplitude is A = f_amp^(2/3); f_amp < 0 takes
+// f itself (a harmonic of a multi-harmonic template passes the dominant harmonic's frequency).
 template <class R>
-__device__ __forceinline__ int tranche_setup(TrancheSpec<R> &ts, double Phi, double f, double fdot, double dT) {
+__device__ __forceinline__ int tranche_setup(TrancheSpec<R> &ts, double Phi, double f, double fdot, double dT,
+                                             double f_amp = -1.0) {
+    const double fa = f_amp < 0.0 ? f : f_amp;
     double fT = f * dT;
     double kc = ceil(fT);
     double x = fT - kc;
@@ -497,7 +570,7 @@ __device__ __forceinline__ int tranche_setup(TrancheSpec<R> &ts, double Phi, dou
     }
     if constexpr (sizeof(R) == 8) {
         ts.s = sqrt(2.0 / beta);
-        double A = pow(f, 2.0 / 3.0);
+        double A = pow(fa, 2.0 / 3.0);
         ts.P = A / sqrt(2.0 * fdot);
         ts.Q = A * dT / kTwoPi;
         ts.half_inv_beta = 0.5 / beta;
@@ -505,7 +578,7 @@ __device__ __forceinline__ int tranche_setup(TrancheSpec<R> &ts, double Phi, dou
         float b = (float)beta;
         float ib = rcp(b);
         ts.s = sqrtf(2.0f * ib);
-        float A = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf((float)f) * (2.0f / 3.0f));
+        float A = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf((float)fa) * (2.0f / 3.0f));
         ts.P = A * __builtin_amdgcn_rsqf((float)(2.0 * fdot));
         ts.Q = A * (float)(dT / kTwoPi);
         ts.half_inv_beta = 0.5f * ib;

@@ -6,12 +6,13 @@
 
 namespace tfsc {
 
-// state[i][16] = m[5], v[5], best Upsilon, best (mc, f0, cos theta, phi, psi)
+// state[i][16] = m[5], v[5], best Upsilon, best (mc, f0, cos theta, phi, psi); a bank given in ln Mc is
+// stepped in ln Mc directly (the best mc is kept as a chirp mass either way)
 __global__ void k_follow_step(FollowLaunch a) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     double *s = a.state + 16 * i;
-    double mc = a.mc[i], f0 = a.f0[i], ct = a.ct[i], ph = a.phi[i], ps = a.psi[i];
+    double mc = a.ln_mc ? exp(a.ln_mc[i]) : a.mc[i], f0 = a.f0[i], ct = a.ct[i], ph = a.phi[i], ps = a.psi[i];
     const double up = a.stat[i];
     if (a.step == 1) {
         for (int p = 0; p < 10; ++p) s[p] = 0.0;
@@ -50,7 +51,8 @@ __global__ void k_follow_step(FollowLaunch a) {
         const double mh = s[p] / c1, vh = s[5 + p] / c2;
         d[p] = vh > 0.0 ? a.lr_scale * res[p] * mh / sqrt(vh) : 0.0;  // ascent
     }
-    mc = mc * exp(d[0]);
+    const double lnmc = a.ln_mc ? a.ln_mc[i] + d[0] : 0.0;
+    mc = a.ln_mc ? exp(lnmc) : mc * exp(d[0]);
     f0 = f0 + d[1];
     if (!(f0 > 0.0)) f0 = a.f0[i];
     ct = ct + d[2];
@@ -67,7 +69,10 @@ __global__ void k_follow_step(FollowLaunch a) {
     ct = fmin(1.0, fmax(-1.0, ct));
     ph = ph - kTwoPi * floor(ph / kTwoPi);
     ps = ps - kPi * floor(ps / kPi);
-    a.mc[i] = mc;
+    if (a.ln_mc)
+        a.ln_mc[i] = lnmc;
+    else
+        a.mc[i] = mc;
     a.f0[i] = f0;
     a.ct[i] = ct;
     a.phi[i] = ph;

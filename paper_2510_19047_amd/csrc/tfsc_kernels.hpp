@@ -21,6 +21,7 @@ inline float *geo32_of(const double *geo, int Nt) {
 struct LayoutLaunch {
     int64_t n;
     const double *mc, *eta, *f0, *ct, *ci;
+    const double *ln_mc;  // the bank given in ln Mc (mc unused), else NULL
     int nseg_fixed;
     int32_t *nseg;
     int64_t *seg_offset;
@@ -42,6 +43,7 @@ struct StatLaunch {
     const double *u_scale;  // device scalar written by launch_weight_scale
     int64_t n;
     const double *mc, *eta, *f0, *ct, *phi, *psi, *ci;
+    const double *ln_mc;  // the bank given in ln Mc (mc unused), else NULL
     const int32_t *nseg;
     const int64_t *seg_offset;
     const int32_t *order;
@@ -71,6 +73,7 @@ struct OrderLaunch {
     double dt;
     int64_t n;
     const double *mc, *eta, *f0, *ct, *ci;
+    const double *ln_mc;
     int32_t *order;
     uint32_t *ws;  // 2 (M/2 + 2) counters
 };
@@ -80,6 +83,7 @@ struct FollowLaunch {
     double dT;
     int64_t n;
     double *mc, *f0, *ct, *phi, *psi;  // updated in place
+    double *ln_mc;                     // updated in place instead of mc when the bank is given in ln Mc
     const double *eta, *ci;
     const int32_t *nseg;
     const double *stat, *g_params;
@@ -105,9 +109,14 @@ struct TransformLaunch {
 };
 
 hipError_t launch_layout(const LayoutLaunch &L, hipStream_t st);
-hipError_t launch_geometry(int Nt, double dT, double *geo, hipStream_t st);
+hipError_t launch_geometry(int Nt, double dT, const double *orbit, double *geo, hipStream_t st);
+hipError_t launch_orbit_positions(int Nt, double dT, double *out, hipStream_t st);
 hipError_t launch_weight_scale(int K, const double *inv_asd, double *scale_out, hipStream_t st);
 hipError_t launch_statistic(const StatLaunch &L, hipStream_t st);
+hipError_t launch_statistic_accurate(const StatLaunch &L, hipStream_t st);
+constexpr int kMaxHarmonics = 4;
+hipError_t launch_statistic_harmonics(const StatLaunch &L, int n_harm, const int *harm, const double *amp,
+                                      hipStream_t st);
 hipError_t launch_statistic_multi(const StatLaunch &L, hipStream_t st);
 hipError_t launch_vjp(const VjpLaunch &L, hipStream_t st);
 hipError_t launch_transform(const TransformLaunch &L, hipStream_t st);
@@ -115,7 +124,7 @@ hipError_t launch_follow_step(const FollowLaunch &L, hipStream_t st);
 hipError_t launch_order(const OrderLaunch &L, hipStream_t st);
 hipError_t launch_tile_max(const double *stat, const int32_t *tile, int64_t n, int32_t n_tiles, double *tile_max,
                            int64_t *tile_arg, hipStream_t st);
-hipError_t launch_track(int64_t n, int M, int Nt, double dt, const double *mc, const double *eta, const double *f0,
-                        const double *ct, const double *ci, double *out, hipStream_t st);
+hipError_t launch_track(int64_t n, int M, int Nt, double dt, const double *mc, const double *ln_mc, const double *eta,
+                        const double *f0, const double *ct, const double *ci, double *out, hipStream_t st);
 
 }  // namespace tfsc

@@ -31,8 +31,8 @@ def test_every_declared_function_is_exported(L):
 
 
 def test_version_and_status_strings(L):
-    assert L.tfsc_abi_version() == 2
-    for s in range(7):
+    assert L.tfsc_abi_version() == 3
+    for s in range(8):
         assert len(L.tfsc_status_string(s)) > 0
 
 
@@ -138,3 +138,59 @@ def test_transform_tf_binding_checks_the_psd_shape():
         tfsc.transform_tf(grid, x, torch.ones((100, 257), dtype=torch.float64), keep)  # transposed
     with pytest.raises(tfsc.TfscError):
         tfsc.transform_tf(grid, x, torch.ones((257, 100), dtype=torch.float32), keep)  # not float64
+
+
+def test_abi3_argument_errors(L):
+    """Host-side checks of the version-3 additions: the bank's ln_mc, the Fresnel mode, the multi-harmonic call,
+    the orbit positions and the tuner (no device call is made)."""
+    from paper_2510_19047_amd import _lib
+    g = _grid()
+    one = (ctypes.c_double * 4)()
+    p = ctypes.cast(one, ctypes.c_void_p)
+    pix = _lib.Pixels(1, 0, p, None, p, p, None, None)
+    seg = _lib.Segments(0, p, p)
+    ws = 1 << 30
+    # exactly one of mc and ln_mc
+    both = _lib.Bank(1, p, p, p, p, p, p, p, p)
+    neither = _lib.Bank(1, None, p, p, p, p, p, p, None)
+    for bank in (both, neither):
+        assert L.tfsc_bank_statistic(ctypes.byref(g), ctypes.byref(pix), ctypes.byref(bank), ctypes.byref(seg),
+                                     None, p, p, None, p, None, p, ws, None) == 1
+        assert L.tfsc_segment_layout(ctypes.byref(g), ctypes.byref(bank), ctypes.byref(seg), p, ws, None) == 1
+    bank = _lib.Bank(1, None, p, p, p, p, p, p, p)  # ln_mc only: valid
+    # Fresnel mode out of range; the accurate mode with F32 pixels and F64 arithmetic, or with 16-bit pixels
+    assert L.tfsc_bank_statistic(ctypes.byref(g), ctypes.byref(pix), ctypes.byref(bank), ctypes.byref(seg),
+                                 ctypes.byref(_lib.Options(1, 1, 0, 0, None, 2, None)), p, p, None, p, None, p, ws,
+                                 None) == 1
+    assert L.tfsc_bank_statistic(ctypes.byref(g), ctypes.byref(pix), ctypes.byref(bank), ctypes.byref(seg),
+                                 ctypes.byref(_lib.Options(0, 0, 0, 0, None, 1, None)), p, p, None, p, None, p, ws,
+                                 None) == 5
+    pix16 = _lib.Pixels(3, 0, p, p, p, p, None, None)
+    assert L.tfsc_bank_statistic(ctypes.byref(g), ctypes.byref(pix16), ctypes.byref(bank), ctypes.byref(seg),
+                                 ctypes.byref(_lib.Options(1, 1, 0, 0, None, 1, None)), p, p, None, p, None, p, ws,
+                                 None) == 5
+    # the VJP takes the paper's Fresnel forms only
+    assert L.tfsc_statistic_vjp(ctypes.byref(g), ctypes.byref(pix), ctypes.byref(bank), ctypes.byref(seg),
+                                ctypes.byref(_lib.Options(1, 1, 0, 0, None, 1, None)), p, p, None, p, p, ws,
+                                None) == 5
+    # harmonics: count, range, duplicates, schedule, per-pixel PSD
+    opt = _lib.Options(1, 1, 0, 0, None, 0, None)
+
+    def harm(hs, o=opt, px=pix):
+        arr = (ctypes.c_int32 * max(len(hs), 1))(*hs)
+        return L.tfsc_bank_statistic_harmonics(ctypes.byref(g), ctypes.byref(px), ctypes.byref(bank),
+                                               ctypes.byref(seg), ctypes.byref(o), len(hs), arr, p, p, p, None, p,
+                                               None, p, ws, None)
+
+    assert harm([]) == 1
+    assert harm([1, 2, 3, 4, 5]) == 1
+    assert harm([2, 2]) == 1
+    assert harm([9]) == 1 and harm([0, 2]) == 1
+    assert harm([1, 2], o=_lib.Options(1, 0, 0, 0, None, 0, None)) == 5
+    assert harm([1, 2], px=_lib.Pixels(1, 0, p, None, p, p, p, None)) == 5
+    assert harm([1, 2], o=_lib.Options(0, 1, 0, 0, None, 0, None)) == 3
+    # orbit positions and tuner arguments
+    assert L.tfsc_orbit_positions(ctypes.byref(g), None, None) == 1
+    bw, gpc = ctypes.c_int32(), ctypes.c_int32()
+    assert L.tfsc_tune_statistic(ctypes.byref(g), ctypes.byref(pix), ctypes.byref(bank), ctypes.byref(seg), None,
+                                 None, p, p, p, p, ws, None, ctypes.byref(bw), ctypes.byref(gpc)) == 1

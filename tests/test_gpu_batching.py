@@ -82,14 +82,20 @@ def test_autotune_picks_a_candidate_and_caches(tmp_path):
     store = tfsc.transform(gridspec(g), dev(d["x"].astype(np.float32)), dev(d["psd"]), dev(d["mu"]),
                            dev(d["keep"]), dtype="f32")
     path = str(tmp_path / "shapes.json")
-    shape = batching.autotune(gridspec(g), store, bt, seg, cache=path,
-                              candidates=((4, 4), (2, 4), (1, 8)))
-    assert shape in ((4, 4), (2, 4), (1, 8))
+    shape = batching.autotune(gridspec(g), store, bt, seg, cache=path)
+    assert shape in ((4, 4), (4, 3), (4, 2), (2, 8), (2, 6), (2, 4), (1, 12), (1, 8))
     with open(path) as fh:
         table = json.load(fh)
     assert len(table) == 1 and tuple(next(iter(table.values()))["shape"]) == shape
     # cached: no re-timing, same answer
-    assert batching.autotune(gridspec(g), store, bt, seg, cache=path, candidates=((4, 4),)) == shape
+    assert batching.autotune(gridspec(g), store, bt, seg, cache=path) == shape
+    # the library keeps the tuned shape under its key: a launch with that tune key uses it, and gives the same
+    # results as the explicit shape
+    key = next(iter(table))
+    a = tfsc.bank_statistic(gridspec(g), store, bt, seg, precision="f32", schedule="wave", tune_key=key)
+    b = tfsc.bank_statistic(gridspec(g), store, bt, seg, precision="f32", schedule="wave", block_waves=shape[0],
+                            groups_per_cu=shape[1])
+    assert torch.equal(a.stat, b.stat)
 
 
 def test_multi_graph_replay_matches_eager_and_single_launches():

@@ -162,6 +162,37 @@ def test_vjp_three_channels_against_oracle_autograd():
         assert cell.max() < 1e-7, i
 
 
+def test_vjp_three_channels_fp32_arithmetic():
+    """The FP32 VJP over A, E and T against the FP64 VJP on every template (per resolution cell within 1e-5
+    of Upsilon) and against the oracle's autograd on the sampled templates (per cell within 1e-4)."""
+    tfsc = lib()
+    d = _data()
+    g, b = d["grid"], d["bank"]
+    lay = otrk.Layout(b, g)
+    st = tfsc.transform(gridspec(g), dev(d["x"]), dev(d["psd"]), dev(d["mu"]), dev(d["keep"]), dtype="f64",
+                        layout="layer_ci")
+    bt = tfsc.BankTensors.from_host(b)
+    seg = tfsc.segment_layout(gridspec(g), bt)
+    fw = tfsc.bank_statistic(gridspec(g), st, bt, seg, precision="f64", want_zn=True)
+    ones = torch.ones(bt.n, dtype=torch.float64, device="cuda")
+    g64 = tfsc.statistic_vjp(gridspec(g), st, bt, seg, fw.seg_zn, g_stat=ones, precision="f64").cpu().numpy()
+    g32 = tfsc.statistic_vjp(gridspec(g), st, bt, seg, fw.seg_zn, g_stat=ones, precision="f32").cpu().numpy()
+    ok = np.nonzero((lay.flags & (otrk.FLAG_INVALID | otrk.FLAG_EMPTY)) == 0)[0]
+    T = g.n_tranches * g.tranche_dur
+    df0 = 0.1 / (T / lay.nseg.astype(np.float64))
+    s = np.stack([df0 / ((5.0 / 3.0) * np.abs(lay.fdot0) * T), df0] + [np.full(lay.n, 0.05)] * 3, axis=1)
+    ups = np.maximum(fw.stat.cpu().numpy(), 1.0)[:, None]
+    cell = np.abs(g32 - g64)[ok] * s[ok] / ups[ok]
+    idx = np.concatenate([ok[:3], ok[-2:]])
+    ref = np.zeros((len(idx), 5))
+    for r, i in enumerate(idx):
+        ref[r], _ = o2.gradient(d["pix"], d["u"], d["wm"], b, g, int(i), layout=lay)
+    cell_o = np.abs(g32[idx] - ref) * s[idx] / ups[idx]
+    note(f"C=3 fp32 vjp: per cell vs fp64 max {cell.max():.2e}, vs oracle autograd max {cell_o.max():.2e}")
+    assert cell.max() < 1e-5
+    assert cell_o.max() < 1e-4
+
+
 def test_three_channels_refused_by_multi():
     tfsc = lib()
     d = _data()

@@ -131,9 +131,13 @@ def test_vjp_two_channel_gapped_segment_weights():
     assert cell.max() < 1e-7
 
 
-@pytest.mark.parametrize("dtype,tol", [("f32", 1e-4), ("f16", 5e-3)])
-def test_vjp_reduced_precision_pixels(dtype, tol):
-    """FP32 or FP16 pixels with the FP32 forward's (z_n, N_n): error of the FP64 VJP against the oracle."""
+@pytest.mark.parametrize("dtype,arith,tol", [("f32", "f64", 1e-4), ("f16", "f64", 5e-3), ("f32", "f32", 1e-4),
+                                              ("f16", "f32", 5e-3)])
+def test_vjp_reduced_precision_pixels(dtype, arith, tol):
+    """FP32 or FP16 pixels with the FP32 forward's (z_n, N_n): error of the FP64 or FP32 VJP against the oracle.
+
+    The bar is in Upsilon units per resolution cell: following the gradient error across one cell moves
+    Upsilon by less than tol of itself (the forward's own FP32 bar is 1e-4 relative)."""
     tfsc = lib()
     d = small_data()
     g = d["grid"]
@@ -141,7 +145,7 @@ def test_vjp_reduced_precision_pixels(dtype, tol):
     lay = otrk.Layout(b, g)
     ok = np.nonzero((lay.flags & (otrk.FLAG_INVALID | otrk.FLAG_EMPTY)) == 0)[0]
     idx = ok[::9][:8]
-    note(f"vjp {dtype} pixels, templates {idx.tolist()}")
+    note(f"vjp {dtype} pixels, {arith} arithmetic, templates {idx.tolist()}")
     bt = tfsc.BankTensors.from_host(b)
     seg = tfsc.segment_layout(gridspec(g), bt)
     if dtype == "f32":
@@ -150,7 +154,7 @@ def test_vjp_reduced_precision_pixels(dtype, tol):
         store = tfsc.transform(gridspec(g), dev(d["x"].astype(np.float32)), dev(d["psd"]), dev(d["mu"]),
                                dev(d["keep"]), dtype=dtype)
     res = tfsc.bank_statistic(gridspec(g), store, bt, seg, precision="f32", schedule="wave", want_zn=True)
-    gp = tfsc.statistic_vjp(gridspec(g), store, bt, seg, res.seg_zn,
+    gp = tfsc.statistic_vjp(gridspec(g), store, bt, seg, res.seg_zn, precision=arith,
                             g_stat=torch.ones(bt.n, dtype=torch.float64, device="cuda")).cpu().numpy()
     ref = _oracle_grads(d, idx)
     err = _rel_err(gp[idx], ref)
@@ -160,6 +164,35 @@ def test_vjp_reduced_precision_pixels(dtype, tol):
     for r, i in enumerate(idx):
         note(f"  #{i}: rel {np.array2string(err[r], precision=2)} per cell {np.array2string(cell[r], precision=2)}")
     assert cell.max() < tol
+
+
+def test_vjp_fp32_arithmetic_against_fp64_on_every_template():
+    """The FP32 VJP against the FP64 VJP on the same FP64 store and (z_n, N_n), every template of the gapped,
+    modulated two-channel data with random per-segment cotangents: per resolution cell within 1e-5 of
+    Upsilon (ten times below the bar against the oracle), invalid and empty templates exactly 0."""
+    tfsc = lib()
+    d = small_data()
+    g = d["grid"]
+    b = d["bank"]
+    lay = otrk.Layout(b, g)
+    note(f"vjp fp32 arithmetic vs fp64, {lay.n} templates")
+    rng = np.random.default_rng(17)
+    g_seg = rng.normal(size=int(lay.seg_offset[-1]))
+    bt = tfsc.BankTensors.from_host(b)
+    seg = tfsc.segment_layout(gridspec(g), bt)
+    store = store_from_oracle(d, "f64")
+    res = tfsc.bank_statistic(gridspec(g), store, bt, seg, precision="f64", schedule="wave", want_zn=True)
+    kw = dict(g_stat=torch.full((bt.n,), 0.5, dtype=torch.float64, device="cuda"), g_seg=dev(g_seg))
+    g64 = tfsc.statistic_vjp(gridspec(g), store, bt, seg, res.seg_zn, precision="f64", **kw).cpu().numpy()
+    g32 = tfsc.statistic_vjp(gridspec(g), store, bt, seg, res.seg_zn, precision="f32", **kw).cpu().numpy()
+    bad = (lay.flags & (otrk.FLAG_INVALID | otrk.FLAG_EMPTY)) != 0
+    assert np.all(g32[bad] == 0.0)
+    ok = ~bad
+    cell = _cell_err(g32[ok], g64[ok], _resolution(d, lay)[ok], res.stat.cpu().numpy()[ok])
+    err = _rel_err(g32[ok], g64[ok])
+    note(f"  per cell: max {cell.max():.2e} median {np.median(cell):.2e}; relative: max {err.max():.2e} "
+         f"median {np.median(err):.2e}")
+    assert cell.max() < 1e-5
 
 
 def test_vjp_channel_interleaved_store_equals_layer_major():
@@ -201,8 +234,8 @@ def test_autograd_function_uses_the_vjp():
     params = [t.clone().requires_grad_(True) for t in (ln_mc, f0, ct, ph, ps)]
     ups = tfsc.TFSCStatistic.apply(*params, fixed)
     grads = torch.autograd.grad(ups.sum(), params)
-    # the same through the raw binding
-    bank = tfsc.BankTensors(torch.exp(ln_mc), fixed["eta"], f0, ct, ph, ps, fixed["cos_iota"])
+    # the same through the raw binding (the bank given in ln Mc, as the autograd function passes it)
+    bank = tfsc.BankTensors(None, fixed["eta"], f0, ct, ph, ps, fixed["cos_iota"], ln_mc=ln_mc)
     seg = tfsc.segment_layout(fixed["grid"], bank, nseg_fixed=8)
     res = tfsc.bank_statistic(fixed["grid"], store, bank, seg, precision="f64", want_zn=True)
     gp = tfsc.statistic_vjp(fixed["grid"], store, bank, seg, res.seg_zn,
