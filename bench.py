@@ -39,7 +39,7 @@ def parse():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=2)
     p.add_argument("--templates", type=int, default=1_000_000)
-    p.add_argument("--chosen-store", default="f32", choices=["f32", "f16", "bf16"])
+    p.add_argument("--chosen-store", default="f32", choices=["f32", "f16", "bf16", "i16"])
     p.add_argument("--chosen-layout", default="layer_ci", choices=["layer_ci", "layer"],
                    help="pixel layout of the chosen form (channels of a cell adjacent, or one block per channel)")
     p.add_argument("--plain-steps", type=int, default=2)
@@ -145,7 +145,7 @@ def main():
     res = tfsc.bank_statistic(grid, pix_chosen, bank, seg, precision="f32", schedule="wave", want_active=True)
     torch.cuda.synchronize()
     n_active = res.n_active.cpu().numpy().astype(np.int64)
-    b_pix = {"f32": 8, "f16": 4, "bf16": 4}[args.chosen_store]
+    b_pix = {"f32": 8, "f16": 4, "bf16": 4, "i16": 4}[args.chosen_store]
     pix_cols = int(n_active.sum())
     alg_bytes = pix_cols * NF * g.n_channels * b_pix + n * 56 + 8 * (seg.total + n)
     alg_bytes_f32 = pix_cols * NF * g.n_channels * 8 + n * 56 + 8 * (seg.total + n)
@@ -378,12 +378,12 @@ def accuracy(stat, flags, ref):
 
 
 def precision_run(args, tfsc, grid, x_d, psd_d, mu_d, keep_d, bank, seg, order, kw, res_c, sub_idx, ref, value_f32):
-    """FP16 and BF16 stores (per-layer FP32 scale, FP32 accumulation, FP64 track): templates/s of the same step
-    and the error of every template of the 10k subsample against the FP64 oracle."""
+    """FP16, BF16 and int16 fixed-point stores (per-layer FP32 scale, FP32 accumulation, FP64 track): templates/s
+    of the same step and the error of every template of the 10k subsample against the FP64 oracle."""
     import torch
     out = {}
     n = bank.n
-    for dt in ("f16", "bf16"):
+    for dt in ("f16", "bf16", "i16"):
         pix = tfsc.transform(grid, x_d, psd_d, mu_d, keep_d, dtype=dt, layout=args.chosen_layout)
 
         def step():
@@ -411,7 +411,9 @@ def precision_run(args, tfsc, grid, x_d, psd_d, mu_d, keep_d, bank, seg, order, 
         acc = accuracy(s[sub_idx], res_c.flags.cpu().numpy()[sub_idx], ref)
         out[dt] = {"templates_per_s": round(n / (ms / 1e3), 1), "ms_per_step": round(ms, 3),
                    "kernel_ms": round(ev[0].elapsed_time(ev[1]), 3), "over_f32": round(n / (ms / 1e3) / value_f32, 4),
-                   "store": f"{dt} {args.chosen_layout} + per-layer f32 scale", "arith": "f32 (track f64)",
+                   "store": f"{dt} {args.chosen_layout} + per-layer f32 scale" + (" (step = layer max / 32767)"
+                                                                                   if dt == "i16" else ""),
+                   "arith": "f32 (track f64)",
                    "vs_oracle": acc}
         log(f"precision {dt}: {ms:.2f} ms/step, {n / (ms / 1e3) / 1e6:.3f} M templates/s; vs oracle {acc}")
         del pix

@@ -38,7 +38,9 @@ typedef enum {
     TFSC_ERR_SCRATCH = 7       /* larger than the static device scratch     */
 } tfsc_status;
 
-typedef enum { TFSC_F64 = 0, TFSC_F32 = 1, TFSC_BF16 = 2, TFSC_F16 = 3 } tfsc_dtype;
+/* TFSC_I16: complex 16-bit two's-complement fixed point, value =
+ * layer_scale * stored with |stored| <= 32767 (see tfsc_pixels). */
+typedef enum { TFSC_F64 = 0, TFSC_F32 = 1, TFSC_BF16 = 2, TFSC_F16 = 3, TFSC_I16 = 4 } tfsc_dtype;
 
 /* Pixel store layouts (complex values stored as interleaved (re, im)):
  *   LAYER_MAJOR    [C][K][Nt]  -- tranches contiguous within one frequency layer
@@ -65,8 +67,13 @@ typedef struct {
 } tfsc_grid;
 
 /* Whitened TF pixels D[c][k][m] plus the template weights.  pix holds
- * complex values of `dtype` in `layout`; for BF16/F16 the true value is
- * layer_scale[c*K + k] * stored (layer_scale is [C][K] FP32, NULL otherwise).
+ * complex values of `dtype` in `layout`; for the 16-bit types (BF16, F16,
+ * I16) the true value is layer_scale[c*K + k] * stored (layer_scale is
+ * [C][K] FP32, NULL otherwise).  The 16-bit stores are the paper's reduced
+ * precision form (Sec. "Hardware acceleration and computational cost":
+ * 16-bit storage with a per-layer scale); I16 spends all 16 bits on one
+ * fixed-point grid per layer (step = layer max / 32767), about seven times
+ * finer than F16's 11-bit significand for unit-variance whitened pixels.
  * inv_asd[K] = u_k = 1/sqrt(S0(f_k)) and tranche_w[Nt] = w_m = 1/sqrt(mu_m)
  * (0 = tranche excluded, e.g. it overlaps a data gap).  The template pixel of
  * channel c is T_c(t_m, f_m) h_m(f_k) u_k w_m (paper Eqs. (tdi2),
@@ -190,7 +197,10 @@ const char *tfsc_status_string(int status);
 
 /* Bytes of device workspace call `which` (TFSC_WS_*) needs for this grid,
  * bank size and options (0 if none).  Workspace contents need not be
- * initialised; calls sharing one workspace must not overlap in time.      */
+ * initialised; calls sharing one workspace must not overlap in time.  The
+ * statistic and VJP figures include 8 bytes per template for a bank given
+ * in ln Mc (the calls form exp(ln Mc) there once); an mc bank needs only
+ * the geometry tables and 256 bytes, and the calls check that need.       */
 size_t tfsc_workspace_bytes(const tfsc_grid *grid, int64_t n_templates, const tfsc_options *opt, int which);
 
 /* Data -> TF pixels (paper Sec. "Implementation details": each tranche is
@@ -204,12 +214,14 @@ size_t tfsc_workspace_bytes(const tfsc_grid *grid, int64_t n_templates, const tf
  * Writes out->pix (D = X sqrt(2 dt / (M W2 mu_m S0(f_k))), X the windowed
  * DFT with the tranche start as time origin, W2 = mean(w^2); excluded
  * tranches are 0), out->inv_asd, out->tranche_w, and out->layer_scale for
- * 16-bit stores (per layer max |component|, FP32).  A pixel whose PSD
+ * 16-bit stores (FP32: per layer max |component| for BF16 and F16, that
+ * max / 32767 for I16, whose stored value is the nearest integer to
+ * value / layer_scale).  A pixel whose PSD
  * mu_m S0(f_k) is not positive and finite (DC and Nyquist may be given as 0
  * or inf; they never enter the statistic) is written as 0, and so is its
  * weight (u_k = 0, or w_m = 0 when mu_m is not positive and finite), never
- * inf or NaN.  out->dtype may be F64 (x F64 only), F32, BF16 or F16; 16-bit
- * outputs need TFSC_WS_TRANSFORM workspace.                                */
+ * inf or NaN.  out->dtype may be F64 (x F64 only), F32, BF16, F16 or I16;
+ * 16-bit outputs need TFSC_WS_TRANSFORM workspace.                                */
 tfsc_status tfsc_transform(const tfsc_grid *grid, const void *x, int x_dtype, const double *psd0,
                            const double *tranche_psd_scale, const uint8_t *tranche_keep, tfsc_pixels *out,
                            void *ws, size_t ws_bytes, void *stream);
@@ -294,7 +306,8 @@ tfsc_status tfsc_bank_statistic_multi(const tfsc_grid *grid, const tfsc_pixels *
  * the process ends (its address is looked up once per device, on the first
  * call with that device current); the call allocates nothing, neither do
  * the kernels it launches.  Grids of more than TFSC_NOALLOC_MAX_TRANCHES
- * tranches return TFSC_ERR_SCRATCH.  All calls on one device share that
+ * tranches return TFSC_ERR_SCRATCH, and so does a bank given in ln Mc whose
+ * 8 bytes per template do not fit beside the geometry tables.  All calls on one device share that
  * device's scratch (it keeps the last call's contents; the work counter is
  * cleared by a kernel at the start of every call): calls that overlap in
  * time on one device, on different streams or from different threads,

@@ -20,9 +20,10 @@ __all__ = ["GridSpec", "PixelStore", "BankTensors", "SegmentLayout", "StatResult
            "statistic_vjp", "track", "tile_max", "orbit_positions", "tune_statistic", "TFSCStatistic", "lib",
            "TfscError"]
 
-_DTYPE = {"f64": _lib.F64, "f32": _lib.F32, "bf16": _lib.BF16, "f16": _lib.F16}
-_TORCH_STORE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16}
-_STORE16 = ("bf16", "f16")
+_DTYPE = {"f64": _lib.F64, "f32": _lib.F32, "bf16": _lib.BF16, "f16": _lib.F16, "i16": _lib.I16}
+_TORCH_STORE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16,
+                "i16": torch.int16}
+_STORE16 = ("bf16", "f16", "i16")
 _LAYOUT = {"layer": _lib.LAYER_MAJOR, "tranche": _lib.TRANCHE_MAJOR, "layer_ci": _lib.LAYER_MAJOR_CI}
 _SCHED = {"thread": _lib.SCHED_THREAD, "wave": _lib.SCHED_WAVE}
 _PREC = {"f64": _lib.F64, "f32": _lib.F32}
@@ -76,7 +77,7 @@ class PixelStore:
     tranche_w: torch.Tensor           # [Nt] f64
     dtype: str = "f32"
     layout: str = "layer"
-    layer_scale: torch.Tensor | None = None  # [C][K] f32 for 16-bit stores (bf16, f16)
+    layer_scale: torch.Tensor | None = None  # [C][K] f32 for 16-bit stores (bf16, f16, i16)
     rho: torch.Tensor | None = None   # [K][Nt] f32 per-pixel weight factor of a general per-tranche PSD
     orbit: torch.Tensor | None = None  # [3][3][Nt] f64 spacecraft positions (light-seconds), None = analytic orbit
 

@@ -15,7 +15,7 @@ ABI_VERSION = 3
 MAX_HARMONICS = 4
 FRESNEL_PAPER, FRESNEL_ACCURATE = 0, 1
 NOALLOC_MAX_TRANCHES = 16384
-F64, F32, BF16, F16 = 0, 1, 2, 3
+F64, F32, BF16, F16, I16 = 0, 1, 2, 3, 4
 LAYER_MAJOR, TRANCHE_MAJOR, LAYER_MAJOR_CI = 0, 1, 2
 SCHED_THREAD, SCHED_WAVE = 0, 1
 WS_LAYOUT, WS_STATISTIC, WS_VJP, WS_TRANSFORM, WS_ORDER = 0, 1, 2, 3, 4

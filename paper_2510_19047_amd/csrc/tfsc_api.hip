@@ -56,14 +56,17 @@ tfsc_status check_bank(const tfsc_bank *b) {
     return TFSC_OK;
 }
 
+// BF16, F16 and I16 stores: 16-bit values with a per-layer FP32 scale
+inline bool is_16bit(int d) { return d == TFSC_BF16 || d == TFSC_F16 || d == TFSC_I16; }
+
 tfsc_status check_pixels(const tfsc_pixels *p, bool need_data) {
     if (!p) return TFSC_ERR_ARG;
-    if (p->dtype < TFSC_F64 || p->dtype > TFSC_F16) return TFSC_ERR_DTYPE;
+    if (p->dtype < TFSC_F64 || p->dtype > TFSC_I16) return TFSC_ERR_DTYPE;
     if (p->layout != TFSC_LAYER_MAJOR && p->layout != TFSC_TRANCHE_MAJOR && p->layout != TFSC_LAYER_MAJOR_CI)
         return TFSC_ERR_ARG;
     if (need_data && !p->pix) return TFSC_ERR_ARG;
     if (!p->inv_asd || !p->tranche_w) return TFSC_ERR_ARG;
-    if ((p->dtype == TFSC_BF16 || p->dtype == TFSC_F16) && !p->layer_scale) return TFSC_ERR_ARG;
+    if (is_16bit(p->dtype) && !p->layer_scale) return TFSC_ERR_ARG;
     return TFSC_OK;
 }
 
@@ -104,7 +107,7 @@ tfsc_status resolve_options(const tfsc_options *o, const tfsc_pixels *p, Resolve
     // the WAVE and VJP kernels are compiled for at most 256 threads (4 waves) per block
     if (r.block_waves > 4 || r.groups_per_cu > 64) return TFSC_ERR_ARG;
     if (p) {
-        if (r.precision == TFSC_F64 && (p->dtype == TFSC_BF16 || p->dtype == TFSC_F16)) return TFSC_ERR_DTYPE;
+        if (r.precision == TFSC_F64 && is_16bit(p->dtype)) return TFSC_ERR_DTYPE;
         if (r.precision == TFSC_F32 && p->dtype == TFSC_F64) return TFSC_ERR_DTYPE;
         if (r.schedule == TFSC_SCHED_WAVE && p->layout == TFSC_TRANCHE_MAJOR) return TFSC_ERR_UNSUPPORTED;
     }
@@ -118,13 +121,20 @@ size_t pixel_store_bytes(const tfsc_grid *g, const tfsc_pixels *p) {
 
 size_t geo_bytes(int Nt) { return tfsc::geo64_bytes(Nt) + tfsc::geo32_bytes(Nt); }
 
+// Statistic and VJP workspace: the geometry tables, the tail (work counter, weight scale) and, for a
+// bank given in ln Mc, a table of the chirp masses exp(ln Mc) formed once per call, so the
+// kernels read Mc as they read every other parameter.
+size_t stat_ws_bytes(const tfsc_grid *g, int64_t n, bool log_mc) {
+    return geo_bytes(g->n_tranches) + kAlign + (log_mc ? align_up(sizeof(double) * (size_t)n) : 0);
+}
+
 size_t ws_bytes_for(const tfsc_grid *g, int64_t n, int which) {
     switch (which) {
         case TFSC_WS_LAYOUT:
             return align_up(sizeof(int64_t) * (size_t)((n + 255) / 256 + 1));
         case TFSC_WS_STATISTIC:
         case TFSC_WS_VJP:
-            return geo_bytes(g->n_tranches) + kAlign;
+            return stat_ws_bytes(g, n, true);
         case TFSC_WS_ORDER:
             return align_up(sizeof(uint32_t) * 2 * (size_t)(g->tranche_len / 2 + 2));
         case TFSC_WS_TRANSFORM: {
@@ -192,7 +202,20 @@ tfsc::StatLaunch stat_launch(const tfsc_grid *grid, const tfsc_pixels *pix, cons
     char *tail = reinterpret_cast<char *>(ws) + geo_bytes(grid->n_tranches);
     L.counter = reinterpret_cast<uint32_t *>(tail);
     L.u_scale = reinterpret_cast<const double *>(tail + tfsc::kTailScale);
+    if (bank->ln_mc) L.mc = reinterpret_cast<const double *>(tail + kAlign);  // filled by prepare_launch
     return L;
+}
+
+// Per-call tables the kernels read: the geometry of the orbit, the weight scale and, for a bank
+// given in ln Mc, the chirp masses.
+hipError_t prepare_launch(const tfsc_grid *grid, const tfsc_pixels *pix, const tfsc::StatLaunch &L, void *ws,
+                          hipStream_t st) {
+    hipError_t e = tfsc::launch_geometry(grid->n_tranches, (double)grid->tranche_len * grid->dt, pix->orbit,
+                                         reinterpret_cast<double *>(ws), st);
+    if (e != hipSuccess) return e;
+    e = tfsc::launch_weight_scale(grid->tranche_len / 2 + 1, pix->inv_asd, const_cast<double *>(L.u_scale), st);
+    if (e != hipSuccess || !L.ln_mc) return e;
+    return tfsc::launch_exp_mc(L.n, L.ln_mc, const_cast<double *>(L.mc), st);
 }
 
 }  // namespace
@@ -256,7 +279,7 @@ tfsc_status tfsc_bank_statistic(const tfsc_grid *grid, const tfsc_pixels *pix, c
     Resolved r;
     if ((s = resolve_options(opt, pix, r)) != TFSC_OK) return s;
     if (bank->n > 0 && (!seg_terms || !stat || !flags)) return TFSC_ERR_ARG;
-    if (!ws || ws_bytes < ws_bytes_for(grid, bank->n, TFSC_WS_STATISTIC)) return TFSC_ERR_WORKSPACE;
+    if (!ws || ws_bytes < stat_ws_bytes(grid, bank->n, bank->ln_mc != nullptr)) return TFSC_ERR_WORKSPACE;
     if (r.schedule == TFSC_SCHED_WAVE && pixel_store_bytes(grid, pix) > 0xffffffffull) return TFSC_ERR_UNSUPPORTED;
     if (pix->rho && r.schedule == TFSC_SCHED_WAVE && pix->dtype != TFSC_F64 && pix->dtype != TFSC_F32)
         return TFSC_ERR_UNSUPPORTED;
@@ -266,12 +289,8 @@ tfsc_status tfsc_bank_statistic(const tfsc_grid *grid, const tfsc_pixels *pix, c
         return TFSC_ERR_UNSUPPORTED;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (bank->n == 0) return TFSC_OK;
-    hipError_t e = tfsc::launch_geometry(grid->n_tranches, (double)grid->tranche_len * grid->dt, pix->orbit,
-                                         reinterpret_cast<double *>(ws), st);
-    if (e != hipSuccess) return TFSC_ERR_HIP;
     tfsc::StatLaunch L = stat_launch(grid, pix, bank, seg, r, ws);
-    e = tfsc::launch_weight_scale(grid->tranche_len / 2 + 1, pix->inv_asd, const_cast<double *>(L.u_scale), st);
-    if (e != hipSuccess) return TFSC_ERR_HIP;
+    if (prepare_launch(grid, pix, L, ws, st) != hipSuccess) return TFSC_ERR_HIP;
     L.seg_terms = seg_terms;
     L.stat = stat;
     L.seg_zn = seg_zn;
@@ -287,7 +306,7 @@ tfsc_status tfsc_bank_statistic_noalloc(const tfsc_grid *grid, const tfsc_pixels
                                         void *stream) {
     tfsc_status s;
     if ((s = check_grid(grid)) != TFSC_OK) return s;
-    const size_t need = ws_bytes_for(grid, bank ? bank->n : 0, TFSC_WS_STATISTIC);
+    const size_t need = stat_ws_bytes(grid, bank ? bank->n : 0, bank && bank->ln_mc);
     if (grid->n_tranches > TFSC_NOALLOC_MAX_TRANCHES || need > kScratchBytes) return TFSC_ERR_SCRATCH;
     void *ws = scratch_on_device();
     if (!ws) return TFSC_ERR_HIP;
@@ -318,15 +337,11 @@ tfsc_status tfsc_bank_statistic_multi(const tfsc_grid *grid, const tfsc_pixels *
     if (real_stride < 0 || (uint64_t)real_stride < one || real_stride % 16 != 0) return TFSC_ERR_SHAPE;
     if ((uint64_t)real_stride * (uint64_t)n_real > 0xffffffffull) return TFSC_ERR_UNSUPPORTED;
     if (bank->n > 0 && (!seg_terms || !stat || !flags)) return TFSC_ERR_ARG;
-    if (!ws || ws_bytes < ws_bytes_for(grid, bank->n, TFSC_WS_STATISTIC)) return TFSC_ERR_WORKSPACE;
+    if (!ws || ws_bytes < stat_ws_bytes(grid, bank->n, bank->ln_mc != nullptr)) return TFSC_ERR_WORKSPACE;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (bank->n == 0) return TFSC_OK;
-    hipError_t e = tfsc::launch_geometry(grid->n_tranches, (double)grid->tranche_len * grid->dt, pix->orbit,
-                                         reinterpret_cast<double *>(ws), st);
-    if (e != hipSuccess) return TFSC_ERR_HIP;
     tfsc::StatLaunch L = stat_launch(grid, pix, bank, seg, r, ws);
-    e = tfsc::launch_weight_scale(grid->tranche_len / 2 + 1, pix->inv_asd, const_cast<double *>(L.u_scale), st);
-    if (e != hipSuccess) return TFSC_ERR_HIP;
+    if (prepare_launch(grid, pix, L, ws, st) != hipSuccess) return TFSC_ERR_HIP;
     L.seg_terms = seg_terms;
     L.stat = stat;
     L.flags = flags;
@@ -352,16 +367,12 @@ tfsc_status tfsc_statistic_vjp(const tfsc_grid *grid, const tfsc_pixels *pix, co
     if ((s = resolve_options(opt, nullptr, r)) != TFSC_OK) return s;
     if (r.fresnel != TFSC_FRESNEL_PAPER) return TFSC_ERR_UNSUPPORTED;
     if (bank->n > 0 && (!seg_zn || !g_params || (!g_stat && !g_seg))) return TFSC_ERR_ARG;
-    if (!ws || ws_bytes < ws_bytes_for(grid, bank->n, TFSC_WS_VJP)) return TFSC_ERR_WORKSPACE;
+    if (!ws || ws_bytes < stat_ws_bytes(grid, bank->n, bank->ln_mc != nullptr)) return TFSC_ERR_WORKSPACE;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (bank->n == 0) return TFSC_OK;
-    hipError_t e = tfsc::launch_geometry(grid->n_tranches, (double)grid->tranche_len * grid->dt, pix->orbit,
-                                         reinterpret_cast<double *>(ws), st);
-    if (e != hipSuccess) return TFSC_ERR_HIP;
     tfsc::VjpLaunch V;
     V.s = stat_launch(grid, pix, bank, seg, r, ws);
-    e = tfsc::launch_weight_scale(grid->tranche_len / 2 + 1, pix->inv_asd, const_cast<double *>(V.s.u_scale), st);
-    if (e != hipSuccess) return TFSC_ERR_HIP;
+    if (prepare_launch(grid, pix, V.s, ws, st) != hipSuccess) return TFSC_ERR_HIP;
     V.seg_zn = seg_zn;
     V.g_stat = g_stat;
     V.g_seg = g_seg;
@@ -440,7 +451,7 @@ tfsc_status transform_common(const tfsc_grid *grid, const void *x, int x_dtype, 
     if (x_dtype != TFSC_F64 && x_dtype != TFSC_F32) return TFSC_ERR_DTYPE;
     if (out->dtype == TFSC_F64 && x_dtype != TFSC_F64) return TFSC_ERR_DTYPE;
     if (out->dtype == TFSC_F64 && grid->tranche_len > 2048) return TFSC_ERR_UNSUPPORTED;
-    const bool q16 = out->dtype == TFSC_BF16 || out->dtype == TFSC_F16;
+    const bool q16 = is_16bit(out->dtype);
     if (q16 && (!ws || ws_bytes < ws_bytes_for(grid, 0, TFSC_WS_TRANSFORM))) return TFSC_ERR_WORKSPACE;
     tfsc::TransformLaunch L;
     L.M = grid->tranche_len;
@@ -530,16 +541,12 @@ tfsc_status tfsc_bank_statistic_harmonics(const tfsc_grid *grid, const tfsc_pixe
     if (!((pix->dtype == TFSC_F64 && r.precision == TFSC_F64) || (pix->dtype == TFSC_F32 && r.precision == TFSC_F32)))
         return TFSC_ERR_DTYPE;
     if (bank->n > 0 && (!seg_terms || !stat || !flags || !amp)) return TFSC_ERR_ARG;
-    if (!ws || ws_bytes < ws_bytes_for(grid, bank->n, TFSC_WS_STATISTIC)) return TFSC_ERR_WORKSPACE;
+    if (!ws || ws_bytes < stat_ws_bytes(grid, bank->n, bank->ln_mc != nullptr)) return TFSC_ERR_WORKSPACE;
     if (pixel_store_bytes(grid, pix) > 0xffffffffull) return TFSC_ERR_UNSUPPORTED;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (bank->n == 0) return TFSC_OK;
-    hipError_t e = tfsc::launch_geometry(grid->n_tranches, (double)grid->tranche_len * grid->dt, pix->orbit,
-                                         reinterpret_cast<double *>(ws), st);
-    if (e != hipSuccess) return TFSC_ERR_HIP;
     tfsc::StatLaunch L = stat_launch(grid, pix, bank, seg, r, ws);
-    e = tfsc::launch_weight_scale(grid->tranche_len / 2 + 1, pix->inv_asd, const_cast<double *>(L.u_scale), st);
-    if (e != hipSuccess) return TFSC_ERR_HIP;
+    if (prepare_launch(grid, pix, L, ws, st) != hipSuccess) return TFSC_ERR_HIP;
     L.seg_terms = seg_terms;
     L.stat = stat;
     L.seg_zn = seg_zn;

@@ -620,6 +620,18 @@ struct PixTraits<__half> {
         return {f.x, f.y};
     }
 };
+// complex int16 fixed point: the low half of the 32-bit word is the real part
+__device__ __forceinline__ cx<float> i16x2_to_float(uint32_t w) {
+    return {(float)(int)(int16_t)(w & 0xffffu), (float)((int)w >> 16)};
+}
+template <>
+struct PixTraits<int16_t> {
+    using R = float;
+    static constexpr bool scaled = true;
+    __device__ static __forceinline__ cx<float> load(const void *p, size_t idx) {
+        return i16x2_to_float(reinterpret_cast<const uint32_t *>(p)[idx]);
+    }
+};
 template <>
 struct PixTraits<__hip_bfloat16> {
     using R = float;

@@ -108,7 +108,7 @@ __global__ __launch_bounds__(256, 2) void k_stat_wave_harm(StatArgs a, HarmArgs 
         SegAcc<double> acc{0, 0, 0, 0, 0, false};
         int flag = 0;
         const bool writer = lane == 0;
-        const double mci = bank_mc(a.mc, a.ln_mc, i);
+        const double mci = a.mc[i];
         if (!params_valid(mci, a.eta[i], a.f0[i], a.ct[i], a.ci[i])) {
             close_segments(acc, ns, off, a.seg_terms, a.seg_zn, writer);
             if (writer) {

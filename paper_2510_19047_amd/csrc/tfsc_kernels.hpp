@@ -43,7 +43,7 @@ struct StatLaunch {
     const double *u_scale;  // device scalar written by launch_weight_scale
     int64_t n;
     const double *mc, *eta, *f0, *ct, *phi, *psi, *ci;
-    const double *ln_mc;  // the bank given in ln Mc (mc unused), else NULL
+    const double *ln_mc;  // the bank given in ln Mc: the entry point fills mc (a workspace table) from it
     const int32_t *nseg;
     const int64_t *seg_offset;
     const int32_t *order;
@@ -111,6 +111,7 @@ struct TransformLaunch {
 hipError_t launch_layout(const LayoutLaunch &L, hipStream_t st);
 hipError_t launch_geometry(int Nt, double dT, const double *orbit, double *geo, hipStream_t st);
 hipError_t launch_orbit_positions(int Nt, double dT, double *out, hipStream_t st);
+hipError_t launch_exp_mc(int64_t n, const double *ln_mc, double *mc, hipStream_t st);
 hipError_t launch_weight_scale(int K, const double *inv_asd, double *scale_out, hipStream_t st);
 hipError_t launch_statistic(const StatLaunch &L, hipStream_t st);
 hipError_t launch_statistic_accurate(const StatLaunch &L, hipStream_t st);

@@ -415,7 +415,7 @@ __global__ __launch_bounds__(256, 4) void k_stat_wave_multi(StatArgs a) {
         const int64_t off = a.seg_offset[i];
         SegAccMulti acc{0, 0, 0, 0, 0, false};
         int flag = 0;
-        if (!params_valid(bank_mc(a.mc, a.ln_mc, i), a.eta[i], a.f0[i], a.ct[i], a.ci[i])) {
+        if (!params_valid(a.mc[i], a.eta[i], a.f0[i], a.ct[i], a.ci[i])) {
             close_segments_multi(acc, ns, off, seg_terms, a.seg_stride, owner, lane);
             if (owner) stat[(int64_t)lane * a.n + i] = 0.0;
             if (lane == 0 && a.rho0 == 0) {
@@ -425,7 +425,7 @@ __global__ __launch_bounds__(256, 4) void k_stat_wave_multi(StatArgs a) {
             continue;
         }
         Track T;
-        track_init(T, bank_mc(a.mc, a.ln_mc, i), a.eta[i], a.f0[i]);
+        track_init(T, a.mc[i], a.eta[i], a.f0[i]);
         wave_uniform(T);
         Sky<R> S;
         sky_init(S, a.ct[i], a.phi[i], a.psi[i], a.ci[i]);
@@ -667,8 +667,26 @@ static hipError_t dispatch_pix(const StatLaunch &L, const StatArgs &a, hipStream
                                        : launch_wave_t<C, R, __half>(a, L.layout, L.n_groups, L.block_waves, st);
             else
                 return hipErrorInvalidValue;
+        case 4:
+            if constexpr (sizeof(R) == 4)
+                return L.schedule == 0 ? launch_thread_t<C, R, int16_t>(a, L.layout, st)
+                                       : launch_wave_t<C, R, int16_t>(a, L.layout, L.n_groups, L.block_waves, st);
+            else
+                return hipErrorInvalidValue;
     }
     return hipErrorInvalidValue;
+}
+
+// Chirp masses of a bank given in ln Mc, formed once per call for the statistic and VJP kernels.
+__global__ void k_exp_mc(int64_t n, const double *__restrict__ ln_mc, double *__restrict__ mc) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) mc[i] = exp(ln_mc[i]);
+}
+
+hipError_t launch_exp_mc(int64_t n, const double *ln_mc, double *mc, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_exp_mc, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, ln_mc, mc);
+    return hipGetLastError();
 }
 
 hipError_t launch_weight_scale(int K, const double *inv_asd, double *scale_out, hipStream_t st) {

@@ -28,7 +28,6 @@ struct StatArgs {
     uint32_t rho_bytes;
     int64_t n;
     const double *mc, *eta, *f0, *ct, *phi, *psi, *ci;
-    const double *ln_mc;  // the bank given in ln Mc (then mc is unused), else NULL
     const int32_t *nseg;
     const int64_t *seg_offset;
     const int32_t *order;
@@ -43,7 +42,8 @@ struct StatArgs {
     int rho0;  // first realisation of this launch
 };
 
-// Chirp mass of template i: from the bank's mc, or exp(ln Mc) when the bank is given in ln Mc.
+// Chirp mass of template i: from the bank's mc, or exp(ln Mc) when the bank is given in ln Mc (the
+// small per-template kernels; the statistic and VJP kernels read a table the entry point fills).
 __device__ __forceinline__ double bank_mc(const double *mc, const double *ln_mc, int64_t i) {
     return ln_mc ? exp(ln_mc[i]) : mc[i];
 }
@@ -300,6 +300,8 @@ __device__ __forceinline__ cx<typename PixTraits<PixT>::R> buf_load(__amdgpu_buf
             __half2 h = __builtin_bit_cast(__half2, w);
             float2 f = __half22float2(h);
             return {f.x, f.y};
+        } else if constexpr (__is_same(PixT, int16_t)) {
+            return i16x2_to_float(w);
         } else {
             return {__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u)};
         }
@@ -330,6 +332,9 @@ __device__ __forceinline__ void bin_pixels(__amdgpu_buffer_rsrc_t r, uint32_t vo
                 const float2 f1 = __half22float2(__builtin_bit_cast(__half2, w1));
                 D[0] = {f0.x, f0.y};
                 D[1] = {f1.x, f1.y};
+            } else if constexpr (__is_same(PixT, int16_t)) {
+                D[0] = i16x2_to_float(w0);
+                D[1] = i16x2_to_float(w1);
             } else {
                 D[0] = {__uint_as_float(w0 << 16), __uint_as_float(w0 & 0xffff0000u)};
                 D[1] = {__uint_as_float(w1 << 16), __uint_as_float(w1 & 0xffff0000u)};
@@ -572,7 +577,7 @@ __device__ __forceinline__ void stat_thread_body(const StatArgs &a) {
     const int64_t off = a.seg_offset[i];
     SegAcc<double> acc{0, 0, 0, 0, 0, false};
     int flag = 0;
-    if (!params_valid(bank_mc(a.mc, a.ln_mc, i), a.eta[i], a.f0[i], a.ct[i], a.ci[i])) {
+    if (!params_valid(a.mc[i], a.eta[i], a.f0[i], a.ct[i], a.ci[i])) {
         flag = kFlagInvalid;
         close_segments(acc, ns, off, a.seg_terms, a.seg_zn, true);
         a.stat[i] = 0.0;
@@ -581,7 +586,7 @@ __device__ __forceinline__ void stat_thread_body(const StatArgs &a) {
         return;
     }
     Track T;
-    track_init(T, bank_mc(a.mc, a.ln_mc, i), a.eta[i], a.f0[i]);
+    track_init(T, a.mc[i], a.eta[i], a.f0[i]);
     Sky<R> S;
     sky_init(S, a.ct[i], a.phi[i], a.psi[i], a.ci[i]);
     const GeoView gv = geo_view(a.geo, a.geo32, a.Nt);
@@ -660,7 +665,7 @@ __device__ __forceinline__ void stat_wave_body(const StatArgs &a) {
         SegAcc<double> acc{0, 0, 0, 0, 0, false};
         int flag = 0;
         const bool writer = lane == 0;
-        if (!params_valid(bank_mc(a.mc, a.ln_mc, i), a.eta[i], a.f0[i], a.ct[i], a.ci[i])) {
+        if (!params_valid(a.mc[i], a.eta[i], a.f0[i], a.ct[i], a.ci[i])) {
             close_segments(acc, ns, off, a.seg_terms, a.seg_zn, writer);
             if (writer) {
                 a.stat[i] = 0.0;
@@ -670,7 +675,7 @@ __device__ __forceinline__ void stat_wave_body(const StatArgs &a) {
             continue;
         }
         Track T;
-        track_init(T, bank_mc(a.mc, a.ln_mc, i), a.eta[i], a.f0[i]);
+        track_init(T, a.mc[i], a.eta[i], a.f0[i]);
         wave_uniform(T);
         Sky<R> S;
         sky_init(S, a.ct[i], a.phi[i], a.psi[i], a.ci[i]);
@@ -789,7 +794,6 @@ inline StatArgs make_args(const StatLaunch &L) {
     a.phi = L.phi;
     a.psi = L.psi;
     a.ci = L.ci;
-    a.ln_mc = L.ln_mc;
     a.nseg = L.nseg;
     a.seg_offset = L.seg_offset;
     a.order = L.order;

@@ -137,6 +137,17 @@ template <>
 __device__ __forceinline__ __half to_q<__half>(float v) { return __float2half_rn(v); }
 template <>
 __device__ __forceinline__ __hip_bfloat16 to_q<__hip_bfloat16>(float v) { return __float2bfloat16(v); }
+template <>
+__device__ __forceinline__ int16_t to_q<int16_t>(float v) {
+    // v = value / layer_scale lies in [-32767, 32767] up to rounding of the scale; nearest integer
+    return (int16_t)fminf(fmaxf(rintf(v), -32767.0f), 32767.0f);
+}
+// Largest stored magnitude of each type: the floating types hold value / (layer max) in [-1, 1],
+// the fixed-point type value / (layer max / 32767) on the integer grid.
+template <class Q>
+constexpr float q_full = 1.0f;
+template <>
+constexpr float q_full<int16_t> = 32767.0f;
 
 template <class Q>
 __global__ void k_quantize(int C, int K, int Nt, int layout, const float *__restrict__ st,
@@ -144,8 +155,8 @@ __global__ void k_quantize(int C, int K, int Nt, int layout, const float *__rest
     const int layer = blockIdx.y;
     const int c = layer / K, k = layer % K;
     float m = __uint_as_float(mx[layer]);
-    float scale = m > 0.0f ? m : 1.0f;
-    float inv = 1.0f / scale;
+    float scale = m > 0.0f ? m / q_full<Q> : 1.0f;
+    float inv = m > 0.0f ? q_full<Q> / m : 1.0f;
     if (blockIdx.x == 0 && threadIdx.x == 0) layer_scale[layer] = scale;
     for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < Nt; t += gridDim.x * blockDim.x) {
         const float *src = st + ((size_t)layer * Nt + t) * 2;
@@ -229,7 +240,7 @@ hipError_t launch_transform(const TransformLaunch &L, hipStream_t st) {
     else
         hipLaunchKernelGGL(k_weights, dim3((nw + 255) / 256), dim3(256), 0, st, K, L.Nt, L.psd0, L.mu, L.keep,
                            L.inv_asd, L.tranche_w);
-    const bool q16 = L.out_dtype == 2 || L.out_dtype == 3;
+    const bool q16 = L.out_dtype == 2 || L.out_dtype == 3 || L.out_dtype == 4;
     TransformLaunch Lw = L;
     hipError_t e;
     // The FFT runs in FP64 whenever the tile fits in LDS (M <= 2048): whitening divides by
@@ -251,7 +262,11 @@ hipError_t launch_transform(const TransformLaunch &L, hipStream_t st) {
         hipLaunchKernelGGL(k_layer_absmax, dim3(L.C * K), dim3(256), 0, st, L.C, K, L.Nt,
                            reinterpret_cast<const float *>(L.ws), mx);
         dim3 g((unsigned)((L.Nt + 255) / 256 > 8 ? 8 : (L.Nt + 255) / 256), (unsigned)(L.C * K));
-        if (L.out_dtype == 3)
+        if (L.out_dtype == 4)
+            hipLaunchKernelGGL(k_quantize<int16_t>, g, dim3(256), 0, st, L.C, K, L.Nt, L.out_layout,
+                               reinterpret_cast<const float *>(L.ws), mx, L.layer_scale,
+                               reinterpret_cast<int16_t *>(L.pix));
+        else if (L.out_dtype == 3)
             hipLaunchKernelGGL(k_quantize<__half>, g, dim3(256), 0, st, L.C, K, L.Nt, L.out_layout,
                                reinterpret_cast<const float *>(L.ws), mx, L.layer_scale,
                                reinterpret_cast<__half *>(L.pix));

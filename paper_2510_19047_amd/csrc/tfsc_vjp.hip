@@ -22,7 +22,7 @@
 // rounding in the adjoint.
 #include "tfsc_device.hpp"
 #include "tfsc_kernels.hpp"
-#include "tfsc_stat_common.hpp"  // bank_mc, wave_uniform, dpp_sum_f64
+#include "tfsc_stat_common.hpp"  // wave_uniform, dpp_sum_f64
 
 // The tangent arithmetic below contracts multiply-adds into FMAs.  The FP64 track that fixes
 // the integer structure (track_step, from tfsc_device.hpp, included above) is not affected.
@@ -522,7 +522,6 @@ struct VjpArgs {
     const float *rho;  // [K][Nt] per-pixel weight factor (general per-tranche PSD), else NULL
     int64_t n;
     const double *mc, *eta, *f0, *ct, *phi, *psi, *ci;
-    const double *ln_mc;  // the bank given in ln Mc (mc unused), else NULL
     const int32_t *nseg;
     const int64_t *seg_offset;
     const double *seg_zn, *g_stat, *g_seg;
@@ -552,7 +551,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 2 : 1) void k_vjp_wave(VjpArg
         const int64_t i = (int64_t)__builtin_amdgcn_readfirstlane(mine);
         if (i >= a.n) break;
         double gr[5] = {0, 0, 0, 0, 0};
-        const double mci = bank_mc(a.mc, a.ln_mc, i);
+        const double mci = a.mc[i];
         const bool ok = params_valid(mci, a.eta[i], a.f0[i], a.ct[i], a.ci[i]);
         if (ok) {
             const int ns = a.nseg[i];
@@ -717,6 +716,7 @@ static hipError_t dispatch_vjp(const VjpArgs &a, int dtype, int n_groups, int bl
         case 1: return launch_vjp_t<C, float, R>(a, n_groups, block_waves, st);
         case 2: return launch_vjp_t<C, __hip_bfloat16, R>(a, n_groups, block_waves, st);
         case 3: return launch_vjp_t<C, __half, R>(a, n_groups, block_waves, st);
+        case 4: return launch_vjp_t<C, int16_t, R>(a, n_groups, block_waves, st);
     }
     return hipErrorInvalidValue;
 }
@@ -755,7 +755,6 @@ hipError_t launch_vjp(const VjpLaunch &V, hipStream_t st) {
     a.phi = L.phi;
     a.psi = L.psi;
     a.ci = L.ci;
-    a.ln_mc = L.ln_mc;
     a.nseg = L.nseg;
     a.seg_offset = L.seg_offset;
     a.seg_zn = V.seg_zn;

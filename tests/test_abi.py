@@ -67,6 +67,9 @@ def test_argument_errors_return_codes(L):
     pix = _lib.Pixels(7, 0, None, None, None, None)
     assert L.tfsc_bank_statistic(ctypes.byref(g), ctypes.byref(pix), ctypes.byref(_lib.Bank(0)), ctypes.byref(seg),
                                  None, None, None, None, None, None, None, 0, None) == 3
+    pix = _lib.Pixels(5, 0, None, None, None, None)  # one past the last element type (I16 = 4)
+    assert L.tfsc_bank_statistic(ctypes.byref(g), ctypes.byref(pix), ctypes.byref(_lib.Bank(0)), ctypes.byref(seg),
+                                 None, None, None, None, None, None, None, 0, None) == 3
     assert L.tfsc_track(ctypes.byref(g), ctypes.byref(bank), None, None) == 1
 
 
@@ -169,6 +172,15 @@ def test_abi3_argument_errors(L):
     assert L.tfsc_bank_statistic(ctypes.byref(g), ctypes.byref(pix16), ctypes.byref(bank), ctypes.byref(seg),
                                  ctypes.byref(_lib.Options(1, 1, 0, 0, None, 1, None)), p, p, None, p, None, p, ws,
                                  None) == 5
+    # the int16 fixed-point store: needs its layer scales, takes FP32 arithmetic only
+    pixi = _lib.Pixels(4, 0, p, None, p, p, None, None)
+    assert L.tfsc_bank_statistic(ctypes.byref(g), ctypes.byref(pixi), ctypes.byref(bank), ctypes.byref(seg),
+                                 ctypes.byref(_lib.Options(1, 1, 0, 0, None, 0, None)), p, p, None, p, None, p, ws,
+                                 None) == 1
+    pixi = _lib.Pixels(4, 0, p, p, p, p, None, None)
+    assert L.tfsc_bank_statistic(ctypes.byref(g), ctypes.byref(pixi), ctypes.byref(bank), ctypes.byref(seg),
+                                 ctypes.byref(_lib.Options(0, 1, 0, 0, None, 0, None)), p, p, None, p, None, p, ws,
+                                 None) == 3
     # the VJP takes the paper's Fresnel forms only
     assert L.tfsc_statistic_vjp(ctypes.byref(g), ctypes.byref(pix), ctypes.byref(bank), ctypes.byref(seg),
                                 ctypes.byref(_lib.Options(1, 1, 0, 0, None, 1, None)), p, p, None, p, p, ws,

@@ -1,10 +1,11 @@
-"""Precision form at the full size: FP32, FP16 and BF16 pixel stores against the FP64 oracle.
+"""Precision form at the full size: FP32, FP16, BF16 and int16 fixed-point pixel stores against the FP64 oracle.
 
 Workload: the full-size data (2-yr A+E, gaps, modulated PSD) with the 20 injections of the full-size
 configuration added in the pixel domain (the oracle's own template pixels, phase-shifted and scaled
 to their target SNR), and a 10,000-template subsample of the full-size bank (the first indices of a
-seeded permutation, always including the 20 exact-parameter templates).  The 16-bit stores hold
-the oracle's pixels divided by a per-layer FP32 scale (the layer's largest component magnitude).
+seeded permutation, always including the 20 exact-parameter templates).  The FP16 and BF16 stores hold
+the oracle's pixels divided by a per-layer FP32 scale (the layer's largest component magnitude); the
+int16 store holds the nearest integers to the pixels divided by that magnitude / 32767.
 """
 import functools
 
@@ -43,6 +44,12 @@ def _store(tfsc, d, dtype):
         return tfsc.PixelStore.from_complex(dev(d["pix"]), dev(d["u"]), dev(d["wm"]), dtype=dtype)
     pix = d["pix"]
     scale = np.maximum(np.abs(pix.real), np.abs(pix.imag)).max(axis=2).astype(np.float32)  # [C][K]
+    if dtype == "i16":
+        step = (scale.astype(np.float64) / 32767.0).astype(np.float32)
+        s = np.where(step > 0, step, 1.0).astype(np.float64)[:, :, None]
+        q = np.clip(np.rint(np.stack([pix.real / s, pix.imag / s], axis=-1)), -32767, 32767).astype(np.int16)
+        return tfsc.PixelStore(torch.from_numpy(np.ascontiguousarray(q)).cuda(), dev(d["u"]), dev(d["wm"]), dtype,
+                               "layer", dev(step))
     safe = np.where(scale > 0, scale, 1.0).astype(np.float64)
     q = np.stack([pix.real / safe[:, :, None], pix.imag / safe[:, :, None]], axis=-1)
     tdt = torch.float16 if dtype == "f16" else torch.bfloat16
@@ -50,7 +57,7 @@ def _store(tfsc, d, dtype):
     return tfsc.PixelStore(t, dev(d["u"]), dev(d["wm"]), dtype, "layer", dev(scale))
 
 
-@pytest.mark.parametrize("dtype,tol", [("f32", 1e-4), ("f16", 2e-3), ("bf16", 2e-2)])
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-4), ("f16", 2e-3), ("bf16", 2e-2), ("i16", 1e-4)])
 def test_precision_forms_against_oracle(dtype, tol):
     tfsc = lib()
     d = data()

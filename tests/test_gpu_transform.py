@@ -9,7 +9,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _complex(store):
-    p = store.pix.float() if store.pix.dtype in (torch.float16, torch.bfloat16) else store.pix
+    p = store.pix.float() if store.pix.dtype in (torch.float16, torch.bfloat16, torch.int16) else store.pix
     z = torch.view_as_complex(p.contiguous().to(torch.float64 if p.dtype == torch.float64 else torch.float32))
     if store.layout == "tranche":
         z = z.transpose(1, 2)
@@ -75,6 +75,29 @@ def test_16bit_store_with_layer_scale(dtype, bits, layout):
     mag = np.maximum(np.abs(r.real), np.abs(r.imag))
     ok = mag > 1e-3 * sc[:, :, None]
     assert np.max(e[ok] / mag[ok]) <= 2.0 ** (-bits) * 1.01
+
+
+@pytest.mark.parametrize("layout", ["layer", "layer_ci"])
+def test_int16_store_on_the_layer_grid(layout):
+    """I16 store: layer_scale = layer max / 32767 and every component is the nearest grid point (within half
+    a step, plus the FP32 rounding of value x 32767 / max)."""
+    tfsc = lib()
+    d = small_data()
+    g = d["grid"]
+    note(f"transform i16 {layout}")
+    x32 = d["x"].astype(np.float32)
+    ref32 = tfsc.transform(gridspec(g), dev(x32), dev(d["psd"]), dev(d["mu"]), dev(d["keep"]), dtype="f32")
+    st = tfsc.transform(gridspec(g), dev(x32), dev(d["psd"]), dev(d["mu"]), dev(d["keep"]), dtype="i16",
+                        layout=layout)
+    assert st.pix.dtype == torch.int16
+    z, r = _complex(st), _complex(ref32)
+    sc = st.layer_scale.cpu().numpy().astype(np.float64)
+    comp = np.maximum(np.abs(r.real).max(axis=2), np.abs(r.imag).max(axis=2))
+    assert np.allclose(sc[comp > 0], comp[comp > 0] / 32767.0, rtol=1e-6)
+    q = np.stack([z.real, z.imag]) / np.where(sc > 0, sc, 1.0)[None, :, :, None]
+    assert np.max(np.abs(q)) <= 32767.0 + 1e-6 and np.allclose(q, np.rint(q), atol=1e-3)
+    e = np.maximum(np.abs(z.real - r.real), np.abs(z.imag - r.imag))
+    assert np.all(e <= 0.51 * sc[:, :, None] + 1e-30)
 
 
 def test_end_to_end_tiny_gpu_transform_then_statistic():

@@ -132,7 +132,7 @@ def test_vjp_two_channel_gapped_segment_weights():
 
 
 @pytest.mark.parametrize("dtype,arith,tol", [("f32", "f64", 1e-4), ("f16", "f64", 5e-3), ("f32", "f32", 1e-4),
-                                              ("f16", "f32", 5e-3)])
+                                              ("f16", "f32", 5e-3), ("i16", "f32", 1e-4)])
 def test_vjp_reduced_precision_pixels(dtype, arith, tol):
     """FP32 or FP16 pixels with the FP32 forward's (z_n, N_n): error of the FP64 or FP32 VJP against the oracle.
 
