@@ -756,33 +756,37 @@ def alu_roofline(prof, k_s):
     """The binding roof of the chosen kernel: vector-ALU issue.
 
     achieved = VALU wave instructions per launch outside the transcendental pipe (counters of the same source
-    and workload) / the launch time measured here; peak = 1,024 SIMDs x clock / 4 cycles per wave64
-    instruction, with the shader clock measured in the counter run (GRBM_GUI_ACTIVE, summed over the eight
-    XCDs, per dispatch time; SQ_BUSY_CYCLES over the 32 shader engines gives the same clock).  Counting every
-    VALU instruction at 4 cycles exceeds the cycles the launch had (reported as valu_all_over_peak), so the
-    transcendental instructions (rcp, rsq, sqrt, sin, cos, exp, log) overlap the others and are left out of
-    the issue count.  The FP32/FP64 operation rate is reported beside it against the non-packed vector peak
-    (64 FMA lanes per CU and cycle for FP32 and FP64 alike: 78.6 TFLOP/s at 2.4 GHz)."""
-    rec = {"bound": "alu", "unit": "G VALU instr/s", "achieved": None, "peak": None, "frac": None}
+    and workload) / the launch time measured here; peak = the chip's issue rate at its rated 2.4 GHz clock,
+    1,024 SIMDs x 2.4e9 / 4 cycles per wave64 instruction = 614.4 G instructions/s.  Under sustained load the
+    shader clock runs below 2.4 GHz; the clock of the counter run (GRBM_GUI_ACTIVE, summed over the eight XCDs,
+    per dispatch time) and the fraction at that clock are reported beside it.  Counting every VALU instruction
+    at 4 cycles exceeds the cycles the launch had (valu_all_over_profile_clock_peak), so the transcendental
+    instructions (rcp, rsq, sqrt, sin, cos, exp, log) overlap the others and are left out of the issue count.
+    The FP32/FP64 operation rate is reported against the non-packed vector peak (64 FMA lanes per CU and cycle
+    for FP32 and FP64 alike: 78.6 TFLOP/s at 2.4 GHz)."""
+    peak = SIMDS * NOMINAL_CLOCK_HZ / CYCLES_PER_VALU
+    rec = {"bound": "alu", "unit": "G VALU instr/s", "achieved": None, "peak": round(peak / 1e9, 2), "frac": None}
     if prof is None or "valu_insts" not in prof:
         rec["note"] = "no counter profile of this kernel source and workload; run the rocprofv3 passes"
         return rec
     clock = prof.get("clock_hz", NOMINAL_CLOCK_HZ)
-    peak = SIMDS * clock / CYCLES_PER_VALU
+    peak_clk = SIMDS * clock / CYCLES_PER_VALU
     issue = prof.get("valu_nontrans_insts", prof["valu_insts"])
     ach = issue / k_s
-    rec.update({"achieved": round(ach / 1e9, 2), "peak": round(peak / 1e9, 2), "frac": round(ach / peak, 4),
-                "clock_ghz": round(clock / 1e9, 4),
-                "peak_nominal_2p4ghz": round(SIMDS * NOMINAL_CLOCK_HZ / CYCLES_PER_VALU / 1e9, 2),
+    rec.update({"achieved": round(ach / 1e9, 2), "frac": round(ach / peak, 4),
+                "peak_note": "1,024 SIMDs x 2.4 GHz rated clock / 4 cycles per wave64 instruction",
+                "profile_clock_ghz": round(clock / 1e9, 4), "peak_at_profile_clock": round(peak_clk / 1e9, 2),
+                "frac_at_profile_clock": round(ach / peak_clk, 4),
                 "valu_insts_per_launch": prof["valu_insts"], "valu_issue_insts_per_launch": issue,
-                "valu_all_over_peak": round(prof["valu_insts"] / k_s / peak, 4),
+                "valu_all_over_profile_clock_peak": round(prof["valu_insts"] / k_s / peak_clk, 4),
                 "issue_note": "issue count excludes the transcendental VALU instructions, which overlap the others"})
     if "flops" in prof:
         tf = prof["flops"] / k_s / 1e12
-        peak_tf = SIMDS * 16 * 2 * clock / 1e12
+        peak_tf = SIMDS * 16 * 2 * NOMINAL_CLOCK_HZ / 1e12
         rec["flops"] = {"per_launch": prof["flops"], "tflops": round(tf, 3), "peak_tflops": round(peak_tf, 2),
                         "frac": round(tf / peak_tf, 4),
-                        "note": "64 x (ADD + MUL + 2 FMA + TRANS) over the FP32 and FP64 VALU instructions"}
+                        "note": "64 x (ADD + MUL + 2 FMA + TRANS) over the FP32 and FP64 VALU instructions, "
+                                "against the non-packed vector peak at 2.4 GHz"}
     return rec
 
 
