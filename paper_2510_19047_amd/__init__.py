@@ -18,7 +18,7 @@ from ._lib import TfscError
 __all__ = ["GridSpec", "PixelStore", "BankTensors", "SegmentLayout", "StatResult", "transform", "transform_tf", "segment_layout",
            "bank_statistic", "bank_statistic_multi", "bank_statistic_harmonics", "realisation_stores", "MultiResult",
            "statistic_vjp", "track", "tile_max", "orbit_positions", "tune_statistic", "TFSCStatistic", "lib",
-           "TfscError"]
+           "TfscError", "interleaved_store", "interleave_store", "interleave_stores", "bank_statistic_interleaved"]
 
 _DTYPE = {"f64": _lib.F64, "f32": _lib.F32, "bf16": _lib.BF16, "f16": _lib.F16, "i16": _lib.I16}
 _TORCH_STORE = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float16,
@@ -410,6 +410,63 @@ def bank_statistic_multi(grid: GridSpec, stores: list, bank: BankTensors, seg: S
                                      ctypes.byref(sc),
                                      ctypes.byref(opt), out.seg_terms.shape[1], _ptr(out.seg_terms), _ptr(out.stat),
                                      _ptr(out.flags), _ptr(out.n_active), _ptr(ws), ws.numel(), _stream())
+    _lib.check(st, "tfsc_bank_statistic_multi")
+    return out
+
+
+def interleaved_store(grid: GridSpec, n_real: int, like: PixelStore) -> PixelStore:
+    """An (uninitialised) FP32 store [K][Nt][n_real][C] for n_real interleaved realisations, with the weights of
+    ``like``."""
+    K, Nt, C = grid.n_bins, grid.n_tranches, grid.n_channels
+    return PixelStore(torch.empty((K, Nt, n_real * C, 2), dtype=torch.float32, device=like.pix.device),
+                      like.inv_asd, like.tranche_w, "f32", "layer_ci", None, None, like.orbit)
+
+
+def interleave_store(grid: GridSpec, src: PixelStore, n_real: int, r: int, out: PixelStore) -> PixelStore:
+    """tfsc_interleave_store: realisation r (an FP32 channel-interleaved store) into slot r of ``out``."""
+    L = lib()
+    if src.dtype != "f32" or src.layout != "layer_ci":
+        raise TfscError("interleave_store takes FP32 channel-interleaved stores")
+    g, pc = grid.c(), src.c()
+    _lib.check(L.tfsc_interleave_store(ctypes.byref(g), ctypes.byref(pc), int(n_real), int(r), _ptr(out.pix),
+                                       _stream()), "tfsc_interleave_store")
+    return out
+
+
+def interleave_stores(grid: GridSpec, stores: list, out: PixelStore | None = None) -> PixelStore:
+    """One FP32 store [K][Nt][R][C] holding the R stores' pixels cell by cell (weights of the first store)."""
+    R = len(stores)
+    if out is None:
+        out = interleaved_store(grid, R, stores[0])
+    for r, s in enumerate(stores):
+        interleave_store(grid, s, R, r, out)
+    return out
+
+
+def bank_statistic_interleaved(grid: GridSpec, store: PixelStore, n_real: int, bank: BankTensors, seg: SegmentLayout,
+                               block_waves: int = 0, groups_per_cu: int = 0, order: torch.Tensor | None = None,
+                               out: MultiResult | None = None, ws: torch.Tensor | None = None,
+                               want_active: bool = False) -> MultiResult:
+    """tfsc_bank_statistic_multi with real_stride 0: the statistic of the n_real realisations interleaved in
+    ``store`` (from interleave_stores), all of them in one pass over the bank."""
+    L = lib()
+    dev = bank.device
+    total = max(seg.total, 1)
+    if out is None:
+        out = MultiResult(torch.empty((n_real, bank.n), dtype=torch.float64, device=dev),
+                          torch.empty((n_real, total), dtype=torch.float64, device=dev),
+                          torch.empty(bank.n, dtype=torch.int32, device=dev),
+                          torch.empty(bank.n, dtype=torch.int32, device=dev) if want_active else None)
+    g = grid.c()
+    opt = _options("f32", "wave", block_waves, groups_per_cu, order)
+    nb = L.tfsc_workspace_bytes(ctypes.byref(g), bank.n, ctypes.byref(opt), _lib.WS_STATISTIC)
+    if ws is None or ws.numel() < nb:
+        ws = _ws(nb, dev)
+    pc, bc, sc = store.c(), bank.c(), seg.c()
+    st = L.tfsc_bank_statistic_multi(ctypes.byref(g), ctypes.byref(pc), int(n_real), 0, 0, ctypes.byref(bc),
+                                     ctypes.byref(sc), ctypes.byref(opt), out.seg_terms.shape[1],
+                                     _ptr(out.seg_terms), _ptr(out.stat), _ptr(out.flags), _ptr(out.n_active),
+                                     _ptr(ws), ws.numel(), _stream())
     _lib.check(st, "tfsc_bank_statistic_multi")
     return out
 

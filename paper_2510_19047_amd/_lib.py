@@ -51,7 +51,7 @@ EXPORTS = ("tfsc_abi_version", "tfsc_status_string", "tfsc_workspace_bytes", "tf
            "tfsc_statistic_vjp",
            "tfsc_follow_up_step",
            "tfsc_processing_order", "tfsc_tile_max", "tfsc_track", "tfsc_bank_statistic_harmonics",
-           "tfsc_orbit_positions", "tfsc_tune_statistic")
+           "tfsc_orbit_positions", "tfsc_tune_statistic", "tfsc_interleave_store")
 
 _lib = None
 
@@ -112,6 +112,8 @@ def load(path: str = LIB_PATH):
                                                 c_void_p, c_void_p, c_size_t, c_void_p]
     L.tfsc_orbit_positions.restype = ctypes.c_int
     L.tfsc_orbit_positions.argtypes = [P(Grid), c_void_p, c_void_p]
+    L.tfsc_interleave_store.restype = ctypes.c_int
+    L.tfsc_interleave_store.argtypes = [P(Grid), P(Pixels), c_int32, c_int32, c_void_p, c_void_p]
     L.tfsc_tune_statistic.restype = ctypes.c_int
     L.tfsc_tune_statistic.argtypes = [P(Grid), P(Pixels), P(Bank), P(Segments), P(Options), ctypes.c_char_p,
                                       c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p, P(c_int32),

@@ -19,7 +19,10 @@ import os
 
 import torch
 
-from . import (BankTensors, GridSpec, PixelStore, SegmentLayout, StatResult, bank_statistic, bank_statistic_multi,
+import ctypes
+
+from . import (BankTensors, GridSpec, PixelStore, SegmentLayout, StatResult, TfscError, _lib, bank_statistic,
+               bank_statistic_interleaved, bank_statistic_multi, interleave_store, interleaved_store, lib,
                realisation_stores, transform, tune_statistic)
 
 
@@ -75,25 +78,52 @@ class RealisationGraph:
     allocated once (eager warm-up) and reused by every replay; ``results[r]`` holds realisation r's
     output after ``replay()``.  multi=True keeps the stores in one block and evaluates every
     realisation in one pass over the bank (bank_statistic_multi) instead of one launch each.
+    interleave=NR (2 or 4; FP32 channel-interleaved stores) transforms each realisation into one staging
+    store, copies it into its slot of an interleaved store of NR realisations, and evaluates each group of
+    NR realisations in one pass over the bank (bank_statistic_interleaved); R must be a multiple of NR.
     """
 
     def __init__(self, grid: GridSpec, xs: torch.Tensor, psd0: torch.Tensor, mu: torch.Tensor, keep: torch.Tensor,
                  bank: BankTensors, seg: SegmentLayout, store: str = "f32", precision: str = "f32",
                  order: torch.Tensor | None = None, block_waves: int = 0, groups_per_cu: int = 0,
-                 layout: str = "layer_ci", multi: bool = False, group: int = 0):
+                 layout: str = "layer_ci", multi: bool = False, group: int = 0, interleave: int = 0):
         self.grid, self.xs, self.psd0, self.mu, self.keep = grid, xs, psd0, mu, keep
         self.bank, self.seg, self.store, self.precision, self.order = bank, seg, store, precision, order
         self.shape = dict(block_waves=block_waves, groups_per_cu=groups_per_cu)
-        self.multi, self.group = multi, group
+        self.multi, self.group, self.interleave = multi, group, interleave
         R = xs.shape[0]
         dev = bank.device
+        L = lib()
+        g = grid.c()
+        nb = L.tfsc_workspace_bytes(ctypes.byref(g), bank.n, None, _lib.WS_STATISTIC)
+        self.ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+        if interleave:
+            if store != "f32" or layout != "layer_ci" or precision != "f32" or R % interleave:
+                raise TfscError("interleaved realisations take FP32 channel-interleaved stores, R a multiple of NR")
+            self.staging = transform(grid, xs[0], psd0, mu, keep, dtype="f32", layout="layer_ci")
+            self.groups = []
+            for q in range(R // interleave):
+                ri = interleaved_store(grid, interleave, self.staging)
+                for j in range(interleave):
+                    transform(grid, xs[q * interleave + j], psd0, mu, keep, dtype="f32", layout="layer_ci",
+                              out=self.staging)
+                    interleave_store(grid, self.staging, interleave, j, ri)
+                res = bank_statistic_interleaved(grid, ri, interleave, bank, seg, order=order, ws=self.ws,
+                                                 **self.shape)
+                self.groups.append((ri, res))
+            self.stores = [grp[0] for grp in self.groups]
+            self.results = [grp[1].realisation(r) for grp in self.groups for r in range(interleave)]
+            torch.cuda.synchronize()
+            self.graph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(self.graph):
+                self._enqueue()
+            return
         if multi:
             self.stores = realisation_stores(grid, R, dtype=store, layout=layout, device=dev)
             for r in range(R):
                 transform(grid, xs[r], psd0, mu, keep, dtype=store, out=self.stores[r])
         else:
             self.stores = [transform(grid, xs[r], psd0, mu, keep, dtype=store, layout=layout) for r in range(R)]
-        self.ws = torch.empty(1 << 22, dtype=torch.uint8, device=dev)
         if multi:
             self.multi_result = bank_statistic_multi(grid, self.stores, bank, seg, precision=precision, order=order,
                                                      ws=self.ws, group=group, **self.shape)
@@ -107,6 +137,16 @@ class RealisationGraph:
             self._enqueue()
 
     def _enqueue(self):
+        if self.interleave:
+            NR = self.interleave
+            for q, (ri, res) in enumerate(self.groups):
+                for j in range(NR):
+                    transform(self.grid, self.xs[q * NR + j], self.psd0, self.mu, self.keep, dtype="f32",
+                              layout="layer_ci", out=self.staging)
+                    interleave_store(self.grid, self.staging, NR, j, ri)
+                bank_statistic_interleaved(self.grid, ri, NR, self.bank, self.seg, order=self.order, out=res,
+                                           ws=self.ws, **self.shape)
+            return
         for r in range(self.xs.shape[0]):
             transform(self.grid, self.xs[r], self.psd0, self.mu, self.keep, dtype=self.store, out=self.stores[r])
             if not self.multi:

@@ -334,8 +334,17 @@ tfsc_status tfsc_bank_statistic_multi(const tfsc_grid *grid, const tfsc_pixels *
     if (!(pix->dtype == TFSC_F32 && r.precision == TFSC_F32) && !(pix->dtype == TFSC_F64 && r.precision == TFSC_F64))
         return TFSC_ERR_DTYPE;
     const uint64_t one = pixel_store_bytes(grid, pix);
-    if (real_stride < 0 || (uint64_t)real_stride < one || real_stride % 16 != 0) return TFSC_ERR_SHAPE;
-    if ((uint64_t)real_stride * (uint64_t)n_real > 0xffffffffull) return TFSC_ERR_UNSUPPORTED;
+    const bool interleaved = real_stride == 0;
+    if (interleaved) {
+        // realisations interleaved cell by cell: FP32, channel-interleaved, 2 or 4 of them, no rho
+        if (pix->layout != TFSC_LAYER_MAJOR_CI || pix->dtype != TFSC_F32 || pix->rho || (n_real != 2 && n_real != 4) ||
+            (group != 0 && group != n_real))
+            return TFSC_ERR_UNSUPPORTED;
+        if (one * (uint64_t)n_real > 0xffffffffull) return TFSC_ERR_UNSUPPORTED;
+    } else {
+        if (real_stride < 0 || (uint64_t)real_stride < one || real_stride % 16 != 0) return TFSC_ERR_SHAPE;
+        if ((uint64_t)real_stride * (uint64_t)n_real > 0xffffffffull) return TFSC_ERR_UNSUPPORTED;
+    }
     if (bank->n > 0 && (!seg_terms || !stat || !flags)) return TFSC_ERR_ARG;
     if (!ws || ws_bytes < stat_ws_bytes(grid, bank->n, bank->ln_mc != nullptr)) return TFSC_ERR_WORKSPACE;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -350,7 +359,21 @@ tfsc_status tfsc_bank_statistic_multi(const tfsc_grid *grid, const tfsc_pixels *
     L.real_stride = real_stride;
     L.seg_stride = seg_stride;
     L.multi_group = group == 0 ? tfsc::kMultiGroupDefault : group;
+    if (interleaved) return hip_status(tfsc::launch_statistic_interleaved(L, st));
     return hip_status(tfsc::launch_statistic_multi(L, st));
+}
+
+tfsc_status tfsc_interleave_store(const tfsc_grid *grid, const tfsc_pixels *src, int32_t n_real, int32_t r,
+                                  void *dst, void *stream) {
+    tfsc_status s;
+    if ((s = check_grid(grid)) != TFSC_OK) return s;
+    if (!src || !src->pix || !dst) return TFSC_ERR_ARG;
+    if (src->dtype != TFSC_F32) return TFSC_ERR_DTYPE;
+    if (src->layout != TFSC_LAYER_MAJOR_CI) return TFSC_ERR_UNSUPPORTED;
+    if (n_real < 1 || n_real > tfsc::kMaxRealisations || r < 0 || r >= n_real) return TFSC_ERR_ARG;
+    const int64_t cells = (int64_t)(grid->tranche_len / 2 + 1) * grid->n_tranches;
+    return hip_status(tfsc::launch_interleave(cells, grid->n_channels, n_real, r, src->pix, dst,
+                                              reinterpret_cast<hipStream_t>(stream)));
 }
 
 tfsc_status tfsc_statistic_vjp(const tfsc_grid *grid, const tfsc_pixels *pix, const tfsc_bank *bank,

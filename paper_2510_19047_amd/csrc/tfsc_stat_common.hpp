@@ -340,6 +340,14 @@ __device__ __forceinline__ void bin_pixels(__amdgpu_buffer_rsrc_t r, uint32_t vo
                 D[1] = {__uint_as_float(w1 << 16), __uint_as_float(w1 & 0xffff0000u)};
             }
         }
+    } else if constexpr (LAYOUT == 2 && C % 2 == 0 && sizeof(PixT) == 4) {
+        // an even number of FP32 channels side by side (several realisations interleaved): 16-byte loads
+#pragma unroll
+        for (int c = 0; c < C; c += 2) {
+            const float4 q = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff + (uint32_t)(c * 8), 0));
+            D[c] = {q.x, q.y};
+            D[c + 1] = {q.z, q.w};
+        }
     } else if constexpr (LAYOUT == 2 && C == 3 && sizeof(PixT) == 4) {
         // A and E with one 16-byte load, T with one 8-byte load (24-byte cells, 8-byte aligned)
         const float4 q = __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));

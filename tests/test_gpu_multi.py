@@ -98,3 +98,66 @@ def test_multi_argument_errors():
         tfsc.bank_statistic_multi(gridspec(g), [stores[0], stores[1], stores[0]], bt, seg)
     with pytest.raises(tfsc.TfscError):  # group size
         tfsc.bank_statistic_multi(gridspec(g), stores, bt, seg, group=3)
+
+
+@pytest.mark.parametrize("channels,n_real", [(2, 2), (2, 4), (1, 2), (1, 4)])
+def test_interleaved_realisations_match_single_launches(channels, n_real):
+    """Realisations interleaved cell by cell in one FP32 store (real_stride 0): each realisation against its own
+    single-realisation launch (2e-6; the same bin sums, FMA contraction may differ), on the small bank plus a
+    bank whose tracks start near bin 2 (the per-lane row path); flags and active counts equal; realisation 0
+    against the oracle (1e-6 on the wide bank, the float64 oracle's own small-beta loss on the low one)."""
+    from oracle import transform as otf
+    tfsc = lib()
+    d = small_data()
+    g0 = d["grid"]
+    g = g0 if channels == 2 else ti.custom_grid(1, g0.tranche_len, g0.n_tranches, dt=g0.dt, modulated=True,
+                                                   gapped=True, cfg_id=g0.cfg_id)
+    note(f"interleaved realisations: C={channels}, {n_real} realisations")
+    keep = ti.sample_keep_mask(g)[None, :]
+    xs = [(ti.noise(g, realisation=r) * keep).astype(np.float32) for r in range(n_real)]
+    psd, mu, kp = ti.psd_on_bins(g), ti.tranche_psd_scale(g), ti.tranche_keep(g)
+    stores = [tfsc.transform(gridspec(g), dev(x), dev(psd), dev(mu), dev(kp), dtype="f32", layout="layer_ci")
+              for x in xs]
+    ri = tfsc.interleave_stores(gridspec(g), stores)
+    low = ti.random_bank(64, 7, mc_range=(5.0, 100.0), f0_range=(0.0008, 0.006), eta=None, stream=35)
+    bank = ti.Bank.concat(low, d["bank"])
+    bt = tfsc.BankTensors.from_host(bank)
+    seg = tfsc.segment_layout(gridspec(g), bt)
+    order = tfsc.processing_order(gridspec(g), bt)
+    res = tfsc.bank_statistic_interleaved(gridspec(g), ri, n_real, bt, seg, order=order, want_active=True)
+    worst = 0.0
+    for r in range(n_real):
+        one = tfsc.bank_statistic(gridspec(g), stores[r], bt, seg, precision="f32", schedule="wave", want_active=True)
+        a, b = res.stat[r].cpu().numpy(), one.stat.cpu().numpy()
+        worst = max(worst, rel(a, b).max())
+        assert rel(a, b).max() < 2e-6, r
+        st_a, st_b = res.seg_terms[r, :seg.total].cpu().numpy(), one.seg_terms[:seg.total].cpu().numpy()
+        assert np.max(np.abs(st_a - st_b) / np.maximum(st_b, 1.0)) < 2e-5, r
+        assert torch.equal(res.flags, one.flags) and torch.equal(res.n_active, one.n_active)
+    pix, u, wm = otf.transform(xs[0].astype(np.float64), g, psd, mu, kp, 0.1, "rfft")
+    ref = oracle_stat(dict(d, grid=g, pix=pix, u=u, wm=wm), bank=bank)
+    r0 = rel(res.stat[0].cpu().numpy(), ref.stat)
+    note(f"  max rel against single launches {worst:.2e}; realisation 0 vs oracle {r0.max():.2e} "
+         f"(wide bank {r0[64:].max():.2e})")
+    assert r0[64:].max() < 1e-6 and r0.max() < 3e-6
+    assert np.array_equal(res.flags.cpu().numpy(), ref.flags)
+    assert not torch.equal(res.stat[0], res.stat[1])
+
+
+def test_interleaved_argument_errors():
+    tfsc = lib()
+    d = small_data()
+    g = d["grid"]
+    bt = tfsc.BankTensors.from_host(d["bank"])
+    seg = tfsc.segment_layout(gridspec(g), bt)
+    x = dev(d["x"].astype(np.float32))
+    s = tfsc.transform(gridspec(g), x, dev(d["psd"]), dev(d["mu"]), dev(d["keep"]), dtype="f32", layout="layer_ci")
+    ri = tfsc.interleave_stores(gridspec(g), [s, s, s])
+    with pytest.raises(tfsc.TfscError):  # three realisations interleaved
+        tfsc.bank_statistic_interleaved(gridspec(g), ri, 3, bt, seg)
+    lay = tfsc.transform(gridspec(g), x, dev(d["psd"]), dev(d["mu"]), dev(d["keep"]), dtype="f32", layout="layer")
+    with pytest.raises(tfsc.TfscError):  # only channel-interleaved stores interleave
+        tfsc.interleave_stores(gridspec(g), [lay, lay])
+    h = tfsc.transform(gridspec(g), x, dev(d["psd"]), dev(d["mu"]), dev(d["keep"]), dtype="f16", layout="layer_ci")
+    with pytest.raises(tfsc.TfscError):  # FP32 stores only
+        tfsc.interleave_stores(gridspec(g), [h, h])
