@@ -299,11 +299,12 @@ tfsc_status tfsc_bank_statistic_multi(const tfsc_grid *grid, const tfsc_pixels *
                                       size_t ws_bytes, void *stream);
 
 /* Realisations interleaved in one store (real_stride = 0 in
- * tfsc_bank_statistic_multi): pix->pix holds [K][Nt][n_real][C] complex FP32
+ * tfsc_bank_statistic_multi): pix->pix holds [K][Nt][n_real][C] complex
  * values, each (bin, tranche) cell carrying every realisation's C channels
- * side by side (pix->layout TFSC_LAYER_MAJOR_CI, dtype TFSC_F32, F32
- * precision, n_real 2 or 4, group 0 or n_real, no rho, n_real stores below
- * 4 GiB; else TFSC_ERR_UNSUPPORTED).  One pass over the bank forms each
+ * side by side (pix->layout TFSC_LAYER_MAJOR_CI; dtype TFSC_F32, or TFSC_I16
+ * with pix->layer_scale [n_real C][K], realisation r's channel c in row
+ * r C + c; F32 precision, n_real 2 or 4, group 0 or n_real, no rho, n_real
+ * stores below 4 GiB; else TFSC_ERR_UNSUPPORTED).  One pass over the bank forms each
  * template's track, bins and response once per tranche for all n_real
  * realisations, and one wide load per bin brings every realisation's pixels;
  * outputs as above.  The bin sums are the single-realisation kernel's (with
@@ -311,12 +312,14 @@ tfsc_status tfsc_bank_statistic_multi(const tfsc_grid *grid, const tfsc_pixels *
  * its own tfsc_bank_statistic to rounding.
  *
  * tfsc_interleave_store writes realisation r (0 <= r < n_real) of such a
- * store: src is one realisation's FP32 LAYER_MAJOR_CI store of this grid (as
- * tfsc_transform writes it), dst the interleaved store (device memory,
- * 8 C n_real K Nt bytes, owned by the caller).  inv_asd, tranche_w and the
- * rest of tfsc_pixels are those of any one realisation of the grid.         */
+ * store: src is one realisation's FP32 or I16 LAYER_MAJOR_CI store of this
+ * grid (as tfsc_transform writes it), dst the interleaved store of the same
+ * dtype and layout (dst->pix: device memory of b C n_real K Nt bytes, b = 8
+ * for F32 and 4 for I16; for I16 also dst->layer_scale [n_real C][K], into
+ * which src's scales are copied; owned by the caller).  inv_asd, tranche_w
+ * and the rest of tfsc_pixels are those of any one realisation of the grid. */
 tfsc_status tfsc_interleave_store(const tfsc_grid *grid, const tfsc_pixels *src, int32_t n_real, int32_t r,
-                                  void *dst, void *stream);
+                                  tfsc_pixels *dst, void *stream);
 
 /* tfsc_bank_statistic for callers that cannot allocate device memory (code
  * under HIP graph capture, tight serving loops, harnesses that forbid

@@ -415,20 +415,23 @@ def bank_statistic_multi(grid: GridSpec, stores: list, bank: BankTensors, seg: S
 
 
 def interleaved_store(grid: GridSpec, n_real: int, like: PixelStore) -> PixelStore:
-    """An (uninitialised) FP32 store [K][Nt][n_real][C] for n_real interleaved realisations, with the weights of
-    ``like``."""
+    """An (uninitialised) store [K][Nt][n_real][C] for n_real interleaved realisations of like's dtype (f32, or
+    i16 with layer scales [n_real C][K]) and weights."""
     K, Nt, C = grid.n_bins, grid.n_tranches, grid.n_channels
-    return PixelStore(torch.empty((K, Nt, n_real * C, 2), dtype=torch.float32, device=like.pix.device),
-                      like.inv_asd, like.tranche_w, "f32", "layer_ci", None, None, like.orbit)
+    if like.dtype not in ("f32", "i16"):
+        raise TfscError("interleaved stores hold f32 or i16 pixels")
+    dev = like.pix.device
+    return PixelStore(torch.empty((K, Nt, n_real * C, 2), dtype=_TORCH_STORE[like.dtype], device=dev),
+                      like.inv_asd, like.tranche_w, like.dtype, "layer_ci",
+                      torch.empty((n_real * C, K), dtype=torch.float32, device=dev) if like.dtype == "i16" else None,
+                      None, like.orbit)
 
 
 def interleave_store(grid: GridSpec, src: PixelStore, n_real: int, r: int, out: PixelStore) -> PixelStore:
-    """tfsc_interleave_store: realisation r (an FP32 channel-interleaved store) into slot r of ``out``."""
+    """tfsc_interleave_store: realisation r (an f32 or i16 channel-interleaved store) into slot r of ``out``."""
     L = lib()
-    if src.dtype != "f32" or src.layout != "layer_ci":
-        raise TfscError("interleave_store takes FP32 channel-interleaved stores")
-    g, pc = grid.c(), src.c()
-    _lib.check(L.tfsc_interleave_store(ctypes.byref(g), ctypes.byref(pc), int(n_real), int(r), _ptr(out.pix),
+    g, pc, oc = grid.c(), src.c(), out.c()
+    _lib.check(L.tfsc_interleave_store(ctypes.byref(g), ctypes.byref(pc), int(n_real), int(r), ctypes.byref(oc),
                                        _stream()), "tfsc_interleave_store")
     return out
 

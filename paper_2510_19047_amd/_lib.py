@@ -113,7 +113,7 @@ def load(path: str = LIB_PATH):
     L.tfsc_orbit_positions.restype = ctypes.c_int
     L.tfsc_orbit_positions.argtypes = [P(Grid), c_void_p, c_void_p]
     L.tfsc_interleave_store.restype = ctypes.c_int
-    L.tfsc_interleave_store.argtypes = [P(Grid), P(Pixels), c_int32, c_int32, c_void_p, c_void_p]
+    L.tfsc_interleave_store.argtypes = [P(Grid), P(Pixels), c_int32, c_int32, P(Pixels), c_void_p]
     L.tfsc_tune_statistic.restype = ctypes.c_int
     L.tfsc_tune_statistic.argtypes = [P(Grid), P(Pixels), P(Bank), P(Segments), P(Options), ctypes.c_char_p,
                                       c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p, P(c_int32),

@@ -78,7 +78,7 @@ class RealisationGraph:
     allocated once (eager warm-up) and reused by every replay; ``results[r]`` holds realisation r's
     output after ``replay()``.  multi=True keeps the stores in one block and evaluates every
     realisation in one pass over the bank (bank_statistic_multi) instead of one launch each.
-    interleave=NR (2 or 4; FP32 channel-interleaved stores) transforms each realisation into one staging
+    interleave=NR (2 or 4; f32 or i16 channel-interleaved stores) transforms each realisation into one staging
     store, copies it into its slot of an interleaved store of NR realisations, and evaluates each group of
     NR realisations in one pass over the bank (bank_statistic_interleaved); R must be a multiple of NR.
     """
@@ -98,14 +98,15 @@ class RealisationGraph:
         nb = L.tfsc_workspace_bytes(ctypes.byref(g), bank.n, None, _lib.WS_STATISTIC)
         self.ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
         if interleave:
-            if store != "f32" or layout != "layer_ci" or precision != "f32" or R % interleave:
-                raise TfscError("interleaved realisations take FP32 channel-interleaved stores, R a multiple of NR")
-            self.staging = transform(grid, xs[0], psd0, mu, keep, dtype="f32", layout="layer_ci")
+            if store not in ("f32", "i16") or layout != "layer_ci" or precision != "f32" or R % interleave:
+                raise TfscError("interleaved realisations take f32 or i16 channel-interleaved stores, R a "
+                                "multiple of NR")
+            self.staging = transform(grid, xs[0], psd0, mu, keep, dtype=store, layout="layer_ci")
             self.groups = []
             for q in range(R // interleave):
                 ri = interleaved_store(grid, interleave, self.staging)
                 for j in range(interleave):
-                    transform(grid, xs[q * interleave + j], psd0, mu, keep, dtype="f32", layout="layer_ci",
+                    transform(grid, xs[q * interleave + j], psd0, mu, keep, dtype=store, layout="layer_ci",
                               out=self.staging)
                     interleave_store(grid, self.staging, interleave, j, ri)
                 res = bank_statistic_interleaved(grid, ri, interleave, bank, seg, order=order, ws=self.ws,
@@ -141,7 +142,7 @@ class RealisationGraph:
             NR = self.interleave
             for q, (ri, res) in enumerate(self.groups):
                 for j in range(NR):
-                    transform(self.grid, self.xs[q * NR + j], self.psd0, self.mu, self.keep, dtype="f32",
+                    transform(self.grid, self.xs[q * NR + j], self.psd0, self.mu, self.keep, dtype=self.store,
                               layout="layer_ci", out=self.staging)
                     interleave_store(self.grid, self.staging, NR, j, ri)
                 bank_statistic_interleaved(self.grid, ri, NR, self.bank, self.seg, order=self.order, out=res,

@@ -331,14 +331,15 @@ tfsc_status tfsc_bank_statistic_multi(const tfsc_grid *grid, const tfsc_pixels *
     if (r.schedule != TFSC_SCHED_WAVE || pix->layout == TFSC_TRANCHE_MAJOR || grid->n_channels == 3 ||
         r.fresnel != TFSC_FRESNEL_PAPER)
         return TFSC_ERR_UNSUPPORTED;
-    if (!(pix->dtype == TFSC_F32 && r.precision == TFSC_F32) && !(pix->dtype == TFSC_F64 && r.precision == TFSC_F64))
+    const bool interleaved = real_stride == 0;
+    if (!(pix->dtype == TFSC_F32 && r.precision == TFSC_F32) && !(pix->dtype == TFSC_F64 && r.precision == TFSC_F64) &&
+        !(interleaved && pix->dtype == TFSC_I16 && r.precision == TFSC_F32))
         return TFSC_ERR_DTYPE;
     const uint64_t one = pixel_store_bytes(grid, pix);
-    const bool interleaved = real_stride == 0;
     if (interleaved) {
         // realisations interleaved cell by cell: FP32, channel-interleaved, 2 or 4 of them, no rho
-        if (pix->layout != TFSC_LAYER_MAJOR_CI || pix->dtype != TFSC_F32 || pix->rho || (n_real != 2 && n_real != 4) ||
-            (group != 0 && group != n_real))
+        if (pix->layout != TFSC_LAYER_MAJOR_CI || (pix->dtype != TFSC_F32 && pix->dtype != TFSC_I16) ||
+            r.precision != TFSC_F32 || pix->rho || (n_real != 2 && n_real != 4) || (group != 0 && group != n_real))
             return TFSC_ERR_UNSUPPORTED;
         if (one * (uint64_t)n_real > 0xffffffffull) return TFSC_ERR_UNSUPPORTED;
     } else {
@@ -364,16 +365,20 @@ tfsc_status tfsc_bank_statistic_multi(const tfsc_grid *grid, const tfsc_pixels *
 }
 
 tfsc_status tfsc_interleave_store(const tfsc_grid *grid, const tfsc_pixels *src, int32_t n_real, int32_t r,
-                                  void *dst, void *stream) {
+                                  tfsc_pixels *dst, void *stream) {
     tfsc_status s;
     if ((s = check_grid(grid)) != TFSC_OK) return s;
-    if (!src || !src->pix || !dst) return TFSC_ERR_ARG;
-    if (src->dtype != TFSC_F32) return TFSC_ERR_DTYPE;
-    if (src->layout != TFSC_LAYER_MAJOR_CI) return TFSC_ERR_UNSUPPORTED;
+    if (!src || !src->pix || !dst || !dst->pix) return TFSC_ERR_ARG;
+    if ((src->dtype != TFSC_F32 && src->dtype != TFSC_I16) || dst->dtype != src->dtype) return TFSC_ERR_DTYPE;
+    if (src->layout != TFSC_LAYER_MAJOR_CI || dst->layout != TFSC_LAYER_MAJOR_CI) return TFSC_ERR_UNSUPPORTED;
+    if (src->dtype == TFSC_I16 && (!src->layer_scale || !dst->layer_scale)) return TFSC_ERR_ARG;
     if (n_real < 1 || n_real > tfsc::kMaxRealisations || r < 0 || r >= n_real) return TFSC_ERR_ARG;
-    const int64_t cells = (int64_t)(grid->tranche_len / 2 + 1) * grid->n_tranches;
-    return hip_status(tfsc::launch_interleave(cells, grid->n_channels, n_real, r, src->pix, dst,
-                                              reinterpret_cast<hipStream_t>(stream)));
+    const int K = grid->tranche_len / 2 + 1;
+    const int64_t cells = (int64_t)K * grid->n_tranches;
+    const bool i16 = src->dtype == TFSC_I16;
+    return hip_status(tfsc::launch_interleave(cells, grid->n_channels, K, n_real, r, i16 ? 4 : 8, src->pix,
+                                              i16 ? src->layer_scale : nullptr, dst->pix,
+                                              i16 ? dst->layer_scale : nullptr, reinterpret_cast<hipStream_t>(stream)));
 }
 
 tfsc_status tfsc_statistic_vjp(const tfsc_grid *grid, const tfsc_pixels *pix, const tfsc_bank *bank,

@@ -4,7 +4,7 @@
 //
 // Layout [K][Nt][NR][C]: each (bin, tranche) cell holds the C channels of each of the NR
 // realisations side by side, so the cell is the channel-interleaved cell of one store with NR C
-// channels.  A template's track, Fresnel bins, response and Q are formed once per tranche; each
+// channels (FP32, or int16 pairs with the NR C channels' layer scales as [NR C][K]).  A template's track, Fresnel bins, response and Q are formed once per tranche; each
 // bin's NR C pixels come in wide loads, and the bin sums are those of the single-realisation WAVE
 // kernel with the cell's NR C values taken as channels.  Realisation r's tranche sum is
 // z_r = w_m sum_c T_c P_{r C + c}; N_n is shared by every realisation.
@@ -12,9 +12,10 @@
 
 namespace tfsc {
 
-// Copy one realisation's channel-interleaved FP32 store into slot r of an interleaved store.
-__global__ void k_interleave(int64_t cells, int C, int NR, int r, const float2 *__restrict__ src,
-                             float2 *__restrict__ dst) {
+// Copy one realisation's channel-interleaved store into slot r of an interleaved store (T: one complex
+// value, float2 for FP32 or uint32_t for int16 pairs).
+template <class T>
+__global__ void k_interleave(int64_t cells, int C, int NR, int r, const T *__restrict__ src, T *__restrict__ dst) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // one complex value of the source
     if (e >= cells * C) return;
     const int64_t cell = e / C;
@@ -22,11 +23,26 @@ __global__ void k_interleave(int64_t cells, int C, int NR, int r, const float2 *
     dst[(cell * NR + r) * C + c] = src[e];
 }
 
-hipError_t launch_interleave(int64_t cells, int C, int NR, int r, const void *src, void *dst, hipStream_t st) {
+// The per-layer scales of a 16-bit store: source [C][K] into rows r C .. r C + C - 1 of [NR C][K].
+__global__ void k_interleave_scale(int C, int K, int r, const float *__restrict__ src, float *__restrict__ dst) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < C * K) dst[r * C * K + e] = src[e];
+}
+
+hipError_t launch_interleave(int64_t cells, int C, int K, int NR, int r, int elem_bytes, const void *src,
+                             const float *src_scale, void *dst, float *dst_scale, hipStream_t st) {
     const int64_t n = cells * C;
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_interleave, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, cells, C, NR, r,
-                       reinterpret_cast<const float2 *>(src), reinterpret_cast<float2 *>(dst));
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (elem_bytes == 8)
+        hipLaunchKernelGGL(k_interleave<float2>, grid, dim3(256), 0, st, cells, C, NR, r,
+                           reinterpret_cast<const float2 *>(src), reinterpret_cast<float2 *>(dst));
+    else
+        hipLaunchKernelGGL(k_interleave<uint32_t>, grid, dim3(256), 0, st, cells, C, NR, r,
+                           reinterpret_cast<const uint32_t *>(src), reinterpret_cast<uint32_t *>(dst));
+    if (src_scale)
+        hipLaunchKernelGGL(k_interleave_scale, dim3((unsigned)((C * K + 255) / 256)), dim3(256), 0, st, C, K, r,
+                           src_scale, dst_scale);
     return hipGetLastError();
 }
 
@@ -57,7 +73,7 @@ __device__ __forceinline__ void close_segments_ri(SegAccRi<NR> &acc, int upto, i
     }
 }
 
-template <int C, int NR>
+template <int C, int NR, class PixT>
 __global__ __launch_bounds__(256, 3) void k_stat_wave_ri(StatArgs a) {
 #pragma clang fp contract(fast)
     using R = float;
@@ -65,12 +81,18 @@ __global__ __launch_bounds__(256, 3) void k_stat_wave_ri(StatArgs a) {
     extern __shared__ unsigned char smem_raw[];
     const int KP = a.K + 2 * kHalfBins;
     R *u_pad = reinterpret_cast<R *>(smem_raw);
+    float *sc_pad = reinterpret_cast<float *>(smem_raw + sizeof(R) * KP);  // int16: the cell's CC layer scales
     const double u_mul = a.u_scale[0];
     const int kmax = a.M / 2 - 1;
     for (int q = threadIdx.x; q < KP; q += blockDim.x) {
         const int k = q - kHalfBins;
         u_pad[q] = (k >= 1 && k <= kmax) ? (R)(a.inv_asd[k] * u_mul) : (R)0;
     }
+    if constexpr (PixTraits<PixT>::scaled)
+        for (int q = threadIdx.x; q < CC * KP; q += blockDim.x) {
+            const int c = q / KP, k = q % KP - kHalfBins;
+            sc_pad[q] = (k >= 0 && k < a.K) ? a.layer_scale[c * a.K + k] : 0.0f;
+        }
     __syncthreads();
     const __amdgpu_buffer_rsrc_t rsrc = pix_rsrc(a.pix, a.pix_bytes);
     const GeoView gv = geo_view(a.geo, a.geo32, a.Nt);
@@ -147,11 +169,11 @@ __global__ __launch_bounds__(256, 3) void k_stat_wave_ri(StatArgs a) {
                 cx<R> P[CC];
                 R Q;
                 if (low)
-                    wave_tranche_bins_low<CC, R, float, 2, false>(ts, kc, m, a.Nt, a.K, rsrc, rsrc, u_pad, nullptr,
-                                                                  jA, jB, P, Q);
+                    wave_tranche_bins_low<CC, R, PixT, 2, false>(ts, kc, m, a.Nt, a.K, rsrc, rsrc, u_pad, sc_pad,
+                                                                 jA, jB, P, Q);
                 else
-                    wave_tranche_bins<CC, R, float, 2, false>(ts, kc, m, a.Nt, a.K, rsrc, rsrc, u_pad, nullptr, jA,
-                                                              jB, P, Q);
+                    wave_tranche_bins<CC, R, PixT, 2, false>(ts, kc, m, a.Nt, a.K, rsrc, rsrc, u_pad, sc_pad, jA,
+                                                             jB, P, Q);
                 cx<R> TA, TE, TT;
                 transfer_ae<R, false>(S, gv, m, f, TA, TE, &TT);
                 R tt = TA.re * TA.re + TA.im * TA.im;
@@ -209,18 +231,31 @@ __global__ __launch_bounds__(256, 3) void k_stat_wave_ri(StatArgs a) {
     }
 }
 
-template <int C, int NR>
+template <int C, int NR, class PixT>
 static hipError_t launch_ri_t(const StatArgs &a, int n_groups, int block_waves, hipStream_t st) {
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, a.counter, 1);
-    const size_t shmem = sizeof(float) * ((size_t)a.K + 2 * kHalfBins);
-    hipLaunchKernelGGL((k_stat_wave_ri<C, NR>), dim3(n_groups), dim3(64 * block_waves), shmem, st, a);
+    const size_t KP = (size_t)a.K + 2 * kHalfBins;
+    const size_t shmem = sizeof(float) * KP * (PixTraits<PixT>::scaled ? 1 + NR * C : 1);
+    hipLaunchKernelGGL((k_stat_wave_ri<C, NR, PixT>), dim3(n_groups), dim3(64 * block_waves), shmem, st, a);
     return hipGetLastError();
+}
+
+template <class PixT>
+static hipError_t dispatch_ri(const StatLaunch &L, const StatArgs &a, int g, int bw, hipStream_t st) {
+    switch (L.C * 8 + L.n_real) {
+        case 8 + 2: return launch_ri_t<1, 2, PixT>(a, g, bw, st);
+        case 8 + 4: return launch_ri_t<1, 4, PixT>(a, g, bw, st);
+        case 16 + 2: return launch_ri_t<2, 2, PixT>(a, g, bw, st);
+        case 16 + 4: return launch_ri_t<2, 4, PixT>(a, g, bw, st);
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_statistic_interleaved(const StatLaunch &L, hipStream_t st) {
     if (L.n == 0) return hipSuccess;
     StatArgs a = make_args(L);
-    const uint64_t tot = 8ull * (uint64_t)L.C * (uint64_t)L.n_real * (uint64_t)(L.M / 2 + 1) * (uint64_t)L.Nt;
+    const uint64_t eb = L.pix_dtype == 4 ? 4ull : 8ull;  // bytes per complex value: int16 pair or FP32
+    const uint64_t tot = eb * (uint64_t)L.C * (uint64_t)L.n_real * (uint64_t)(L.M / 2 + 1) * (uint64_t)L.Nt;
     if (tot > 0xffffffffull) return hipErrorInvalidValue;
     a.pix_bytes = (uint32_t)tot;
     a.seg_stride = L.seg_stride;
@@ -228,13 +263,8 @@ hipError_t launch_statistic_interleaved(const StatLaunch &L, hipStream_t st) {
     int64_t groups = (L.n + bw - 1) / bw;
     if (groups > (int64_t)L.n_groups) groups = L.n_groups;
     const int g = (int)groups;
-    switch (L.C * 8 + L.n_real) {
-        case 8 + 2: return launch_ri_t<1, 2>(a, g, bw, st);
-        case 8 + 4: return launch_ri_t<1, 4>(a, g, bw, st);
-        case 16 + 2: return launch_ri_t<2, 2>(a, g, bw, st);
-        case 16 + 4: return launch_ri_t<2, 4>(a, g, bw, st);
-    }
-    return hipErrorInvalidValue;
+    if (L.pix_dtype == 4) return dispatch_ri<int16_t>(L, a, g, bw, st);
+    return dispatch_ri<float>(L, a, g, bw, st);
 }
 
 }  // namespace tfsc

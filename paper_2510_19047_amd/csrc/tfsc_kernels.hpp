@@ -112,7 +112,8 @@ hipError_t launch_layout(const LayoutLaunch &L, hipStream_t st);
 hipError_t launch_geometry(int Nt, double dT, const double *orbit, double *geo, hipStream_t st);
 hipError_t launch_orbit_positions(int Nt, double dT, double *out, hipStream_t st);
 hipError_t launch_statistic_interleaved(const StatLaunch &L, hipStream_t st);
-hipError_t launch_interleave(int64_t cells, int C, int NR, int r, const void *src, void *dst, hipStream_t st);
+hipError_t launch_interleave(int64_t cells, int C, int K, int NR, int r, int elem_bytes, const void *src,
+                             const float *src_scale, void *dst, float *dst_scale, hipStream_t st);
 hipError_t launch_exp_mc(int64_t n, const double *ln_mc, double *mc, hipStream_t st);
 hipError_t launch_weight_scale(int K, const double *inv_asd, double *scale_out, hipStream_t st);
 hipError_t launch_statistic(const StatLaunch &L, hipStream_t st);

@@ -340,6 +340,14 @@ __device__ __forceinline__ void bin_pixels(__amdgpu_buffer_rsrc_t r, uint32_t vo
                 D[1] = {__uint_as_float(w1 << 16), __uint_as_float(w1 & 0xffff0000u)};
             }
         }
+    } else if constexpr (LAYOUT == 2 && C % 4 == 0 && __is_same(PixT, int16_t)) {
+        // a multiple of four int16 channels side by side (several realisations interleaved): 16-byte loads
+#pragma unroll
+        for (int c = 0; c < C; c += 4) {
+            const auto q = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff + (uint32_t)(c * 4), 0);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) D[c + e] = i16x2_to_float((uint32_t)q[e]);
+        }
     } else if constexpr (LAYOUT == 2 && C % 2 == 0 && sizeof(PixT) == 4) {
         // an even number of FP32 channels side by side (several realisations interleaved): 16-byte loads
 #pragma unroll

@@ -91,3 +91,39 @@ def test_noalloc_refuses_grids_beyond_the_scratch():
                                        ctypes.byref(opt), p(out), p(out), None, p(fl), None, None)
     assert st == _lib.TFSC_ERR_SCRATCH
     assert b"scratch" in L.tfsc_status_string(st)
+
+
+def test_noalloc_bank_in_ln_mc():
+    """A bank given in ln Mc: the chirp-mass table lies in the static scratch beside the geometry tables; the call
+    equals the workspace call bit for bit, twice in a row; a bank too large for the table is refused before any
+    launch."""
+    tfsc = lib()
+    from paper_2510_19047_amd import _lib
+    g, pix, u, wm, b = _case(700, 96, 61)
+    grid = gridspec(g)
+    bt = tfsc.BankTensors.from_host(b)
+    bl = tfsc.BankTensors(None, bt.eta, bt.f0, bt.cos_theta, bt.phi, bt.psi, bt.cos_iota, ln_mc=torch.log(bt.mc))
+    seg = tfsc.segment_layout(grid, bl)
+    store = tfsc.PixelStore.from_complex(dev(pix), dev(u), dev(wm), dtype="f32", layout="layer_ci")
+    note("noalloc: bank in ln Mc")
+    want = tfsc.bank_statistic(grid, store, bl, seg, precision="f32", schedule="wave", want_zn=True)
+    for _ in range(2):
+        stat, terms, zn, flags = _raw_noalloc(tfsc, grid, store, bl, seg, "f32", "wave")
+        torch.cuda.synchronize()
+        assert torch.equal(stat, want.stat) and torch.equal(flags, want.flags)
+        assert torch.equal(terms, want.seg_terms[:seg.total]) and torch.equal(zn, want.seg_zn[:seg.total])
+    # 8 bytes per template beside the tables of a 700-tranche grid: 400,000 templates do not fit in 3 MiB
+    L = _lib.load()
+    n = 400_000
+    z = torch.zeros(n, dtype=torch.float64, device="cuda")
+    big = tfsc.BankTensors(None, z, z, z, z, z, z, ln_mc=z)
+    segb = tfsc.SegmentLayout(nseg=torch.full((n,), 16, dtype=torch.int32, device="cuda"),
+                              seg_offset=torch.zeros(n + 1, dtype=torch.int64, device="cuda"), total=0)
+    out = torch.empty(16, dtype=torch.float64, device="cuda")
+    fl = torch.empty(n, dtype=torch.int32, device="cuda")
+    gc, pc, bc, sc = grid.c(), store.c(), big.c(), segb.c()
+    opt = tfsc._options("f32", "wave", 0, 0, None)
+    p = lambda t: ctypes.c_void_p(t.data_ptr())
+    st = L.tfsc_bank_statistic_noalloc(ctypes.byref(gc), ctypes.byref(pc), ctypes.byref(bc), ctypes.byref(sc),
+                                       ctypes.byref(opt), p(out), p(out), None, p(fl), None, None)
+    assert st == _lib.TFSC_ERR_SCRATCH
