@@ -87,6 +87,10 @@ def parse():
                    help="only the differentiation kernels, for profiling: on the 2-yr grid, the first 65,536 "
                         "templates of the bench's bank, one FP32 statistic (with z_n) and --steps launches each of "
                         "the statistic, the FP64 VJP and the FP32 VJP; prints one JSON line of event timings")
+    p.add_argument("--batching-profile", action="store_true",
+                   help="only the batching kernels, for profiling: the first 1,000,000 templates of the batching bank "
+                        "over 4 noise realisations, one graph replay each of one FP32 launch per realisation, FP32 "
+                        "pairs and int16 pairs interleaved per store; prints one JSON line of timings")
     p.add_argument("--fetch-factor", type=float, default=2.0,
                    help="bytes per FETCH_SIZE KiB / 1024 from the copy calibration")
     p.add_argument("--write-factor", type=float, default=1.0,
@@ -109,7 +113,7 @@ def main():
     import torch
     import tfsc_inputs as ti
     noise_jobs = None
-    if not args.no_batching:
+    if not (args.no_batching or args.vjp_profile or args.batching_profile):
         # the batching workload's 16 noise realisations are drawn on the host by worker processes forked
         # here, before this process touches the GPU; they run while the GPU works on the rest
         import multiprocessing as mp
@@ -124,6 +128,9 @@ def main():
     grid = tfsc.GridSpec(g.n_channels, g.tranche_len, g.n_tranches, g.dt, 0.1)
     if args.vjp_profile:
         vjp_profile_run(args, tfsc, ti, g, grid, dev)
+        return
+    if args.batching_profile:
+        batching_profile_run(tfsc, ti, g, grid, dev)
         return
 
     log("generating synthetic data (noise, gaps, modulation) and bank")
@@ -378,6 +385,53 @@ def harmonics_run(args, tfsc, grid, g, pix, bank, bank_h, seg, order, kw, k_ms_o
             "templates_per_s_kernel": round(n / (k_ms / 1e3), 1), "kernel_over_single": round(k_ms / k_ms_one, 4),
             "store": f"f32 {args.chosen_layout}", "arith": "f32 (track f64)",
             "sampled_parity": {"templates": len(idx), "max_rel_vs_oracle": float(r.max()), "flags_equal": flags_ok}}
+
+
+def batching_profile_run(tfsc, ti, g, grid, dev):
+    """One statistic launch per realisation against realisations interleaved in pairs (FP32 and int16) on 1M
+    templates of the batching bank and 4 realisations, each as a replayed graph timed by wall clock (the run
+    rocprofv3 profiles for the interleaved kernel)."""
+    import torch
+    from paper_2510_19047_amd import batching
+    R = 4
+    keep = ti.sample_keep_mask(g)[None, :]
+    xs = torch.stack([torch.from_numpy((ti.noise(g, realisation=r) * keep).astype(np.float32))
+                      for r in range(R)]).to(dev)
+    psd, mu, kp = (torch.from_numpy(a).to(dev) for a in (ti.psd_on_bins(g), ti.tranche_psd_scale(g),
+                                                           ti.tranche_keep(g)))
+    bank = tfsc.BankTensors.from_host(ti.batching_bank(1_000_000), dev)
+    seg = tfsc.segment_layout(grid, bank)
+    order = tfsc.processing_order(grid, bank)
+    kw = dict(block_waves=4, groups_per_cu=4)
+
+    def timed(rg, reps=3):
+        rg.replay()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            rg.replay()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    out = {"workload": "first 1,000,000 templates of the batching bank x 4 noise realisations of the 2-yr A+E data",
+           "templates": bank.n, "realisations": R}
+    rg = batching.RealisationGraph(grid, xs, psd, mu, kp, bank, seg, store="f32", layout="layer_ci", precision="f32",
+                                   order=order, **kw)
+    out["one_per_launch_ms"] = round(1e3 * timed(rg), 2)
+    log(f"batching profile: one launch per realisation {out['one_per_launch_ms']:.1f} ms per replay")
+    for st in ("f32", "i16"):
+        rgi = batching.RealisationGraph(grid, xs, psd, mu, kp, bank, seg, store=st, layout="layer_ci",
+                                        precision="f32", order=order, interleave=2, **kw)
+        ms = 1e3 * timed(rgi)
+        d = max(float(torch.max(torch.abs(rgi.results[r].stat - rg.results[r].stat)
+                                / torch.clamp(rg.results[r].stat.abs(), min=1.0))) for r in range(R))
+        out[f"pairs_{st}_ms"] = round(ms, 2)
+        out[f"pairs_{st}_max_rel_vs_fp32"] = d
+        log(f"batching profile: {st} pairs {ms:.1f} ms per replay ({out['one_per_launch_ms'] / ms:.3f}x); max rel {d:.1e}")
+        del rgi
+    print(json.dumps(out), flush=True)
 
 
 def vjp_profile_run(args, tfsc, ti, g, grid, dev):
