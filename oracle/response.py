@@ -29,6 +29,18 @@ the reconstruction used here is the standard one and is stated in full:
     A = (Z - X) / sqrt 2, E = (X - 2Y + Z) / sqrt 6.
   The TDI-2 rescaling is a common factor of A and E and cancels in the
   statistic, so it is omitted.
+* Unequal arms (the Outlook's varying arm lengths and point-ahead light
+  times): a caller's table of the six link light times L_sr at the tranche
+  starts, the geometry frozen over each tranche.  Link s -> r is received
+  at p_r after travelling L_sr along the arm direction n_sr, so it left
+  from p_r - L_sr n_sr:
+    time domain: y_sr(t) = n.[H(t - k.p_r - L_sr (1 - k.n)) - H(t - k.p_r)].n / (2 (1 - k.n))
+    per tranche: G_sr = -i pi f L_sr sinc(pi f L_sr (1 - k.n))
+                        exp(-i pi f (L_sr (1 - k.n) + 2 k.p_r)) (a+ n.e+.n + ax n.ex.n)
+  and first-generation TDI with each path's own delays, D_sr = exp(-2 pi i f L_sr):
+    X = (1 - D12 D21)(y31 + D31 y13) - (1 - D13 D31)(y21 + D21 y12), Y, Z cyclic.
+  With six equal light times L on a table whose sides are exactly L this is
+  the equal-arm form above (p_s = p_r - L n).
 """
 from __future__ import annotations
 
@@ -44,6 +56,8 @@ YEAR_S = 31557600.0
 
 # ordered links (sender, receiver), 0-based spacecraft indices
 LINKS = [(0, 1), (1, 0), (1, 2), (2, 1), (2, 0), (0, 2)]
+# rows of a link light-time table [6][Nt]: each arm's link to the next spacecraft, then the reverse links
+LINK_ROWS = [(0, 1), (1, 2), (2, 0), (1, 0), (2, 1), (0, 2)]
 
 
 def orbits(t):
@@ -83,6 +97,13 @@ def sky_frame(cos_theta, phi, psi):
     return k, ep, ex
 
 
+def link_lengths(pos):
+    """|p_r - p_s| of each link of positions [..., 3, 3] as a table [..., 6] (rows as LINK_ROWS): the light
+    times of a constellation whose links have no point-ahead difference."""
+    p = torch.as_tensor(pos, dtype=torch.float64)
+    return torch.stack([torch.linalg.norm(p[..., r, :] - p[..., s, :], dim=-1) for (s, r) in LINK_ROWS], dim=-1)
+
+
 def _link_geometry(p, s, r):
     d = p[..., r, :] - p[..., s, :]
     n = d / torch.linalg.norm(d, dim=-1, keepdim=True)
@@ -103,28 +124,33 @@ def transfer_ae(t, f, cos_theta, phi, psi, cos_iota):
     return TA, TE
 
 
-def transfer_aet(t, f, cos_theta, phi, psi, cos_iota, pos=None):
+def transfer_aet(t, f, cos_theta, phi, psi, cos_iota, pos=None, links=None):
     """(T_A, T_E, T_T): the third channel T = (X + Y + Z) / sqrt 3 completes A and E to an orthonormal
     combination of X, Y, Z (so |T_A|^2 + |T_E|^2 + |T_T|^2 = |T_X|^2 + |T_Y|^2 + |T_Z|^2).  ``pos``: spacecraft
-    positions [..., 3, 3] at the times t (a caller's orbit), None for the analytic orbit."""
-    TX, TY, TZ = transfer_xyz(t, f, cos_theta, phi, psi, cos_iota, pos)
+    positions [..., 3, 3] at the times t (a caller's orbit), None for the analytic orbit; ``links``: the six
+    link light times [..., 6] at the times t (unequal arms), None for equal arms."""
+    TX, TY, TZ = transfer_xyz(t, f, cos_theta, phi, psi, cos_iota, pos, links)
     TA = (TZ - TX) / math.sqrt(2.0)
     TE = (TX - 2.0 * TY + TZ) / math.sqrt(6.0)
     TT = (TX + TY + TZ) / math.sqrt(3.0)
     return TA, TE, TT
 
 
-def transfer_xyz(t, f, cos_theta, phi, psi, cos_iota, pos=None):
+def transfer_xyz(t, f, cos_theta, phi, psi, cos_iota, pos=None, links=None):
     """Per-tranche transfer of the Michelson combinations (T_X, T_Y, T_Z) that A, E and T are formed from.
 
     ``pos``: spacecraft positions [..., 3 spacecraft, 3 coordinates] (light-seconds) at the times t, for an
     orbit other than the analytic one (Sec. "Outlook": numerical or generic orbits); the arm directions come
-    from them, the arm length of the link transfer and the TDI delays stays L."""
+    from them, the arm length of the link transfer and the TDI delays stays L.
+    ``links``: the six link light times [..., 6] (light-seconds, rows as LINK_ROWS) at the times t; the
+    unequal-arm form of the module docstring then replaces the equal-arm one."""
     t = t if torch.is_tensor(t) else torch.as_tensor(t, dtype=torch.float64)
     f = f if torch.is_tensor(f) else torch.as_tensor(f, dtype=torch.float64)
     ci = cos_iota if torch.is_tensor(cos_iota) else torch.as_tensor(cos_iota, dtype=torch.float64)
     k, ep, ex = sky_frame(cos_theta, phi, psi)
     p = orbits(t) if pos is None else torch.as_tensor(pos, dtype=torch.float64)
+    if links is not None:
+        return _transfer_xyz_links(f, k, ep, ex, ci, p, torch.as_tensor(links, dtype=torch.float64))
     ap = (1.0 + ci * ci) / 2.0
     G = {}
     for (s, r) in LINKS:
@@ -145,6 +171,58 @@ def transfer_xyz(t, f, cos_theta, phi, psi, cos_iota, pos=None):
     TY = one_m_d2 * ((g(1, 2) + D * g(2, 1)) - (g(3, 2) + D * g(2, 3)))
     TZ = one_m_d2 * ((g(2, 3) + D * g(3, 2)) - (g(1, 3) + D * g(3, 1)))
     return TX, TY, TZ
+
+
+def _transfer_xyz_links(f, k, ep, ex, ci, p, links):
+    """(T_X, T_Y, T_Z) with the six link light times ``links`` [..., 6] and positions ``p`` [..., 3, 3]."""
+    ap = (1.0 + ci * ci) / 2.0
+    G, D = {}, {}
+    for row, (s, r) in enumerate(LINK_ROWS):
+        L = links[..., row]
+        n = _link_geometry(p, s, r)
+        kn = n @ k
+        amp = torch.complex(ap * _quad(n, ep), -ci * _quad(n, ex))
+        x = PI * f * L * (1.0 - kn)
+        sinc = torch.where(x == 0, torch.ones_like(x), torch.sin(x) / torch.where(x == 0, torch.ones_like(x), x))
+        ph = -PI * f * (L * (1.0 - kn) + 2.0 * (p[..., r, :] @ k))
+        G[(s, r)] = torch.complex(torch.zeros_like(f), -PI * f * L) * sinc * torch.polar(torch.ones_like(ph), ph) * amp
+        D[(s, r)] = torch.polar(torch.ones_like(f), -2.0 * PI * f * L)
+    g = lambda s, r: G[(s - 1, r - 1)]  # 1-based spacecraft labels, sender first
+    d = lambda s, r: D[(s - 1, r - 1)]
+    TX = (1.0 - d(1, 2) * d(2, 1)) * (g(3, 1) + d(3, 1) * g(1, 3)) - (1.0 - d(1, 3) * d(3, 1)) * (g(2, 1) + d(2, 1) * g(1, 2))
+    TY = (1.0 - d(2, 3) * d(3, 2)) * (g(1, 2) + d(1, 2) * g(2, 1)) - (1.0 - d(2, 1) * d(1, 2)) * (g(3, 2) + d(3, 2) * g(2, 3))
+    TZ = (1.0 - d(3, 1) * d(1, 3)) * (g(2, 3) + d(2, 3) * g(3, 2)) - (1.0 - d(3, 2) * d(2, 3)) * (g(1, 3) + d(1, 3) * g(3, 1))
+    return TX, TY, TZ
+
+
+def tdi_xyz_td_frozen(t, hfun, cos_theta, phi, psi, pos, links):
+    """Time-domain X, Y, Z at times t for one frozen geometry: positions ``pos`` [3, 3] and the six link light
+    times ``links`` [6] (rows as LINK_ROWS), every link and delay of the unequal-arm form written out."""
+    k, ep, ex = sky_frame(cos_theta, phi, psi)
+    p = torch.as_tensor(pos, dtype=torch.float64)
+    Ls = {sr: float(links[row]) for row, sr in enumerate(LINK_ROWS)}
+
+    def y(s, r, tau):
+        s0, r0 = s - 1, r - 1
+        n = _link_geometry(p, s0, r0)
+        kn = float(n @ k)
+        kpr = float(p[r0] @ k)
+        te = tau - kpr - Ls[(s0, r0)] * (1.0 - kn)
+        tr = tau - kpr
+        hp_e, hx_e = hfun(te)
+        hp_r, hx_r = hfun(tr)
+        return ((hp_e - hp_r) * _quad(n, ep) + (hx_e - hx_r) * _quad(n, ex)) / (2.0 * (1.0 - kn))
+
+    def L(s, r):
+        return Ls[(s - 1, r - 1)]
+
+    def michelson(a, b, c):
+        # centred on a: (1 - R_ab)(y_ca + D_ca y_ac) - (1 - R_ac)(y_ba + D_ba y_ab), R_ab the round trip a -> b -> a
+        rab, rac = L(a, b) + L(b, a), L(a, c) + L(c, a)
+        return (y(c, a, t) + y(a, c, t - L(c, a)) - y(c, a, t - rab) - y(a, c, t - rab - L(c, a))) \
+            - (y(b, a, t) + y(a, b, t - L(b, a)) - y(b, a, t - rac) - y(a, b, t - rac - L(b, a)))
+
+    return michelson(1, 2, 3), michelson(2, 3, 1), michelson(3, 1, 2)
 
 
 def link_td(t, hfun, s, r, k, ep, ex):
