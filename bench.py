@@ -58,6 +58,9 @@ def parse():
                    help="skip the 16-bit pixel stores (FP16, BF16) of the precision form")
     p.add_argument("--no-harmonics", action="store_true",
                    help="skip the multi-harmonic leg (harmonics 1, 2, 3 of the orbital phase on the same data and bank)")
+    p.add_argument("--no-links", action="store_true",
+                   help="skip the unequal-arm leg (the chosen form with six link light times per tranche on the "
+                        "same data and bank)")
     p.add_argument("--interleave", type=int, default=2, choices=[0, 2, 4],
                    help="also time the batching workload with 2 or 4 realisations interleaved cell by cell in one "
                         "store and evaluated in one pass over the bank (0: skip)")
@@ -325,6 +328,11 @@ def main():
         out["harmonics"] = harmonics_run(args, tfsc, grid, g, pix_chosen, bank, bank_h, seg, order, kw, k_ms, pix_o,
                                          u_o, wm_o)
 
+    # ---------------- unequal arms: six link light times per tranche on the same store and bank
+    if not args.no_links:
+        out["links"] = links_run(args, tfsc, grid, g, pix_chosen, bank, bank_h, seg, order, kw, k_ms, pix_o, u_o,
+                                 wm_o)
+
     # ---------------- precision form: 16-bit pixel stores with a per-layer FP32 scale
     if not args.no_precision:
         del pix_plain
@@ -384,6 +392,53 @@ def harmonics_run(args, tfsc, grid, g, pix, bank, bank_h, seg, order, kw, k_ms_o
                         "(|a1| 0.3, a2 1, |a3| 0.4)", "harmonics": hs, "kernel_ms": round(k_ms, 3),
             "templates_per_s_kernel": round(n / (k_ms / 1e3), 1), "kernel_over_single": round(k_ms / k_ms_one, 4),
             "store": f"f32 {args.chosen_layout}", "arith": "f32 (track f64)",
+            "sampled_parity": {"templates": len(idx), "max_rel_vs_oracle": float(r.max()), "flags_equal": flags_ok}}
+
+
+def links_run(args, tfsc, grid, g, pix, bank, bank_h, seg, order, kw, k_ms_eq, pix_o, u_o, wm_o):
+    """The chosen form with a caller's link light times (unequal arms): the analytic orbit's |p_r - p_s|
+    (tfsc_link_lengths), arm a flexing by +-1% over a year (phase 2 pi a / 3) and each reverse link 1e-5 longer
+    (a point-ahead scale difference).  The statistic kernel timed with events against the equal-arm kernel, and
+    sampled templates against the oracle's unequal-arm statistic."""
+    import dataclasses
+    import torch
+    from oracle import o2
+    from oracle import track as otrk
+    n = bank.n
+    lk = tfsc.link_lengths(grid)
+    t = torch.arange(g.n_tranches, dtype=torch.float64, device=lk.device) * g.tranche_dur
+    yr = 31557600.0
+    flex = torch.stack([0.01 * torch.sin(2.0 * np.pi * t / yr + 2.0 * np.pi * a / 3.0) for a in range(3)])
+    lk = (lk * (1.0 + torch.cat([flex, flex])) * torch.tensor([1, 1, 1, 1 + 1e-5, 1 + 1e-5, 1 + 1e-5],
+                                                               dtype=torch.float64, device=lk.device)[:, None])
+    lk = lk.contiguous()
+    store = dataclasses.replace(pix, links=lk)
+    res = tfsc.bank_statistic(grid, store, bank, seg, precision="f32", schedule="wave", order=order, **kw)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    ks = []
+    for _ in range(3):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(st)
+        tfsc.bank_statistic(grid, store, bank, seg, precision="f32", schedule="wave", out=res, order=order, **kw)
+        ev[1].record(st)
+        torch.cuda.synchronize()
+        ks.append(ev[0].elapsed_time(ev[1]))
+    k_ms = float(np.median(ks))
+    s = res.stat.cpu().numpy()
+    idx = sorted(set(np.argsort(-np.nan_to_num(s, nan=-1.0))[:3].tolist()) |
+                 set(np.random.default_rng(31).choice(n, 5, replace=False).tolist()))
+    sub = bank_h.subset(idx)
+    ref = o2.statistic(pix_o, u_o, wm_o, sub, g, layout=otrk.Layout(sub, g), links=lk.cpu().numpy())
+    r = np.abs(s[idx] - ref.stat) / np.maximum(np.abs(ref.stat), 1.0)
+    flags_ok = bool(np.array_equal(res.flags.cpu().numpy()[idx], ref.flags))
+    log(f"links: statistic kernel {k_ms:.2f} ms ({n / (k_ms / 1e3) / 1e6:.3f} M templates/s, {k_ms / k_ms_eq:.3f}x "
+        f"the equal-arm kernel); {len(idx)} sampled templates vs oracle max rel {r.max():.2e}, flags equal {flags_ok}")
+    return {"workload": "same 2-yr grid, store and bank; link light times |p_r - p_s| of the analytic orbit, arms "
+                        "flexing +-1% over a year, reverse links 1e-5 longer",
+            "kernel_ms": round(k_ms, 3), "templates_per_s_kernel": round(n / (k_ms / 1e3), 1),
+            "kernel_over_equal_arm": round(k_ms / k_ms_eq, 4), "store": f"f32 {args.chosen_layout}",
+            "arith": "f32 (track and f k.p FP64)",
             "sampled_parity": {"templates": len(idx), "max_rel_vs_oracle": float(r.max()), "flags_equal": flags_ok}}
 
 

@@ -25,7 +25,7 @@
 extern "C" {
 #endif
 
-#define TFSC_ABI_VERSION 3
+#define TFSC_ABI_VERSION 4
 
 typedef enum {
     TFSC_OK = 0,
@@ -99,7 +99,27 @@ typedef struct {
  * the link transfer and the TDI-1.5 combination keep the equal arm length
  * L = 2.5e9 m.  tfsc_orbit_positions writes the analytic orbit in this
  * layout (a table equal to it gives the same results bit for bit).  Read by
- * every statistic call and the VJP.                                        */
+ * every statistic call and the VJP.
+ *
+ * links: NULL for equal arms.  Else the light times of the six links at the
+ * tranche starts (paper Sec. "Outlook": varying arm lengths and point-ahead
+ * corrections of numerical orbits), links[l Nt + m] in seconds, FP64 [6][Nt],
+ * device memory owned by the caller, positive and finite; rows 0, 1, 2 are
+ * the links 0->1, 1->2, 2->0 and rows 3, 4, 5 the reverse links 1->0, 2->1,
+ * 0->2 (sender->receiver).  Each tranche's geometry is frozen: link s->r is
+ * received at p_r after its light time along the arm direction n_sr, and
+ * the TDI combinations take every path's own delay,
+ *   G_sr = -i pi f L_sr sinc(pi f L_sr (1 - k.n_sr))
+ *          exp(-i pi f (L_sr (1 - k.n_sr) + 2 k.p_r)) (polarisation factor),
+ *   X = (1 - D01 D10)(G20 + D20 G02) - (1 - D02 D20)(G10 + D10 G01), Y, Z
+ *   cyclic, D_sr = exp(-2 pi i f L_sr), A, E, T from X, Y, Z as for equal
+ *   arms (paper Sec. "Implementation details", Eq. (tdi2)).
+ * Six equal times L on a table whose sides are exactly L give the
+ * equal-arm response.  tfsc_link_lengths writes |p_r - p_s| of an orbit.
+ * Read by tfsc_bank_statistic (both schedules; F64 pixels with F64
+ * arithmetic or F32 with F32; no rho; the paper's Fresnel forms); the VJP,
+ * the several-realisation and the harmonics calls return
+ * TFSC_ERR_UNSUPPORTED when it is set.                                     */
 typedef struct {
     tfsc_dtype dtype;
     tfsc_layout layout;
@@ -109,6 +129,7 @@ typedef struct {
     double *tranche_w;
     float *rho;
     const double *orbit;
+    const double *links;
 } tfsc_pixels;
 
 /* Template bank, structure of arrays, n templates, FP64:
@@ -436,6 +457,13 @@ tfsc_status tfsc_bank_statistic_harmonics(const tfsc_grid *grid, const tfsc_pixe
  * out[(3 i + x) Nt + m] (light-seconds, FP64 [3][3][Nt], device), in the
  * layout of tfsc_pixels.orbit (paper Sec. "Implementation details").        */
 tfsc_status tfsc_orbit_positions(const tfsc_grid *grid, double *out, void *stream);
+
+/* The six link light times of an orbit without point-ahead differences,
+ * out[l Nt + m] = |p_r - p_s| (seconds, FP64 [6][Nt], device, rows as
+ * tfsc_pixels.links) of the caller's positions orbit (layout of
+ * tfsc_pixels.orbit) or, for orbit = NULL, of the analytic orbit: the
+ * varying arm lengths of a numerical orbit (paper Sec. "Outlook").         */
+tfsc_status tfsc_link_lengths(const tfsc_grid *grid, const double *orbit, double *out, void *stream);
 
 /* Launch-shape autotuner of the WAVE statistic (paper Sec. "Hardware
  * acceleration and computational cost": large batches per launch): times

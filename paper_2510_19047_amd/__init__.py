@@ -17,7 +17,7 @@ from ._lib import TfscError
 
 __all__ = ["GridSpec", "PixelStore", "BankTensors", "SegmentLayout", "StatResult", "transform", "transform_tf", "segment_layout",
            "bank_statistic", "bank_statistic_multi", "bank_statistic_harmonics", "realisation_stores", "MultiResult",
-           "statistic_vjp", "track", "tile_max", "orbit_positions", "tune_statistic", "TFSCStatistic", "lib",
+           "statistic_vjp", "track", "tile_max", "orbit_positions", "link_lengths", "tune_statistic", "TFSCStatistic", "lib",
            "TfscError", "interleaved_store", "interleave_store", "interleave_stores", "bank_statistic_interleaved"]
 
 _DTYPE = {"f64": _lib.F64, "f32": _lib.F32, "bf16": _lib.BF16, "f16": _lib.F16, "i16": _lib.I16}
@@ -80,10 +80,12 @@ class PixelStore:
     layer_scale: torch.Tensor | None = None  # [C][K] f32 for 16-bit stores (bf16, f16, i16)
     rho: torch.Tensor | None = None   # [K][Nt] f32 per-pixel weight factor of a general per-tranche PSD
     orbit: torch.Tensor | None = None  # [3][3][Nt] f64 spacecraft positions (light-seconds), None = analytic orbit
+    links: torch.Tensor | None = None  # [6][Nt] f64 link light times (seconds), None = equal arms
 
     def c(self) -> _lib.Pixels:
         return _lib.Pixels(_DTYPE[self.dtype], _LAYOUT[self.layout], _ptr(self.pix), _ptr(self.layer_scale),
-                           _ptr(self.inv_asd), _ptr(self.tranche_w), _ptr(self.rho), _ptr(self.orbit))
+                           _ptr(self.inv_asd), _ptr(self.tranche_w), _ptr(self.rho), _ptr(self.orbit),
+                           _ptr(self.links))
 
     @staticmethod
     def from_complex(pix: torch.Tensor, inv_asd: torch.Tensor, tranche_w: torch.Tensor, dtype: str = "f64",
@@ -329,6 +331,16 @@ def orbit_positions(grid: GridSpec, device="cuda") -> torch.Tensor:
     return out
 
 
+def link_lengths(grid: GridSpec, orbit: torch.Tensor | None = None, device="cuda") -> torch.Tensor:
+    """tfsc_link_lengths: |p_r - p_s| of the six links [6][Nt] (seconds, FP64) of ``orbit`` [3][3][Nt] or of the
+    analytic orbit (None)."""
+    L = lib()
+    out = torch.empty((6, grid.n_tranches), dtype=torch.float64, device=device)
+    g = grid.c()
+    _lib.check(L.tfsc_link_lengths(ctypes.byref(g), _ptr(orbit), _ptr(out), _stream()), "tfsc_link_lengths")
+    return out
+
+
 def tune_statistic(grid: GridSpec, pixels: PixelStore, bank: BankTensors, seg: SegmentLayout, tune_key: str,
                    precision: str = "f32", order: torch.Tensor | None = None) -> tuple[int, int]:
     """tfsc_tune_statistic: the library's launch-shape autotuner on a tuning bank; returns (block_waves,
@@ -424,7 +436,7 @@ def interleaved_store(grid: GridSpec, n_real: int, like: PixelStore) -> PixelSto
     return PixelStore(torch.empty((K, Nt, n_real * C, 2), dtype=_TORCH_STORE[like.dtype], device=dev),
                       like.inv_asd, like.tranche_w, like.dtype, "layer_ci",
                       torch.empty((n_real * C, K), dtype=torch.float32, device=dev) if like.dtype == "i16" else None,
-                      None, like.orbit)
+                      None, like.orbit, like.links)
 
 
 def interleave_store(grid: GridSpec, src: PixelStore, n_real: int, r: int, out: PixelStore) -> PixelStore:

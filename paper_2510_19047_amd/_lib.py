@@ -11,7 +11,7 @@ c_int32, c_int64, c_double, c_void_p, c_size_t = ctypes.c_int32, ctypes.c_int64,
 
 TFSC_OK = 0
 TFSC_ERR_SCRATCH = 7
-ABI_VERSION = 3
+ABI_VERSION = 4
 MAX_HARMONICS = 4
 FRESNEL_PAPER, FRESNEL_ACCURATE = 0, 1
 NOALLOC_MAX_TRANCHES = 16384
@@ -29,7 +29,8 @@ class Grid(ctypes.Structure):
 
 class Pixels(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int), ("layout", ctypes.c_int), ("pix", c_void_p), ("layer_scale", c_void_p),
-                ("inv_asd", c_void_p), ("tranche_w", c_void_p), ("rho", c_void_p), ("orbit", c_void_p)]
+                ("inv_asd", c_void_p), ("tranche_w", c_void_p), ("rho", c_void_p), ("orbit", c_void_p),
+                ("links", c_void_p)]
 
 
 class Bank(ctypes.Structure):
@@ -51,7 +52,7 @@ EXPORTS = ("tfsc_abi_version", "tfsc_status_string", "tfsc_workspace_bytes", "tf
            "tfsc_statistic_vjp",
            "tfsc_follow_up_step",
            "tfsc_processing_order", "tfsc_tile_max", "tfsc_track", "tfsc_bank_statistic_harmonics",
-           "tfsc_orbit_positions", "tfsc_tune_statistic", "tfsc_interleave_store")
+           "tfsc_orbit_positions", "tfsc_link_lengths", "tfsc_tune_statistic", "tfsc_interleave_store")
 
 _lib = None
 
@@ -112,6 +113,8 @@ def load(path: str = LIB_PATH):
                                                 c_void_p, c_void_p, c_size_t, c_void_p]
     L.tfsc_orbit_positions.restype = ctypes.c_int
     L.tfsc_orbit_positions.argtypes = [P(Grid), c_void_p, c_void_p]
+    L.tfsc_link_lengths.restype = ctypes.c_int
+    L.tfsc_link_lengths.argtypes = [P(Grid), c_void_p, c_void_p, c_void_p]
     L.tfsc_interleave_store.restype = ctypes.c_int
     L.tfsc_interleave_store.argtypes = [P(Grid), P(Pixels), c_int32, c_int32, P(Pixels), c_void_p]
     L.tfsc_tune_statistic.restype = ctypes.c_int

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtfsc.so")
 SOURCES = ["tfsc_api.hip", "tfsc_stat.hip", "tfsc_fresnel.hip", "tfsc_harm.hip", "tfsc_transform.hip", "tfsc_vjp.hip",
-           "tfsc_follow.hip", "tfsc_tiles.hip", "tfsc_interleave.hip"]
+           "tfsc_follow.hip", "tfsc_tiles.hip", "tfsc_interleave.hip", "tfsc_links.hip"]
 HEADERS = ["tfsc_device.hpp", "tfsc_kernels.hpp", "tfsc_stat_common.hpp", os.path.join("..", "..", "include", "tfsc.h")]
 ARCH = os.environ.get("TFSC_OFFLOAD_ARCH", "gfx950")
 

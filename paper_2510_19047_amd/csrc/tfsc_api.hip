@@ -186,6 +186,7 @@ tfsc::StatLaunch stat_launch(const tfsc_grid *grid, const tfsc_pixels *pix, cons
     L.inv_asd = pix->inv_asd;
     L.tranche_w = pix->tranche_w;
     L.rho = pix->rho;
+    L.links = pix->links;
     L.geo = reinterpret_cast<const double *>(ws);
     L.n = bank->n;
     L.mc = bank->mc;
@@ -287,6 +288,10 @@ tfsc_status tfsc_bank_statistic(const tfsc_grid *grid, const tfsc_pixels *pix, c
         (pix->rho || !((pix->dtype == TFSC_F64 && r.precision == TFSC_F64) ||
                        (pix->dtype == TFSC_F32 && r.precision == TFSC_F32))))
         return TFSC_ERR_UNSUPPORTED;
+    if (pix->links && (pix->rho || r.fresnel != TFSC_FRESNEL_PAPER ||
+                       !((pix->dtype == TFSC_F64 && r.precision == TFSC_F64) ||
+                         (pix->dtype == TFSC_F32 && r.precision == TFSC_F32))))
+        return TFSC_ERR_UNSUPPORTED;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     if (bank->n == 0) return TFSC_OK;
     tfsc::StatLaunch L = stat_launch(grid, pix, bank, seg, r, ws);
@@ -297,6 +302,7 @@ tfsc_status tfsc_bank_statistic(const tfsc_grid *grid, const tfsc_pixels *pix, c
     L.flags = flags;
     L.n_active = n_active;
     if (r.fresnel == TFSC_FRESNEL_ACCURATE) return hip_status(tfsc::launch_statistic_accurate(L, st));
+    if (pix->links) return hip_status(tfsc::launch_statistic_links(L, st));
     return hip_status(tfsc::launch_statistic(L, st));
 }
 
@@ -329,7 +335,7 @@ tfsc_status tfsc_bank_statistic_multi(const tfsc_grid *grid, const tfsc_pixels *
     Resolved r;
     if ((s = resolve_options(opt, pix, r)) != TFSC_OK) return s;
     if (r.schedule != TFSC_SCHED_WAVE || pix->layout == TFSC_TRANCHE_MAJOR || grid->n_channels == 3 ||
-        r.fresnel != TFSC_FRESNEL_PAPER)
+        r.fresnel != TFSC_FRESNEL_PAPER || pix->links)
         return TFSC_ERR_UNSUPPORTED;
     const bool interleaved = real_stride == 0;
     if (!(pix->dtype == TFSC_F32 && r.precision == TFSC_F32) && !(pix->dtype == TFSC_F64 && r.precision == TFSC_F64) &&
@@ -393,7 +399,7 @@ tfsc_status tfsc_statistic_vjp(const tfsc_grid *grid, const tfsc_pixels *pix, co
     // Either arithmetic reads every pixel type and layout (no pixel check against the precision).
     Resolved r;
     if ((s = resolve_options(opt, nullptr, r)) != TFSC_OK) return s;
-    if (r.fresnel != TFSC_FRESNEL_PAPER) return TFSC_ERR_UNSUPPORTED;
+    if (r.fresnel != TFSC_FRESNEL_PAPER || pix->links) return TFSC_ERR_UNSUPPORTED;
     if (bank->n > 0 && (!seg_zn || !g_params || (!g_stat && !g_seg))) return TFSC_ERR_ARG;
     if (!ws || ws_bytes < stat_ws_bytes(grid, bank->n, bank->ln_mc != nullptr)) return TFSC_ERR_WORKSPACE;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -547,6 +553,14 @@ tfsc_status tfsc_orbit_positions(const tfsc_grid *grid, double *out, void *strea
                                                    reinterpret_cast<hipStream_t>(stream)));
 }
 
+tfsc_status tfsc_link_lengths(const tfsc_grid *grid, const double *orbit, double *out, void *stream) {
+    tfsc_status s;
+    if ((s = check_grid(grid)) != TFSC_OK) return s;
+    if (!out) return TFSC_ERR_ARG;
+    return hip_status(tfsc::launch_link_lengths(grid->n_tranches, (double)grid->tranche_len * grid->dt, orbit, out,
+                                                reinterpret_cast<hipStream_t>(stream)));
+}
+
 tfsc_status tfsc_bank_statistic_harmonics(const tfsc_grid *grid, const tfsc_pixels *pix, const tfsc_bank *bank,
                                           const tfsc_segments *seg, const tfsc_options *opt, int32_t n_harm,
                                           const int32_t *harmonics, const double *amp, double *seg_terms,
@@ -565,7 +579,8 @@ tfsc_status tfsc_bank_statistic_harmonics(const tfsc_grid *grid, const tfsc_pixe
     }
     Resolved r;
     if ((s = resolve_options(opt, pix, r)) != TFSC_OK) return s;
-    if (r.schedule != TFSC_SCHED_WAVE || r.fresnel != TFSC_FRESNEL_PAPER || pix->rho) return TFSC_ERR_UNSUPPORTED;
+    if (r.schedule != TFSC_SCHED_WAVE || r.fresnel != TFSC_FRESNEL_PAPER || pix->rho || pix->links)
+        return TFSC_ERR_UNSUPPORTED;
     if (!((pix->dtype == TFSC_F64 && r.precision == TFSC_F64) || (pix->dtype == TFSC_F32 && r.precision == TFSC_F32)))
         return TFSC_ERR_DTYPE;
     if (bank->n > 0 && (!seg_terms || !stat || !flags || !amp)) return TFSC_ERR_ARG;

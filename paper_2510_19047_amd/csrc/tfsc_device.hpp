@@ -46,6 +46,23 @@ __device__ __forceinline__ double div_rn(double a, double b, double yb) {
     return fma(r, yb, q);
 }
 
+// sqrt(x), correctly rounded, for a positive normal x >= 2^-767 (the track's q and its roots): Goldschmidt's
+// iteration from the hardware reciprocal square root y ~ 1/sqrt(x) (g -> sqrt(x), h -> 1/(2 sqrt(x))), one
+// refinement of both, then two corrections of g by the exact residual x - g^2.  This is the sequence the
+// compiler emits for sqrt(double) without its rescaling of tiny inputs and its selects for 0 and infinity,
+// so on these inputs it returns the same bits with eight fewer instructions.
+__device__ __forceinline__ double sqrt_pos(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-h, g, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    double d = fma(-g, g, x);
+    g = fma(d, h, g);
+    d = fma(-g, g, x);
+    return fma(d, h, g);
+}
+
 __device__ __forceinline__ bool params_valid(double mc, double eta, double f0, double ct, double ci) {
     if (!(mc > 0.0) || !(eta >= 0.01) || !(eta <= 0.25) || !(f0 > 0.0)) return false;
     if (!(fabs(ct) <= 1.0) || !(fabs(ci) <= 1.0)) return false;
@@ -95,15 +112,15 @@ __device__ inline void track_init(Track &T, double mc, double eta, double f0) {
 }
 
 // Phase Phi (rad, phi_c = 0), GW frequency f and its derivative at time t < t_c, in the
-// operation order of the formulas: q = eta (t_c - t) / (5M), theta = 1 / q^(1/8) (three square
-// roots), f = (theta^3 / (8 pi M)) P_f, fdot = ((theta^2 / (8 pi M)) P_f') (eta theta^9 / (40M)),
+// operation order of the formulas: q = eta (t_c - t) / (5M), theta = 1 / q^(1/8) (three correctly
+// rounded square roots, sqrt_pos: every caller has t_c - t >= dT, so q is a normal number far above 2^-767), f = (theta^3 / (8 pi M)) P_f, fdot = ((theta^2 / (8 pi M)) P_f') (eta theta^9 / (40M)),
 // Phi = -(2 theta^-5 P_phi) / eta with theta^-5 = 1 / (theta^4 theta).  Divisions by the
 // per-template constants 5M, 8 pi M, 40M and eta are formed by div_rn (the same correctly
 // rounded quotients); 1/s and 1/(theta^4 theta) are full divisions.
 __device__ inline void track_at(const Track &T, double t, double &Phi, double &f, double &fdot) {
     double tau = T.tc - t;
     double q = div_rn(T.eta * tau, T.M5, T.r5M);
-    double s = sqrt(sqrt(sqrt(q)));
+    double s = sqrt_pos(sqrt_pos(sqrt_pos(q)));
     double th = 1.0 / s;
     double th2 = th * th, th3 = th2 * th, th4 = th2 * th2;
     double Pf = ((1.0 + T.a2 * th2) + T.a3 * th3) + T.a4 * th4;
@@ -256,15 +273,23 @@ __device__ __forceinline__ R sinc_of(R x) {
 struct GeoView {
     __amdgpu_buffer_rsrc_t g64, g32;
     uint32_t row64, row32;  // bytes per row
+    __amdgpu_buffer_rsrc_t lk;  // a caller's link light times [6][Nt] (FP64, rows of row64 bytes), if any
 };
 
-__device__ __forceinline__ GeoView geo_view(const double *geo, const float *geo32, int Nt) {
+__device__ __forceinline__ GeoView geo_view(const double *geo, const float *geo32, int Nt,
+                                            const double *links = nullptr) {
     GeoView v;
     v.row64 = (uint32_t)Nt * 8u;
     v.row32 = (uint32_t)Nt * 4u;
     v.g64 = __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(geo), (short)0, (int)(v.row64 * kGeoRows), 0x00020000);
     v.g32 = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(geo32), (short)0, (int)(v.row32 * 9u), 0x00020000);
+    v.lk = __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(links), (short)0, links ? (int)(v.row64 * 6u) : 0,
+                                             0x00020000);
     return v;
+}
+
+__device__ __forceinline__ double geo_link(const GeoView &v, int m, int l) {  // light time of link row l
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(v.lk, (uint32_t)m * 8u, (uint32_t)l * v.row64, 0));
 }
 
 __device__ __forceinline__ double geo_d(const GeoView &v, int m, int r) {
@@ -340,6 +365,68 @@ __device__ inline void transfer_ae(const Sky<R> &S, const GeoView &gv, int m, do
         // the third channel T = (X + Y + Z) / sqrt3, the null channel of the equal-arm constellation
         const R is3 = (R)0.57735026918962576451;
         *TT = cmul(cscale(D, sp * is3), cadd(cadd(Xp, Yp), Zp));
+    }
+}
+
+// T_A, T_E (and T) with the six link light times of the tranche from the caller's table (unequal arms; the
+// two directions of an arm may differ, as with point-ahead), the geometry frozen over the tranche.  Table rows
+// 0..2 are the links s = a -> r = a + 1 of arms a = 0..2, rows 3..5 their reverse links.  Link s -> r is
+// received at p_r after travelling L_sr along the arm direction n_sr, so it left from p_r - L_sr n_sr:
+//   G_sr = -i pi f L_sr sinc(pi f L_sr (1 - k.n_sr)) e^{-i pi f (L_sr (1 - k.n_sr) + 2 k.p_r)} amp_a,
+// and first-generation TDI with each path's delay D_sr = e^{-2 pi i f L_sr}:
+//   X = (1 - D01 D10)(G20 + D20 G02) - (1 - D02 D20)(G10 + D10 G01), Y and Z cyclic.
+// The round trip of arm a, l_a = L_sr + L_rs, enters as 1 - D_sr D_rs = 2 i sin(pi f l_a) e^{-i pi f l_a}
+// (the sine of an argument folded into [-1/4, 1/4] revolutions, as for equal arms); with the common factor
+// -i pi f it is the real 2 pi f sin(pi f l_a) times e^{-i pi f l_a}.  f k.p_r reaches tens of revolutions and
+// is reduced in FP64; the link terms below a revolution are formed in R.
+template <class R, bool WITH_T = false>
+__device__ inline void transfer_links(const Sky<R> &S, const GeoView &gv, int m, double f, cx<R> &TA, cx<R> &TE,
+                                      cx<R> *TT = nullptr) {
+#pragma clang fp contract(fast)
+    R rp[3];  // -f k.p_i in revolutions, reduced
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double kp =
+            S.kd[0] * geo_d(gv, m, 3 * i) + S.kd[1] * geo_d(gv, m, 3 * i + 1) + S.kd[2] * geo_d(gv, m, 3 * i + 2);
+        rp[i] = (R)frac_rev(-f * kp);
+    }
+    const R pf = (R)(kPi * f), hf = (R)(-0.5 * f), rf = (R)f;
+    cx<R> Gd[3], Gr[3], F[3], Dd[3], Dr[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int s = a, r = (a + 1) % 3;
+        const double Lfd = geo_link(gv, m, a), Lbd = geo_link(gv, m, 3 + a);
+        const R Lf = (R)Lfd, Lb = (R)Lbd;
+        R n0 = geo_arm<R>(gv, m, 3 * a + 0);
+        R n1 = geo_arm<R>(gv, m, 3 * a + 1);
+        R n2 = geo_arm<R>(gv, m, 3 * a + 2);
+        R kn = S.k[0] * n0 + S.k[1] * n1 + S.k[2] * n2;
+        R nu = S.u[0] * n0 + S.u[1] * n1 + S.u[2] * n2;
+        R nv = S.v[0] * n0 + S.v[1] * n1 + S.v[2] * n2;
+        cx<R> amp = {nu * nu - nv * nv, S.q * (nu * nv)};
+        const R om = (R)1 - kn, op = (R)1 + kn;  // 1 - k.n of the forward and of the reverse link
+        const cx<R> Ef = expi_rev(rp[r] + hf * Lf * om);
+        const cx<R> Eb = expi_rev(rp[s] + hf * Lb * op);
+        Gd[a] = cscale(cmul(Ef, amp), Lf * sinc_of(pf * Lf * om));
+        Gr[a] = cscale(cmul(Eb, amp), Lb * sinc_of(pf * Lb * op));
+        Dd[a] = expi_rev(-(rf * Lf));
+        Dr[a] = expi_rev(-(rf * Lb));
+        const double rr = frac_rev(0.5 * f * (Lfd + Lbd));
+        const double rfold = rr > 0.25 ? 0.5 - rr : (rr < -0.25 ? -0.5 - rr : rr);
+        F[a] = cscale(expi_rev((R)(-rr)), (R)(kTwoPi * f) * sin_rev_accurate((R)rfold));
+    }
+    // 0-based spacecraft: arm 0 = (0,1), arm 1 = (1,2), arm 2 = (2,0)
+    const cx<R> G01 = Gd[0], G10 = Gr[0], G12 = Gd[1], G21 = Gr[1], G20 = Gd[2], G02 = Gr[2];
+    const cx<R> D01 = Dd[0], D10 = Dr[0], D12 = Dd[1], D21 = Dr[1], D20 = Dd[2], D02 = Dr[2];
+    const cx<R> X = csub(cmul(F[0], cadd(G20, cmul(D20, G02))), cmul(F[2], cadd(G10, cmul(D10, G01))));
+    const cx<R> Y = csub(cmul(F[1], cadd(G01, cmul(D01, G10))), cmul(F[0], cadd(G21, cmul(D21, G12))));
+    const cx<R> Z = csub(cmul(F[2], cadd(G12, cmul(D12, G21))), cmul(F[1], cadd(G02, cmul(D02, G20))));
+    const R is2 = (R)0.70710678118654752440, is6 = (R)0.40824829046386301637;
+    TA = cscale(csub(Z, X), is2);
+    TE = cscale(cadd(csub(X, cscale(Y, (R)2)), Z), is6);
+    if constexpr (WITH_T) {
+        const R is3 = (R)0.57735026918962576451;
+        *TT = cscale(cadd(cadd(X, Y), Z), is3);
     }
 }
 

@@ -40,6 +40,7 @@ struct StatLaunch {
     const float *layer_scale;
     const double *inv_asd, *tranche_w, *geo;
     const float *rho;       // [K][Nt] per-pixel weight factor, NULL for a separable PSD
+    const double *links;    // [6][Nt] link light times (unequal arms), NULL for equal arms
     const double *u_scale;  // device scalar written by launch_weight_scale
     int64_t n;
     const double *mc, *eta, *f0, *ct, *phi, *psi, *ci;
@@ -111,6 +112,7 @@ struct TransformLaunch {
 hipError_t launch_layout(const LayoutLaunch &L, hipStream_t st);
 hipError_t launch_geometry(int Nt, double dT, const double *orbit, double *geo, hipStream_t st);
 hipError_t launch_orbit_positions(int Nt, double dT, double *out, hipStream_t st);
+hipError_t launch_link_lengths(int Nt, double dT, const double *orbit, double *out, hipStream_t st);
 hipError_t launch_statistic_interleaved(const StatLaunch &L, hipStream_t st);
 hipError_t launch_interleave(int64_t cells, int C, int K, int NR, int r, int elem_bytes, const void *src,
                              const float *src_scale, void *dst, float *dst_scale, hipStream_t st);
@@ -118,6 +120,7 @@ hipError_t launch_exp_mc(int64_t n, const double *ln_mc, double *mc, hipStream_t
 hipError_t launch_weight_scale(int K, const double *inv_asd, double *scale_out, hipStream_t st);
 hipError_t launch_statistic(const StatLaunch &L, hipStream_t st);
 hipError_t launch_statistic_accurate(const StatLaunch &L, hipStream_t st);
+hipError_t launch_statistic_links(const StatLaunch &L, hipStream_t st);
 constexpr int kMaxHarmonics = 4;
 hipError_t launch_statistic_harmonics(const StatLaunch &L, int n_harm, const int *harm, const double *amp,
                                       hipStream_t st);

@@ -225,6 +225,32 @@ __global__ void k_orbit_positions(int Nt, double dT, double *__restrict__ out) {
         for (int x = 0; x < 3; ++x) out[(size_t)(3 * i + x) * Nt + m] = p[i][x];
 }
 
+// Link light times without point-ahead: out[l Nt + m] = |p_r - p_s| of link row l (rows 0..2: s = a -> r = a + 1 of arm a; rows 3..5 the reverse
+// links) at tranche m, from the caller's positions orbit[(3 i + x) Nt + m] or the analytic orbit.
+__global__ void k_link_lengths(int Nt, double dT, const double *__restrict__ orbit, double *__restrict__ out) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= Nt) return;
+    double p[3][3];
+    if (orbit) {
+        for (int i = 0; i < 3; ++i)
+            for (int x = 0; x < 3; ++x) p[i][x] = orbit[(size_t)(3 * i + x) * Nt + m];
+    } else {
+        analytic_positions((double)m * dT, p);
+    }
+    for (int a = 0; a < 3; ++a) {
+        const int s = a, r = (a + 1) % 3;
+        const double dx = p[r][0] - p[s][0], dy = p[r][1] - p[s][1], dz = p[r][2] - p[s][2];
+        const double len = sqrt(dx * dx + dy * dy + dz * dz);
+        out[(size_t)a * Nt + m] = len;
+        out[(size_t)(3 + a) * Nt + m] = len;
+    }
+}
+
+hipError_t launch_link_lengths(int Nt, double dT, const double *orbit, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_link_lengths, dim3((Nt + 127) / 128), dim3(128), 0, st, Nt, dT, orbit, out);
+    return hipGetLastError();
+}
+
 // Exact power-of-two normalisation of the template weights: scale = 2^-e with e the
 // binary exponent of max_k u_k, so that max_k u_k * scale lies in [1/2, 1).  Upsilon is
 // invariant to it; it keeps |h u|^2 inside the FP32 range (u_k ~ 1e20 in strain units).

@@ -26,6 +26,7 @@ struct StatArgs {
     const double *u_scale;  // [1], see k_weight_scale
     const float *rho;       // [K][Nt] per-pixel weight factor (general per-tranche PSD), else NULL
     uint32_t rho_bytes;
+    const double *links;    // [6][Nt] link light times (unequal arms), else NULL
     int64_t n;
     const double *mc, *eta, *f0, *ct, *phi, *psi, *ci;
     const int32_t *nseg;
@@ -145,13 +146,17 @@ __device__ __forceinline__ void tranche_bins(const StatArgs &a, const TrancheSpe
     }
 }
 
-// Tranche contribution z_m = w_m sum_c T_c P_c, N_m = w_m^2 (sum_c |T_c|^2) Q.
-template <int C, class R>
+// Tranche contribution z_m = w_m sum_c T_c P_c, N_m = w_m^2 (sum_c |T_c|^2) Q.  LK: the response with the
+// caller's link light times (unequal arms).
+template <int C, class R, bool LK = false>
 __device__ __forceinline__ void tranche_combine(const Sky<R> &S, const GeoView &gv, int m, double f, R wm,
                                                 const cx<R> (&P)[C], R Q, R &zr, R &zi, R &nn) {
 #pragma clang fp contract(fast)
     cx<R> TA, TE, TT;
-    transfer_ae<R, (C == 3)>(S, gv, m, f, TA, TE, &TT);
+    if constexpr (LK)
+        transfer_links<R, (C == 3)>(S, gv, m, f, TA, TE, &TT);
+    else
+        transfer_ae<R, (C == 3)>(S, gv, m, f, TA, TE, &TT);
     cx<R> z = cmul(TA, P[0]);
     R tt = TA.re * TA.re + TA.im * TA.im;
     if constexpr (C >= 2) {
@@ -583,7 +588,7 @@ __device__ __forceinline__ void wave_uniform(Sky<R> &S) {
 
 // ------------------------------------------------------------------ THREAD schedule
 // The body of the thread-per-template kernels (k_stat_thread; the accurate-Fresnel variant).
-template <int C, class R, class PixT, int LAYOUT, bool RHO, int FR>
+template <int C, class R, class PixT, int LAYOUT, bool RHO, int FR, bool LK = false>
 __device__ __forceinline__ void stat_thread_body(const StatArgs &a) {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= a.n) return;
@@ -605,7 +610,7 @@ __device__ __forceinline__ void stat_thread_body(const StatArgs &a) {
     track_init(T, a.mc[i], a.eta[i], a.f0[i]);
     Sky<R> S;
     sky_init(S, a.ct[i], a.phi[i], a.psi[i], a.ci[i]);
-    const GeoView gv = geo_view(a.geo, a.geo32, a.Nt);
+    const GeoView gv = geo_view(a.geo, a.geo32, a.Nt, LK ? a.links : nullptr);
     const double u_mul = a.u_scale[0];
     int m = 0, n_act = 0;
     for (; m < a.Nt; ++m) {
@@ -626,7 +631,7 @@ __device__ __forceinline__ void stat_thread_body(const StatArgs &a) {
         R Q;
         tranche_bins<C, R, PixT, LAYOUT, double, RHO, FR>(a, ts, kc, m, a.inv_asd, u_mul, a.layer_scale, P, Q);
         R zr, zi, nn;
-        tranche_combine<C, R>(S, gv, m, f, (R)wmd, P, Q, zr, zi, nn);
+        tranche_combine<C, R, LK>(S, gv, m, f, (R)wmd, P, Q, zr, zi, nn);
         acc.zr += zr;
         acc.zi += zi;
         acc.N += nn;
@@ -640,8 +645,8 @@ __device__ __forceinline__ void stat_thread_body(const StatArgs &a) {
 }
 
 // The body of the wave-per-template kernels (k_stat_wave; the accurate-Fresnel variant, which takes the
-// general form on all 21 bins).
-template <int C, class R, class PixT, int LAYOUT, bool RHO, int FR>
+// general form on all 21 bins; the unequal-arm variant, LK).
+template <int C, class R, class PixT, int LAYOUT, bool RHO, int FR, bool LK = false>
 __device__ __forceinline__ void stat_wave_body(const StatArgs &a) {
     // Zero-padded template weights u_pad[k + 10] = u_k for 1 <= k <= M/2 - 1 (else 0), and
     // the 16-bit layer scales, staged in LDS once per block.
@@ -663,7 +668,7 @@ __device__ __forceinline__ void stat_wave_body(const StatArgs &a) {
     __syncthreads();
     const __amdgpu_buffer_rsrc_t rsrc = pix_rsrc(a.pix, a.pix_bytes);
     const __amdgpu_buffer_rsrc_t rho_rsrc = pix_rsrc(RHO ? a.rho : a.pix, RHO ? a.rho_bytes : 0u);
-    const GeoView gv = geo_view(a.geo, a.geo32, a.Nt);
+    const GeoView gv = geo_view(a.geo, a.geo32, a.Nt, LK ? a.links : nullptr);
 
     const int lane = threadIdx.x & 63;
     for (;;) {
@@ -744,7 +749,7 @@ __device__ __forceinline__ void stat_wave_body(const StatArgs &a) {
                 else
                     wave_tranche_bins<C, R, PixT, LAYOUT, RHO, FR>(ts, kc, m, a.Nt, a.K, rsrc, rho_rsrc, u_pad, sc_pad,
                                                                jA, jB, P, Q);
-                tranche_combine<C, R>(S, gv, m, f, (R)wmd, P, Q, zr, zi, nn);
+                tranche_combine<C, R, LK>(S, gv, m, f, (R)wmd, P, Q, zr, zi, nn);
             }
             // segmented reduction over the lanes of this chunk
             const int last = min(min(m0 + 63, lim - 1), a.Nt - 1);
@@ -798,6 +803,7 @@ inline StatArgs make_args(const StatLaunch &L) {
     a.geo32 = geo32_of(L.geo, L.Nt);
     a.u_scale = L.u_scale;
     a.rho = L.rho;
+    a.links = L.links;
     {
         const uint64_t rb = (uint64_t)a.K * (uint64_t)a.Nt * 4u;
         a.rho_bytes = L.rho ? (rb > 0xffffffffull ? 0xffffffffu : (uint32_t)rb) : 0u;

@@ -31,7 +31,7 @@ def test_every_declared_function_is_exported(L):
 
 
 def test_version_and_status_strings(L):
-    assert L.tfsc_abi_version() == 3
+    assert L.tfsc_abi_version() == 4
     for s in range(8):
         assert len(L.tfsc_status_string(s)) > 0
 
@@ -206,3 +206,36 @@ def test_abi3_argument_errors(L):
     bw, gpc = ctypes.c_int32(), ctypes.c_int32()
     assert L.tfsc_tune_statistic(ctypes.byref(g), ctypes.byref(pix), ctypes.byref(bank), ctypes.byref(seg), None,
                                  None, p, p, p, p, ws, None, ctypes.byref(bw), ctypes.byref(gpc)) == 1
+
+
+def test_links_argument_errors(L):
+    """Host-side checks of the link light-time table (tfsc_pixels.links): the statistic takes it with F64 or F32
+    pixels in the same arithmetic, no rho and the paper's Fresnel forms; the VJP, the several-realisation and the
+    harmonics calls refuse it; tfsc_link_lengths needs its output (no device call is made)."""
+    from paper_2510_19047_amd import _lib
+    g = _grid()
+    one = (ctypes.c_double * 4)()
+    p = ctypes.cast(one, ctypes.c_void_p)
+    seg = _lib.Segments(0, p, p)
+    bank = _lib.Bank(1, p, p, p, p, p, p, p, None)
+    ws = 1 << 30
+
+    def stat(px, o):
+        return L.tfsc_bank_statistic(ctypes.byref(g), ctypes.byref(px), ctypes.byref(bank), ctypes.byref(seg),
+                                     ctypes.byref(o), p, p, None, p, None, p, ws, None)
+
+    f32 = _lib.Options(1, 1, 0, 0, None, 0, None)
+    lk = _lib.Pixels(1, 2, p, None, p, p, None, None, p)
+    assert stat(_lib.Pixels(1, 2, p, None, p, p, p, None, p), f32) == 5  # with rho
+    assert stat(lk, _lib.Options(1, 1, 0, 0, None, 1, None)) == 5  # accurate Fresnel mode
+    assert stat(lk, _lib.Options(0, 1, 0, 0, None, 0, None)) == 5  # F32 pixels, F64 arithmetic
+    assert stat(_lib.Pixels(4, 2, p, p, p, p, None, None, p), f32) == 5  # int16 store
+    assert L.tfsc_statistic_vjp(ctypes.byref(g), ctypes.byref(lk), ctypes.byref(bank), ctypes.byref(seg),
+                                ctypes.byref(f32), p, p, None, p, p, ws, None) == 5
+    assert L.tfsc_bank_statistic_multi(ctypes.byref(g), ctypes.byref(lk), 2, 0, 0, ctypes.byref(bank),
+                                       ctypes.byref(seg), ctypes.byref(f32), 0, p, p, p, None, p, ws, None) == 5
+    arr = (ctypes.c_int32 * 1)(2)
+    assert L.tfsc_bank_statistic_harmonics(ctypes.byref(g), ctypes.byref(lk), ctypes.byref(bank), ctypes.byref(seg),
+                                           ctypes.byref(f32), 1, arr, p, p, p, None, p, None, p, ws, None) == 5
+    assert L.tfsc_link_lengths(ctypes.byref(g), None, None, None) == 1
+    assert L.tfsc_link_lengths(ctypes.byref(_grid(n_tranches=0)), None, p, None) != 0
