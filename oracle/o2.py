@@ -43,7 +43,7 @@ def _bins(f_m: torch.Tensor, dT: float, M: int):
 
 
 def template_pixels(mc, eta, f0, cos_theta, phi, psi, cos_iota, m_end: int, grid, u, wm,
-                    exact_fresnel: bool = False, weight_tf=None, orbit=None, links=None):
+                    exact_fresnel: bool = False, weight_tf=None, orbit=None, links=None, generation: int = 1):
     """Whitened template pixels of one template on its active tranches.
 
     Parameters may be 0-d tensors carrying autograd.  Returns (m, kc, k, valid, Y)
@@ -54,7 +54,8 @@ def template_pixels(mc, eta, f0, cos_theta, phi, psi, cos_iota, m_end: int, grid
     orbit: optional spacecraft positions [3][3][Nt] at the tranche starts (light-seconds), the caller's orbit
     in place of the analytic one.
     links: optional link light times [6][Nt] at the tranche starts (light-seconds, rows as
-    ``response.LINK_ROWS``): the unequal-arm response in place of the equal-arm one.
+    ``response.LINK_ROWS``): the unequal-arm response in place of the equal-arm one; ``generation`` 2 forms
+    it in the second TDI generation.
     """
     dT = float(grid.tranche_dur)
     M = grid.tranche_len
@@ -71,7 +72,7 @@ def template_pixels(mc, eta, f0, cos_theta, phi, psi, cos_iota, m_end: int, grid
     lk = None
     if links is not None:
         lk = torch.as_tensor(np.asarray(links), dtype=torch.float64)[:, m].T
-    T = list(transfer_aet(tm, f, cos_theta, phi, psi, cos_iota, pos, lk))[: grid.n_channels]
+    T = list(transfer_aet(tm, f, cos_theta, phi, psi, cos_iota, pos, lk, generation))[: grid.n_channels]
     if weight_tf is not None:
         wt = torch.as_tensor(np.asarray(weight_tf), dtype=torch.float64)
         wkm = wt[k.clamp(0, M // 2), m[:, None]]
@@ -116,7 +117,7 @@ class Result:
 
 
 def statistic(pix, u, wm, bank, grid, layout: trk.Layout | None = None, exact_fresnel: bool = False,
-              idx=None, weight_tf=None, orbit=None, links=None) -> Result:
+              idx=None, weight_tf=None, orbit=None, links=None, generation: int = 1) -> Result:
     """Upsilon and its per-segment terms for every template of ``bank``.
 
     pix: complex [C][K][Nt] whitened data pixels (numpy), u: [K], wm: [Nt].
@@ -124,7 +125,7 @@ def statistic(pix, u, wm, bank, grid, layout: trk.Layout | None = None, exact_fr
     weight_tf: optional per-pixel template weights [K][Nt] in place of u_k w_m
     (``transform.transform_tf``); u and wm must then be None.
     orbit: optional spacecraft positions [3][3][Nt] at the tranche starts (a caller's orbit).
-    links: optional link light times [6][Nt] at the tranche starts (unequal arms).
+    links: optional link light times [6][Nt] at the tranche starts (unequal arms); generation: TDI 1 or 2.
     """
     if weight_tf is not None and (u is not None or wm is not None):
         raise ValueError("give either (u, wm) or weight_tf")
@@ -142,7 +143,8 @@ def statistic(pix, u, wm, bank, grid, layout: trk.Layout | None = None, exact_fr
                 continue
             m, kc, k, valid, Y = template_pixels(
                 bank.mc[i], bank.eta[i], bank.f0[i], bank.cos_theta[i], bank.phi[i], bank.psi[i],
-                bank.cos_iota[i], layout.m_end[i], grid, u, wm, exact_fresnel, weight_tf, orbit, links)
+                bank.cos_iota[i], layout.m_end[i], grid, u, wm, exact_fresnel, weight_tf, orbit, links,
+                generation)
             z, N = _segment_sums(pix_t, m, k, valid, Y, layout.nseg[i], grid.n_tranches)
             ups = _upsilon(z, N)
             o = layout.seg_offset[i]

@@ -41,6 +41,13 @@ the reconstruction used here is the standard one and is stated in full:
     X = (1 - D12 D21)(y31 + D31 y13) - (1 - D13 D31)(y21 + D21 y12), Y, Z cyclic.
   With six equal light times L on a table whose sides are exactly L this is
   the equal-arm form above (p_s = p_r - L n).
+* Second-generation TDI on the same frozen geometry (the data the paper
+  analyses are TDI-2): with the arms static over the tranche the
+  second-generation Michelson combination is the first-generation one
+  minus itself delayed by both round trips, X2(t) = X(t) - X(t - R12 - R13)
+  (R_ab = L_ab + L_ba), so X2 = (1 - D_R12 D_R13) X; Y, Z cyclic.  For equal
+  arms the factor 1 - D^4 is common to X, Y, Z; for unequal arms it differs
+  between them and A, E, T are formed from the factored X2, Y2, Z2.
 """
 from __future__ import annotations
 
@@ -124,33 +131,37 @@ def transfer_ae(t, f, cos_theta, phi, psi, cos_iota):
     return TA, TE
 
 
-def transfer_aet(t, f, cos_theta, phi, psi, cos_iota, pos=None, links=None):
+def transfer_aet(t, f, cos_theta, phi, psi, cos_iota, pos=None, links=None, generation: int = 1):
     """(T_A, T_E, T_T): the third channel T = (X + Y + Z) / sqrt 3 completes A and E to an orthonormal
     combination of X, Y, Z (so |T_A|^2 + |T_E|^2 + |T_T|^2 = |T_X|^2 + |T_Y|^2 + |T_Z|^2).  ``pos``: spacecraft
     positions [..., 3, 3] at the times t (a caller's orbit), None for the analytic orbit; ``links``: the six
-    link light times [..., 6] at the times t (unequal arms), None for equal arms."""
-    TX, TY, TZ = transfer_xyz(t, f, cos_theta, phi, psi, cos_iota, pos, links)
+    link light times [..., 6] at the times t (unequal arms), None for equal arms; ``generation``: TDI 1 or 2
+    (2 with a link table)."""
+    TX, TY, TZ = transfer_xyz(t, f, cos_theta, phi, psi, cos_iota, pos, links, generation)
     TA = (TZ - TX) / math.sqrt(2.0)
     TE = (TX - 2.0 * TY + TZ) / math.sqrt(6.0)
     TT = (TX + TY + TZ) / math.sqrt(3.0)
     return TA, TE, TT
 
 
-def transfer_xyz(t, f, cos_theta, phi, psi, cos_iota, pos=None, links=None):
+def transfer_xyz(t, f, cos_theta, phi, psi, cos_iota, pos=None, links=None, generation: int = 1):
     """Per-tranche transfer of the Michelson combinations (T_X, T_Y, T_Z) that A, E and T are formed from.
 
     ``pos``: spacecraft positions [..., 3 spacecraft, 3 coordinates] (light-seconds) at the times t, for an
     orbit other than the analytic one (Sec. "Outlook": numerical or generic orbits); the arm directions come
     from them, the arm length of the link transfer and the TDI delays stays L.
     ``links``: the six link light times [..., 6] (light-seconds, rows as LINK_ROWS) at the times t; the
-    unequal-arm form of the module docstring then replaces the equal-arm one."""
+    unequal-arm form of the module docstring then replaces the equal-arm one, in the first or (``generation``
+    = 2) the second TDI generation."""
     t = t if torch.is_tensor(t) else torch.as_tensor(t, dtype=torch.float64)
     f = f if torch.is_tensor(f) else torch.as_tensor(f, dtype=torch.float64)
     ci = cos_iota if torch.is_tensor(cos_iota) else torch.as_tensor(cos_iota, dtype=torch.float64)
     k, ep, ex = sky_frame(cos_theta, phi, psi)
     p = orbits(t) if pos is None else torch.as_tensor(pos, dtype=torch.float64)
     if links is not None:
-        return _transfer_xyz_links(f, k, ep, ex, ci, p, torch.as_tensor(links, dtype=torch.float64))
+        return _transfer_xyz_links(f, k, ep, ex, ci, p, torch.as_tensor(links, dtype=torch.float64), generation)
+    if generation != 1:
+        raise ValueError("the second TDI generation is formed with a link light-time table")
     ap = (1.0 + ci * ci) / 2.0
     G = {}
     for (s, r) in LINKS:
@@ -173,7 +184,7 @@ def transfer_xyz(t, f, cos_theta, phi, psi, cos_iota, pos=None, links=None):
     return TX, TY, TZ
 
 
-def _transfer_xyz_links(f, k, ep, ex, ci, p, links):
+def _transfer_xyz_links(f, k, ep, ex, ci, p, links, generation=1):
     """(T_X, T_Y, T_Z) with the six link light times ``links`` [..., 6] and positions ``p`` [..., 3, 3]."""
     ap = (1.0 + ci * ci) / 2.0
     G, D = {}, {}
@@ -192,12 +203,20 @@ def _transfer_xyz_links(f, k, ep, ex, ci, p, links):
     TX = (1.0 - d(1, 2) * d(2, 1)) * (g(3, 1) + d(3, 1) * g(1, 3)) - (1.0 - d(1, 3) * d(3, 1)) * (g(2, 1) + d(2, 1) * g(1, 2))
     TY = (1.0 - d(2, 3) * d(3, 2)) * (g(1, 2) + d(1, 2) * g(2, 1)) - (1.0 - d(2, 1) * d(1, 2)) * (g(3, 2) + d(3, 2) * g(2, 3))
     TZ = (1.0 - d(3, 1) * d(1, 3)) * (g(2, 3) + d(2, 3) * g(3, 2)) - (1.0 - d(3, 2) * d(2, 3)) * (g(1, 3) + d(1, 3) * g(3, 1))
+    if generation == 2:
+        rt = lambda a, b: d(a, b) * d(b, a)  # round trip of the arm between a and b
+        TX = (1.0 - rt(1, 2) * rt(1, 3)) * TX
+        TY = (1.0 - rt(2, 3) * rt(2, 1)) * TY
+        TZ = (1.0 - rt(3, 1) * rt(3, 2)) * TZ
+    elif generation != 1:
+        raise ValueError("TDI generation 1 or 2")
     return TX, TY, TZ
 
 
-def tdi_xyz_td_frozen(t, hfun, cos_theta, phi, psi, pos, links):
+def tdi_xyz_td_frozen(t, hfun, cos_theta, phi, psi, pos, links, generation: int = 1):
     """Time-domain X, Y, Z at times t for one frozen geometry: positions ``pos`` [3, 3] and the six link light
-    times ``links`` [6] (rows as LINK_ROWS), every link and delay of the unequal-arm form written out."""
+    times ``links`` [6] (rows as LINK_ROWS), every link and delay of the unequal-arm form written out; the
+    second generation as each combination minus itself delayed by its two round trips."""
     k, ep, ex = sky_frame(cos_theta, phi, psi)
     p = torch.as_tensor(pos, dtype=torch.float64)
     Ls = {sr: float(links[row]) for row, sr in enumerate(LINK_ROWS)}
@@ -216,13 +235,18 @@ def tdi_xyz_td_frozen(t, hfun, cos_theta, phi, psi, pos, links):
     def L(s, r):
         return Ls[(s - 1, r - 1)]
 
-    def michelson(a, b, c):
+    def first(a, b, c, t):
         # centred on a: (1 - R_ab)(y_ca + D_ca y_ac) - (1 - R_ac)(y_ba + D_ba y_ab), R_ab the round trip a -> b -> a
         rab, rac = L(a, b) + L(b, a), L(a, c) + L(c, a)
         return (y(c, a, t) + y(a, c, t - L(c, a)) - y(c, a, t - rab) - y(a, c, t - rab - L(c, a))) \
             - (y(b, a, t) + y(a, b, t - L(b, a)) - y(b, a, t - rac) - y(a, b, t - rac - L(b, a)))
 
-    return michelson(1, 2, 3), michelson(2, 3, 1), michelson(3, 1, 2)
+    def michelson(a, b, c, t):
+        if generation == 1:
+            return first(a, b, c, t)
+        return first(a, b, c, t) - first(a, b, c, t - (L(a, b) + L(b, a)) - (L(a, c) + L(c, a)))
+
+    return michelson(1, 2, 3, t), michelson(2, 3, 1, t), michelson(3, 1, 2, t)
 
 
 def link_td(t, hfun, s, r, k, ep, ex):

@@ -10,6 +10,9 @@ point-ahead light times; the response of Sec. "Implementation details" with each
   2e-3, as for equal arms.
 * In the statistic: equal links on an exactly equilateral orbit give the equal-arm statistic; a longer arm
   changes it.
+* Second TDI generation: the time-domain combination minus itself delayed by both round trips equals the
+  transfer times the carrier for a monochromatic wave; for equal arms it is the first generation times the
+  closed form 1 - exp(-8 pi i f L), and for unequal arms the three channels get different factors.
 """
 import math
 
@@ -158,3 +161,38 @@ def test_statistic_with_equal_links_on_an_equilateral_orbit():
     d = o2.statistic(pix, u, wm, b, g, orbit=tab, links=lk2)
     assert np.max(np.abs(d.stat - a.stat) / np.maximum(a.stat, 1.0)) > 1e-4
     assert np.array_equal(d.flags, a.flags)
+
+
+@pytest.mark.parametrize("ct,ph,ps,ci", _sky_pars()[:2])
+@pytest.mark.parametrize("f", [0.009, 0.052])
+def test_second_generation_time_domain_is_the_transfer(ct, ph, ps, ci, f):
+    pos = rsp.orbits(torch.tensor(9.3e6, dtype=torch.float64))
+    links = _links(int(1000 * f) + 40)
+    t = torch.linspace(3.0e5, 8.0e5, 5, dtype=torch.float64)
+    X, Y, Z = rsp.tdi_xyz_td_frozen(t, _mono(f, ci), ct, ph, ps, pos, links, generation=2)
+    fz = torch.full((1,), f, dtype=torch.float64)
+    T2 = rsp.transfer_xyz(torch.zeros(1, dtype=torch.float64), fz, ct, ph, ps, ci, pos[None],
+                          torch.as_tensor(links)[None], generation=2)
+    T1 = rsp.transfer_xyz(torch.zeros(1, dtype=torch.float64), fz, ct, ph, ps, ci, pos[None],
+                          torch.as_tensor(links)[None])
+    carrier = torch.polar(torch.ones_like(t), 2.0 * math.pi * f * t)
+    ratios = []
+    for td, T, T1c in zip((X, Y, Z), T2, T1):
+        ref = T * carrier
+        assert float(((td - ref).abs() / ref.abs().max()).max()) < 1e-9
+        ratios.append(complex(T[0] / T1c[0]))
+    # unequal arms: each channel's own factor
+    assert abs(ratios[0] - ratios[1]) > 1e-3 and abs(ratios[1] - ratios[2]) > 1e-3
+
+
+def test_second_generation_with_equal_arms_is_the_common_factor():
+    ct, ph, ps, ci = _sky_pars()[2]
+    t = torch.tensor([2.0e6, 1.1e7], dtype=torch.float64)
+    pos = torch.stack([_equilateral(float(x), rsp.L_S) for x in t])
+    f = torch.tensor([0.017, 0.066], dtype=torch.float64)
+    lk = torch.full((2, 6), rsp.L_S, dtype=torch.float64)
+    one = rsp.transfer_xyz(t, f, ct, ph, ps, ci, pos, lk)
+    two = rsp.transfer_xyz(t, f, ct, ph, ps, ci, pos, lk, generation=2)
+    factor = 1.0 - torch.polar(torch.ones_like(f), -8.0 * math.pi * f * rsp.L_S)
+    for a, b in zip(one, two):
+        assert float(((b - factor * a).abs() / b.abs().max()).max()) < 1e-12
