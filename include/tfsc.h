@@ -116,6 +116,14 @@ typedef struct {
  *   arms (paper Sec. "Implementation details", Eq. (tdi2)).
  * Six equal times L on a table whose sides are exactly L give the
  * equal-arm response.  tfsc_link_lengths writes |p_r - p_s| of an orbit.
+ *
+ * tdi_generation: 0 or 1 for the first-generation combinations above (the
+ * paper's rescaled TDI-1.5), 2 for the second generation on the same
+ * frozen geometry (the data the paper analyses are TDI-2; Sec.
+ * "Implementation details"): each combination minus itself delayed by the
+ * round trips of its two arms, X2 = (1 - D01 D10 D02 D20) X, Y and Z
+ * cyclic.  2 needs the links table (else TFSC_ERR_UNSUPPORTED); other
+ * values give TFSC_ERR_ARG.
  * Read by tfsc_bank_statistic (both schedules; F64 pixels with F64
  * arithmetic or F32 with F32; no rho; the paper's Fresnel forms); the VJP,
  * the several-realisation and the harmonics calls return
@@ -130,6 +138,7 @@ typedef struct {
     float *rho;
     const double *orbit;
     const double *links;
+    int32_t tdi_generation;
 } tfsc_pixels;
 
 /* Template bank, structure of arrays, n templates, FP64:

@@ -81,11 +81,12 @@ class PixelStore:
     rho: torch.Tensor | None = None   # [K][Nt] f32 per-pixel weight factor of a general per-tranche PSD
     orbit: torch.Tensor | None = None  # [3][3][Nt] f64 spacecraft positions (light-seconds), None = analytic orbit
     links: torch.Tensor | None = None  # [6][Nt] f64 link light times (seconds), None = equal arms
+    tdi_generation: int = 1            # 2: second-generation TDI (with links)
 
     def c(self) -> _lib.Pixels:
         return _lib.Pixels(_DTYPE[self.dtype], _LAYOUT[self.layout], _ptr(self.pix), _ptr(self.layer_scale),
                            _ptr(self.inv_asd), _ptr(self.tranche_w), _ptr(self.rho), _ptr(self.orbit),
-                           _ptr(self.links))
+                           _ptr(self.links), int(self.tdi_generation))
 
     @staticmethod
     def from_complex(pix: torch.Tensor, inv_asd: torch.Tensor, tranche_w: torch.Tensor, dtype: str = "f64",
@@ -436,7 +437,7 @@ def interleaved_store(grid: GridSpec, n_real: int, like: PixelStore) -> PixelSto
     return PixelStore(torch.empty((K, Nt, n_real * C, 2), dtype=_TORCH_STORE[like.dtype], device=dev),
                       like.inv_asd, like.tranche_w, like.dtype, "layer_ci",
                       torch.empty((n_real * C, K), dtype=torch.float32, device=dev) if like.dtype == "i16" else None,
-                      None, like.orbit, like.links)
+                      None, like.orbit, like.links, like.tdi_generation)
 
 
 def interleave_store(grid: GridSpec, src: PixelStore, n_real: int, r: int, out: PixelStore) -> PixelStore:

@@ -30,7 +30,7 @@ class Grid(ctypes.Structure):
 class Pixels(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int), ("layout", ctypes.c_int), ("pix", c_void_p), ("layer_scale", c_void_p),
                 ("inv_asd", c_void_p), ("tranche_w", c_void_p), ("rho", c_void_p), ("orbit", c_void_p),
-                ("links", c_void_p)]
+                ("links", c_void_p), ("tdi_generation", c_int32)]
 
 
 class Bank(ctypes.Structure):

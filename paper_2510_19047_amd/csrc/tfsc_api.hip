@@ -67,6 +67,8 @@ tfsc_status check_pixels(const tfsc_pixels *p, bool need_data) {
     if (need_data && !p->pix) return TFSC_ERR_ARG;
     if (!p->inv_asd || !p->tranche_w) return TFSC_ERR_ARG;
     if (is_16bit(p->dtype) && !p->layer_scale) return TFSC_ERR_ARG;
+    if (p->tdi_generation < 0 || p->tdi_generation > 2) return TFSC_ERR_ARG;
+    if (p->tdi_generation == 2 && !p->links) return TFSC_ERR_UNSUPPORTED;
     return TFSC_OK;
 }
 
@@ -187,6 +189,7 @@ tfsc::StatLaunch stat_launch(const tfsc_grid *grid, const tfsc_pixels *pix, cons
     L.tranche_w = pix->tranche_w;
     L.rho = pix->rho;
     L.links = pix->links;
+    L.tdi2 = pix->links && pix->tdi_generation == 2;
     L.geo = reinterpret_cast<const double *>(ws);
     L.n = bank->n;
     L.mc = bank->mc;

@@ -63,6 +63,20 @@ __device__ __forceinline__ double sqrt_pos(double x) {
     return fma(d, h, g);
 }
 
+// 1/b, correctly rounded, for a normal b whose reciprocal is normal and far from the range limits (the track's
+// 1/s and 1/theta^5): the hardware reciprocal refined by two Newton steps, then Markstein's correction of the
+// quotient by its exact residual 1 - b q.  This is the compiler's division sequence for 1/b without its operand
+// rescaling and its special-value fix-up, so on these inputs it returns the same bits.
+__device__ __forceinline__ double rcp_rn(double b) {
+    double y = __builtin_amdgcn_rcp(b);
+    double e = fma(-b, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-b, y, 1.0);
+    y = fma(y, e, y);
+    const double r = fma(-b, y, 1.0);
+    return fma(r, y, y);
+}
+
 __device__ __forceinline__ bool params_valid(double mc, double eta, double f0, double ct, double ci) {
     if (!(mc > 0.0) || !(eta >= 0.01) || !(eta <= 0.25) || !(f0 > 0.0)) return false;
     if (!(fabs(ct) <= 1.0) || !(fabs(ci) <= 1.0)) return false;
@@ -113,15 +127,16 @@ __device__ inline void track_init(Track &T, double mc, double eta, double f0) {
 
 // Phase Phi (rad, phi_c = 0), GW frequency f and its derivative at time t < t_c, in the
 // operation order of the formulas: q = eta (t_c - t) / (5M), theta = 1 / q^(1/8) (three correctly
-// rounded square roots, sqrt_pos: every caller has t_c - t >= dT, so q is a normal number far above 2^-767), f = (theta^3 / (8 pi M)) P_f, fdot = ((theta^2 / (8 pi M)) P_f') (eta theta^9 / (40M)),
+// rounded square roots), f = (theta^3 / (8 pi M)) P_f, fdot = ((theta^2 / (8 pi M)) P_f') (eta theta^9 / (40M)),
 // Phi = -(2 theta^-5 P_phi) / eta with theta^-5 = 1 / (theta^4 theta).  Divisions by the
 // per-template constants 5M, 8 pi M, 40M and eta are formed by div_rn (the same correctly
-// rounded quotients); 1/s and 1/(theta^4 theta) are full divisions.
+// rounded quotients); 1/s and 1/(theta^4 theta) by rcp_rn and the roots by sqrt_pos (the same
+// correctly rounded results: every caller has t_c - t > 0 with q, s and theta far inside the normal range).
 __device__ inline void track_at(const Track &T, double t, double &Phi, double &f, double &fdot) {
     double tau = T.tc - t;
     double q = div_rn(T.eta * tau, T.M5, T.r5M);
     double s = sqrt_pos(sqrt_pos(sqrt_pos(q)));
-    double th = 1.0 / s;
+    double th = rcp_rn(s);
     double th2 = th * th, th3 = th2 * th, th4 = th2 * th2;
     double Pf = ((1.0 + T.a2 * th2) + T.a3 * th3) + T.a4 * th4;
     f = div_rn(th3, T.c8, T.rc8) * Pf;
@@ -131,7 +146,7 @@ __device__ inline void track_at(const Track &T, double t, double &Phi, double &f
     double dthdt = div_rn(T.eta * th9, T.M40, T.r40M);
     fdot = dfdth * dthdt;
     double Pp = ((1.0 + T.b2 * th2) + T.b3 * th3) + T.b4 * th4;
-    double thm5 = 1.0 / (th4 * th);
+    double thm5 = rcp_rn(th4 * th);
     Phi = -div_rn((2.0 * thm5) * Pp, T.eta, T.reta);
 }
 
@@ -141,6 +156,17 @@ __device__ __forceinline__ int track_step(const Track &T, double tm, double dT, 
                                           double &Phi, double &f, double &fdot) {
     if (tm + dT >= T.tc) return kFlagMergeEnd;
     track_at(T, tm, Phi, f, fdot);
+    if ((f + fdot * dT >= fnyq - 11.0 * df) || (fdot * dT > 10.0 * df)) return kFlagBandEnd;
+    return 0;
+}
+
+// track_step for the lanes of a wave: the track is evaluated unconditionally (past the merger it is NaN and
+// the flag says so; the caller uses the values only where the flag is 0), which spares the wave the masked
+// branch and the zeroed outputs.  Same flag and, where it is 0, the same values as track_step.
+__device__ __forceinline__ int track_step_lanes(const Track &T, double tm, double dT, double df, double fnyq,
+                                                double &Phi, double &f, double &fdot) {
+    track_at(T, tm, Phi, f, fdot);
+    if (tm + dT >= T.tc) return kFlagMergeEnd;
     if ((f + fdot * dT >= fnyq - 11.0 * df) || (fdot * dT > 10.0 * df)) return kFlagBandEnd;
     return 0;
 }
@@ -274,10 +300,11 @@ struct GeoView {
     __amdgpu_buffer_rsrc_t g64, g32;
     uint32_t row64, row32;  // bytes per row
     __amdgpu_buffer_rsrc_t lk;  // a caller's link light times [6][Nt] (FP64, rows of row64 bytes), if any
+    int tdi2;                   // with the link table: second-generation TDI combinations
 };
 
 __device__ __forceinline__ GeoView geo_view(const double *geo, const float *geo32, int Nt,
-                                            const double *links = nullptr) {
+                                            const double *links = nullptr, int tdi2 = 0) {
     GeoView v;
     v.row64 = (uint32_t)Nt * 8u;
     v.row32 = (uint32_t)Nt * 4u;
@@ -285,6 +312,7 @@ __device__ __forceinline__ GeoView geo_view(const double *geo, const float *geo3
     v.g32 = __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(geo32), (short)0, (int)(v.row32 * 9u), 0x00020000);
     v.lk = __builtin_amdgcn_make_buffer_rsrc(const_cast<double *>(links), (short)0, links ? (int)(v.row64 * 6u) : 0,
                                              0x00020000);
+    v.tdi2 = tdi2;
     return v;
 }
 
@@ -379,6 +407,18 @@ __device__ inline void transfer_ae(const Sky<R> &S, const GeoView &gv, int m, do
 // (the sine of an argument folded into [-1/4, 1/4] revolutions, as for equal arms); with the common factor
 // -i pi f it is the real 2 pi f sin(pi f l_a) times e^{-i pi f l_a}.  f k.p_r reaches tens of revolutions and
 // is reduced in FP64; the link terms below a revolution are formed in R.
+// Second generation (gv.tdi2, the arms static over the tranche): each combination minus itself delayed by the
+// round trips of its two arms, X2 = (1 - R_0 R_2) X, Y2 = (1 - R_0 R_1) Y, Z2 = (1 - R_1 R_2) Z with
+// R_a = e^{-2 pi i f l_a}, each factor formed as 2 i sin(pi f (l_a + l_b)) e^{-i pi f (l_a + l_b)}.
+template <class R>
+__device__ __forceinline__ cx<R> one_minus_round_trips(double f, double lab) {
+    const double rr = frac_rev(0.5 * f * lab);
+    const double rfold = rr > 0.25 ? 0.5 - rr : (rr < -0.25 ? -0.5 - rr : rr);
+    const R s2 = (R)2 * sin_rev_accurate((R)rfold);
+    const cx<R> e = expi_rev((R)(-rr));
+    return {-s2 * e.im, s2 * e.re};
+}
+
 template <class R, bool WITH_T = false>
 __device__ inline void transfer_links(const Sky<R> &S, const GeoView &gv, int m, double f, cx<R> &TA, cx<R> &TE,
                                       cx<R> *TT = nullptr) {
@@ -392,10 +432,12 @@ __device__ inline void transfer_links(const Sky<R> &S, const GeoView &gv, int m,
     }
     const R pf = (R)(kPi * f), hf = (R)(-0.5 * f), rf = (R)f;
     cx<R> Gd[3], Gr[3], F[3], Dd[3], Dr[3];
+    double la[3];  // round trips of the arms
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int s = a, r = (a + 1) % 3;
         const double Lfd = geo_link(gv, m, a), Lbd = geo_link(gv, m, 3 + a);
+        la[a] = Lfd + Lbd;
         const R Lf = (R)Lfd, Lb = (R)Lbd;
         R n0 = geo_arm<R>(gv, m, 3 * a + 0);
         R n1 = geo_arm<R>(gv, m, 3 * a + 1);
@@ -411,16 +453,21 @@ __device__ inline void transfer_links(const Sky<R> &S, const GeoView &gv, int m,
         Gr[a] = cscale(cmul(Eb, amp), Lb * sinc_of(pf * Lb * op));
         Dd[a] = expi_rev(-(rf * Lf));
         Dr[a] = expi_rev(-(rf * Lb));
-        const double rr = frac_rev(0.5 * f * (Lfd + Lbd));
+        const double rr = frac_rev(0.5 * f * la[a]);
         const double rfold = rr > 0.25 ? 0.5 - rr : (rr < -0.25 ? -0.5 - rr : rr);
         F[a] = cscale(expi_rev((R)(-rr)), (R)(kTwoPi * f) * sin_rev_accurate((R)rfold));
     }
     // 0-based spacecraft: arm 0 = (0,1), arm 1 = (1,2), arm 2 = (2,0)
     const cx<R> G01 = Gd[0], G10 = Gr[0], G12 = Gd[1], G21 = Gr[1], G20 = Gd[2], G02 = Gr[2];
     const cx<R> D01 = Dd[0], D10 = Dr[0], D12 = Dd[1], D21 = Dr[1], D20 = Dd[2], D02 = Dr[2];
-    const cx<R> X = csub(cmul(F[0], cadd(G20, cmul(D20, G02))), cmul(F[2], cadd(G10, cmul(D10, G01))));
-    const cx<R> Y = csub(cmul(F[1], cadd(G01, cmul(D01, G10))), cmul(F[0], cadd(G21, cmul(D21, G12))));
-    const cx<R> Z = csub(cmul(F[2], cadd(G12, cmul(D12, G21))), cmul(F[1], cadd(G02, cmul(D02, G20))));
+    cx<R> X = csub(cmul(F[0], cadd(G20, cmul(D20, G02))), cmul(F[2], cadd(G10, cmul(D10, G01))));
+    cx<R> Y = csub(cmul(F[1], cadd(G01, cmul(D01, G10))), cmul(F[0], cadd(G21, cmul(D21, G12))));
+    cx<R> Z = csub(cmul(F[2], cadd(G12, cmul(D12, G21))), cmul(F[1], cadd(G02, cmul(D02, G20))));
+    if (gv.tdi2) {
+        X = cmul(one_minus_round_trips<R>(f, la[0] + la[2]), X);
+        Y = cmul(one_minus_round_trips<R>(f, la[0] + la[1]), Y);
+        Z = cmul(one_minus_round_trips<R>(f, la[1] + la[2]), Z);
+    }
     const R is2 = (R)0.70710678118654752440, is6 = (R)0.40824829046386301637;
     TA = cscale(csub(Z, X), is2);
     TE = cscale(cadd(csub(X, cscale(Y, (R)2)), Z), is6);

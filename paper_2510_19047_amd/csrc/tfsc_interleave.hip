@@ -137,8 +137,9 @@ __global__ __launch_bounds__(256, 3) void k_stat_wave_ri(StatArgs a) {
             const int m = m0 + lane;
             const bool inr = m < a.Nt;
             const double wm_raw = inr ? a.tranche_w[m] : 0.0;
-            double Phi = 0.0, f = 0.0, fdot = 0.0;
-            int code = inr ? track_step(T, (double)m * a.dT, a.dT, a.df, a.fnyq, Phi, f, fdot) : 0;
+            double Phi, f, fdot;
+            int code = track_step_lanes(T, (double)(inr ? m : a.Nt - 1) * a.dT, a.dT, a.df, a.fnyq, Phi, f, fdot);
+            code = inr ? code : 0;
             const uint64_t viol = __ballot(code != 0);
             int lim = a.Nt;
             if (viol) {

@@ -41,6 +41,7 @@ struct StatLaunch {
     const double *inv_asd, *tranche_w, *geo;
     const float *rho;       // [K][Nt] per-pixel weight factor, NULL for a separable PSD
     const double *links;    // [6][Nt] link light times (unequal arms), NULL for equal arms
+    int tdi2;               // with links: second-generation TDI combinations
     const double *u_scale;  // device scalar written by launch_weight_scale
     int64_t n;
     const double *mc, *eta, *f0, *ct, *phi, *psi, *ci;

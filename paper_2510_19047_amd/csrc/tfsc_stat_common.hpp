@@ -27,6 +27,7 @@ struct StatArgs {
     const float *rho;       // [K][Nt] per-pixel weight factor (general per-tranche PSD), else NULL
     uint32_t rho_bytes;
     const double *links;    // [6][Nt] link light times (unequal arms), else NULL
+    int tdi2;               // with links: second-generation TDI combinations
     int64_t n;
     const double *mc, *eta, *f0, *ct, *phi, *psi, *ci;
     const int32_t *nseg;
@@ -610,7 +611,7 @@ __device__ __forceinline__ void stat_thread_body(const StatArgs &a) {
     track_init(T, a.mc[i], a.eta[i], a.f0[i]);
     Sky<R> S;
     sky_init(S, a.ct[i], a.phi[i], a.psi[i], a.ci[i]);
-    const GeoView gv = geo_view(a.geo, a.geo32, a.Nt, LK ? a.links : nullptr);
+    const GeoView gv = geo_view(a.geo, a.geo32, a.Nt, LK ? a.links : nullptr, LK ? a.tdi2 : 0);
     const double u_mul = a.u_scale[0];
     int m = 0, n_act = 0;
     for (; m < a.Nt; ++m) {
@@ -668,7 +669,7 @@ __device__ __forceinline__ void stat_wave_body(const StatArgs &a) {
     __syncthreads();
     const __amdgpu_buffer_rsrc_t rsrc = pix_rsrc(a.pix, a.pix_bytes);
     const __amdgpu_buffer_rsrc_t rho_rsrc = pix_rsrc(RHO ? a.rho : a.pix, RHO ? a.rho_bytes : 0u);
-    const GeoView gv = geo_view(a.geo, a.geo32, a.Nt, LK ? a.links : nullptr);
+    const GeoView gv = geo_view(a.geo, a.geo32, a.Nt, LK ? a.links : nullptr, LK ? a.tdi2 : 0);
 
     const int lane = threadIdx.x & 63;
     for (;;) {
@@ -708,8 +709,9 @@ __device__ __forceinline__ void stat_wave_body(const StatArgs &a) {
             const int m = m0 + lane;
             const bool inr = m < a.Nt;
             const double wm_raw = inr ? a.tranche_w[m] : 0.0;  // issued before the track is evaluated
-            double Phi = 0.0, f = 0.0, fdot = 0.0;
-            int code = inr ? track_step(T, (double)m * a.dT, a.dT, a.df, a.fnyq, Phi, f, fdot) : 0;
+            double Phi, f, fdot;
+            int code = track_step_lanes(T, (double)(inr ? m : a.Nt - 1) * a.dT, a.dT, a.df, a.fnyq, Phi, f, fdot);
+            code = inr ? code : 0;
             const uint64_t viol = __ballot(code != 0);
             int lim = a.Nt;
             if (viol) {
@@ -804,6 +806,7 @@ inline StatArgs make_args(const StatLaunch &L) {
     a.u_scale = L.u_scale;
     a.rho = L.rho;
     a.links = L.links;
+    a.tdi2 = L.tdi2;
     {
         const uint64_t rb = (uint64_t)a.K * (uint64_t)a.Nt * 4u;
         a.rho_bytes = L.rho ? (rb > 0xffffffffull ? 0xffffffffu : (uint32_t)rb) : 0u;

@@ -572,8 +572,9 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 2 : 1) void k_vjp_wave(VjpArg
             for (int m0 = 0; m0 < m_end; m0 += 64) {
                 const int m = m0 + lane;
                 const bool inr = m < a.Nt;
-                double Phi = 0.0, f = 0.0, fdot = 0.0;
-                const int code = inr ? track_step(T, (double)m * a.dT, a.dT, a.df, a.fnyq, Phi, f, fdot) : 0;
+                double Phi, f, fdot;
+                int code = track_step_lanes(T, (double)(inr ? m : a.Nt - 1) * a.dT, a.dT, a.df, a.fnyq, Phi, f, fdot);
+                code = inr ? code : 0;
                 const uint64_t viol = __ballot(code != 0);
                 int lim = a.Nt;
                 if (viol) {

@@ -239,3 +239,22 @@ def test_links_argument_errors(L):
                                            ctypes.byref(f32), 1, arr, p, p, p, None, p, None, p, ws, None) == 5
     assert L.tfsc_link_lengths(ctypes.byref(g), None, None, None) == 1
     assert L.tfsc_link_lengths(ctypes.byref(_grid(n_tranches=0)), None, p, None) != 0
+
+
+def test_tdi_generation_argument_errors(L):
+    """tfsc_pixels.tdi_generation: 0, 1 or 2, and 2 only with the link light-time table (no device call)."""
+    from paper_2510_19047_amd import _lib
+    g = _grid()
+    one = (ctypes.c_double * 4)()
+    p = ctypes.cast(one, ctypes.c_void_p)
+    seg = _lib.Segments(0, p, p)
+    bank = _lib.Bank(1, p, p, p, p, p, p, p, None)
+    opt = _lib.Options(1, 1, 0, 0, None, 0, None)
+
+    def stat(px):
+        return L.tfsc_bank_statistic(ctypes.byref(g), ctypes.byref(px), ctypes.byref(bank), ctypes.byref(seg),
+                                     ctypes.byref(opt), p, p, None, p, None, p, 1 << 30, None)
+
+    assert stat(_lib.Pixels(1, 2, p, None, p, p, None, None, p, 3)) == 1
+    assert stat(_lib.Pixels(1, 2, p, None, p, p, None, None, p, -1)) == 1
+    assert stat(_lib.Pixels(1, 2, p, None, p, p, None, None, None, 2)) == 5

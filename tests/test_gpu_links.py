@@ -5,6 +5,7 @@ times of numerical orbits) through the C ABI, against the oracle (``oracle.respo
 * Six equal light times L on an exactly equilateral orbit give the equal-arm statistic.
 * Unequal, direction-dependent light times on the analytic orbit and on a perturbed table: both schedules,
   FP64 and FP32, two and three channels, against the oracle given the same table; flags equal.
+* Second-generation TDI on the same geometry against the oracle's.
 * The calls that do not take the table refuse it.
 """
 import functools
@@ -177,6 +178,32 @@ def test_three_channels_with_links():
         note(f"A + E + T with links, {dtype} {schedule}: max rel vs oracle {e.max():.2e}")
         assert e.max() < tol
         assert np.array_equal(res.flags.cpu().numpy(), ref.flags)
+
+
+@pytest.mark.parametrize("dtype,schedule,tol", [("f64", "wave", 1e-6), ("f64", "thread", 1e-6), ("f32", "wave", 1e-4)])
+def test_second_generation_against_the_oracle(dtype, schedule, tol):
+    tfsc = lib()
+    d = small_data()
+    g = d["grid"]
+    grid = gridspec(g)
+    b = d["bank"]
+    idx = _subset(len(b))
+    links = _links_table(g, 13)
+    ref = o2.statistic(d["pix"], d["u"], d["wm"], b, g, layout=otrk.Layout(b, g), idx=idx, links=links, generation=2)
+    first = o2.statistic(d["pix"], d["u"], d["wm"], b, g, layout=otrk.Layout(b, g), idx=idx, links=links)
+    bt = tfsc.BankTensors.from_host(b)
+    seg = tfsc.segment_layout(grid, bt)
+    store = store_from_oracle(d, dtype, "layer_ci")
+    from dataclasses import replace
+    store = replace(store, links=dev(links), tdi_generation=2)
+    res = tfsc.bank_statistic(grid, store, bt, seg, precision=dtype, schedule=schedule)
+    e = rel(res.stat.cpu().numpy()[idx], ref.stat[idx])
+    moved = rel(first.stat[idx], ref.stat[idx]).max()
+    note(f"second-generation TDI, unequal links, {dtype} {schedule}: max rel vs oracle {e.max():.2e} (the "
+         f"generation moves Upsilon by {moved:.1e})")
+    assert e.max() < tol
+    assert moved > 10 * tol
+    assert np.array_equal(res.flags.cpu().numpy()[idx], ref.flags[idx])
 
 
 def test_calls_without_the_unequal_arm_response_refuse_links():
