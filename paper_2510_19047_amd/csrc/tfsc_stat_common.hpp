@@ -147,30 +147,45 @@ __device__ __forceinline__ void tranche_bins(const StatArgs &a, const TrancheSpe
     }
 }
 
-// Tranche contribution z_m = w_m sum_c T_c P_c, N_m = w_m^2 (sum_c |T_c|^2) Q.  LK: the response with the
-// caller's link light times (unequal arms).
+// The response T_c(t_m, f_m) of the C channels.  LK: with the caller's link light times (unequal arms).
 template <int C, class R, bool LK = false>
-__device__ __forceinline__ void tranche_combine(const Sky<R> &S, const GeoView &gv, int m, double f, R wm,
-                                                const cx<R> (&P)[C], R Q, R &zr, R &zi, R &nn) {
-#pragma clang fp contract(fast)
+__device__ __forceinline__ void tranche_transfer(const Sky<R> &S, const GeoView &gv, int m, double f, cx<R> (&T)[C]) {
     cx<R> TA, TE, TT;
     if constexpr (LK)
         transfer_links<R, (C == 3)>(S, gv, m, f, TA, TE, &TT);
     else
         transfer_ae<R, (C == 3)>(S, gv, m, f, TA, TE, &TT);
-    cx<R> z = cmul(TA, P[0]);
-    R tt = TA.re * TA.re + TA.im * TA.im;
+    T[0] = TA;
+    if constexpr (C >= 2) T[1] = TE;
+    if constexpr (C == 3) T[2] = TT;
+}
+
+// Tranche contribution z_m = w_m sum_c T_c P_c, N_m = w_m^2 (sum_c |T_c|^2) Q.
+template <int C, class R>
+__device__ __forceinline__ void tranche_sums(const cx<R> (&T)[C], R wm, const cx<R> (&P)[C], R Q, R &zr, R &zi,
+                                             R &nn) {
+#pragma clang fp contract(fast)
+    cx<R> z = cmul(T[0], P[0]);
+    R tt = T[0].re * T[0].re + T[0].im * T[0].im;
     if constexpr (C >= 2) {
-        z = cadd(z, cmul(TE, P[1]));
-        tt += TE.re * TE.re + TE.im * TE.im;
+        z = cadd(z, cmul(T[1], P[1]));
+        tt += T[1].re * T[1].re + T[1].im * T[1].im;
     }
     if constexpr (C == 3) {
-        z = cadd(z, cmul(TT, P[2]));
-        tt += TT.re * TT.re + TT.im * TT.im;
+        z = cadd(z, cmul(T[2], P[2]));
+        tt += T[2].re * T[2].re + T[2].im * T[2].im;
     }
     zr = wm * z.re;
     zi = wm * z.im;
     nn = wm * wm * tt * Q;
+}
+
+template <int C, class R, bool LK = false>
+__device__ __forceinline__ void tranche_combine(const Sky<R> &S, const GeoView &gv, int m, double f, R wm,
+                                                const cx<R> (&P)[C], R Q, R &zr, R &zi, R &nn) {
+    cx<R> T[C];
+    tranche_transfer<C, R, LK>(S, gv, m, f, T);
+    tranche_sums<C, R>(T, wm, P, Q, zr, zi, nn);
 }
 
 // ------------------------------------------------------------------ WAVE schedule
@@ -705,13 +720,16 @@ __device__ __forceinline__ void stat_wave_body(const StatArgs &a) {
         int m_end = a.Nt, n_act = 0;
         SegWalk sw;
         sw.init(a.Nt, ns);
+        // The track of a chunk is evaluated during the previous chunk, in the same block as that chunk's
+        // response, so the dependent FP64 chain and the FP32 response fill each other's issue gaps.
+        double Phi, f, fdot;
+        int code = track_step_lanes(T, (double)(lane < a.Nt ? lane : a.Nt - 1) * a.dT, a.dT, a.df, a.fnyq, Phi, f,
+                                    fdot);
+        code = lane < a.Nt ? code : 0;
         for (int m0 = 0; m0 < m_end; m0 += 64) {
             const int m = m0 + lane;
             const bool inr = m < a.Nt;
-            const double wm_raw = inr ? a.tranche_w[m] : 0.0;  // issued before the track is evaluated
-            double Phi, f, fdot;
-            int code = track_step_lanes(T, (double)(inr ? m : a.Nt - 1) * a.dT, a.dT, a.df, a.fnyq, Phi, f, fdot);
-            code = inr ? code : 0;
+            const double wm_raw = inr ? a.tranche_w[m] : 0.0;
             const uint64_t viol = __ballot(code != 0);
             int lim = a.Nt;
             if (viol) {
@@ -742,17 +760,27 @@ __device__ __forceinline__ void stat_wave_body(const StatArgs &a) {
             }
             R zr = 0, zi = 0, nn = 0;
             const bool low = __ballot(work && kc < kHalfBins) != 0;
+            cx<R> P[C];
+            R Q = 0;
             if (work) {
-                cx<R> P[C];
-                R Q;
                 if (low)
                     wave_tranche_bins_low<C, R, PixT, LAYOUT, RHO, FR>(ts, kc, m, a.Nt, a.K, rsrc, rho_rsrc, u_pad, sc_pad,
                                                                    jA, jB, P, Q);
                 else
                     wave_tranche_bins<C, R, PixT, LAYOUT, RHO, FR>(ts, kc, m, a.Nt, a.K, rsrc, rho_rsrc, u_pad, sc_pad,
                                                                jA, jB, P, Q);
-                tranche_combine<C, R, LK>(S, gv, m, f, (R)wmd, P, Q, zr, zi, nn);
             }
+            // this chunk's response and the next chunk's track, for every lane (values of lanes without work
+            // are not used; the geometry row is clamped into the table)
+            cx<R> Tc[C];
+            tranche_transfer<C, R, LK>(S, gv, inr ? m : a.Nt - 1, f, Tc);
+            {
+                const int mn = m + 64;
+                int cn = track_step_lanes(T, (double)(mn < a.Nt ? mn : a.Nt - 1) * a.dT, a.dT, a.df, a.fnyq, Phi, f,
+                                          fdot);
+                code = mn < a.Nt ? cn : 0;
+            }
+            if (work) tranche_sums<C, R>(Tc, (R)wmd, P, Q, zr, zi, nn);
             // segmented reduction over the lanes of this chunk
             const int last = min(min(m0 + 63, lim - 1), a.Nt - 1);
             if (last >= m0) {
