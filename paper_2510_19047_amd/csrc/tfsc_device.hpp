@@ -282,14 +282,15 @@ __device__ inline void sky_init(Sky<R> &S, double ct, double phi, double psi, do
     S.q = (R)(-2.0 * ci / ap);
 }
 
+// sin(2 pi y) / y = 2 pi sinc(2 pi y) for an argument y in revolutions (the hardware sine takes revolutions, so
+// no scaling of the argument is spent; the constant 2 pi is folded into the caller's prefactor); series near 0,
+// selected rather than branched on (the unselected quotient may be inf or nan at y = 0).
 template <class R>
-__device__ __forceinline__ R sinc_of(R x) {
+__device__ __forceinline__ R sinc_rev2pi(R y) {
 #pragma clang fp contract(fast)
-    // sin(x)/x for 0 <= x <= ~2 pi f L; series near 0 (a select, not a branch: the
-    // unselected quotient may be inf or nan at x = 0)
-    const R q = sin_rev(x * (R)(1.0 / kTwoPi)) * rcp(x);
-    const R ser = (R)1 - x * x * (R)(1.0 / 6.0);
-    return x < (R)1e-4 ? ser : q;
+    const R q = sin_rev(y) * rcp(y);
+    const R ser = (R)kTwoPi - y * y * (R)(kTwoPi * kTwoPi * kTwoPi / 6.0);
+    return y < (R)1.6e-5 ? ser : q;
 }
 
 // Buffer views of the geometry tables: the FP64 table (rows of Nt doubles) and, for the FP32
@@ -348,9 +349,9 @@ __device__ inline void transfer_ae(const Sky<R> &S, const GeoView &gv, int m, do
 #pragma unroll
     for (int i = 0; i < 3; ++i)
         kp[i] = S.kd[0] * geo_d(gv, m, 3 * i) + S.kd[1] * geo_d(gv, m, 3 * i + 1) + S.kd[2] * geo_d(gv, m, 3 * i + 2);
-    const R pfL = (R)(kPi * f * L);
-    // Arm a, direction (s -> r) and reverse: G = -i pi f L e^{i ph} amp sinc(pi f L (1 -+ k.n));
-    // the common factor -i pi f L is applied once, to T_A and T_E below.
+    const R hfL = (R)(0.5 * f * L);  // pi f L in revolutions
+    // Arm a, direction (s -> r) and reverse: G = -i pi f L e^{i ph} amp sinc(pi f L (1 -+ k.n)); the sinc is
+    // taken as 2 pi sinc (sinc_rev2pi), and the common factor -i pi f L / (2 pi) is applied once, to T_A and T_E.
     cx<R> Gd[3], Gr[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -365,8 +366,8 @@ __device__ inline void transfer_ae(const Sky<R> &S, const GeoView &gv, int m, do
         double rev = frac_rev(-0.5 * f * (L + (kp[s] + kp[r])));  // -pi f (L + k.(p_s + p_r)) / 2 pi
         cx<R> E = expi_rev((R)rev);
         cx<R> Ea = cmul(E, amp);
-        Gd[a] = cscale(Ea, sinc_of(pfL * ((R)1 - kn)));
-        Gr[a] = cscale(Ea, sinc_of(pfL * ((R)1 + kn)));
+        Gd[a] = cscale(Ea, sinc_rev2pi(hfL * ((R)1 - kn)));
+        Gr[a] = cscale(Ea, sinc_rev2pi(hfL * ((R)1 + kn)));
     }
     // 0-based spacecraft: arm 0 = (0,1), arm 1 = (1,2), arm 2 = (2,0)
     const cx<R> G01 = Gd[0], G10 = Gr[0], G12 = Gd[1], G21 = Gr[1], G20 = Gd[2], G02 = Gr[2];
@@ -382,9 +383,9 @@ __device__ inline void transfer_ae(const Sky<R> &S, const GeoView &gv, int m, do
     const cx<R> Xp = cadd(csub(G20, G10), cmul(D, csub(G02, G01)));
     const cx<R> Yp = cadd(csub(G01, G21), cmul(D, csub(G10, G12)));
     const cx<R> Zp = cadd(csub(G12, G02), cmul(D, csub(G21, G20)));
-    // (1 - D^2)(-i pi f L) = 2 sin(2 pi f L) pi f L D, times 1/sqrt2 (A) or 1/sqrt6 (E)
+    // (1 - D^2)(-i pi f L) / (2 pi) = sin(2 pi f L) f L D, times 1/sqrt2 (A) or 1/sqrt6 (E)
     const R is2 = (R)0.70710678118654752440, is6 = (R)0.40824829046386301637;
-    const R sp = (R)2 * s2 * pfL;
+    const R sp = s2 * (hfL + hfL);
     const cx<R> oma = cscale(D, sp * is2);
     const cx<R> ome = cscale(D, sp * is6);
     TA = cmul(oma, csub(Zp, Xp));
@@ -405,7 +406,8 @@ __device__ inline void transfer_ae(const Sky<R> &S, const GeoView &gv, int m, do
 //   X = (1 - D01 D10)(G20 + D20 G02) - (1 - D02 D20)(G10 + D10 G01), Y and Z cyclic.
 // The round trip of arm a, l_a = L_sr + L_rs, enters as 1 - D_sr D_rs = 2 i sin(pi f l_a) e^{-i pi f l_a}
 // (the sine of an argument folded into [-1/4, 1/4] revolutions, as for equal arms); with the common factor
-// -i pi f it is the real 2 pi f sin(pi f l_a) times e^{-i pi f l_a}.  f k.p_r reaches tens of revolutions and
+// -i pi f it is the real 2 pi f sin(pi f l_a) times e^{-i pi f l_a}, of which 2 pi goes into the sincs
+// (sinc_rev2pi) and f sin(pi f l_a) e^{-i pi f l_a} stays in F.  f k.p_r reaches tens of revolutions and
 // is reduced in FP64; the link terms below a revolution are formed in R.
 // Second generation (gv.tdi2, the arms static over the tranche): each combination minus itself delayed by the
 // round trips of its two arms, X2 = (1 - R_0 R_2) X, Y2 = (1 - R_0 R_1) Y, Z2 = (1 - R_1 R_2) Z with
@@ -430,7 +432,7 @@ __device__ inline void transfer_links(const Sky<R> &S, const GeoView &gv, int m,
             S.kd[0] * geo_d(gv, m, 3 * i) + S.kd[1] * geo_d(gv, m, 3 * i + 1) + S.kd[2] * geo_d(gv, m, 3 * i + 2);
         rp[i] = (R)frac_rev(-f * kp);
     }
-    const R pf = (R)(kPi * f), hf = (R)(-0.5 * f), rf = (R)f;
+    const R hp = (R)(0.5 * f), hf = -hp, rf = (R)f;
     cx<R> Gd[3], Gr[3], F[3], Dd[3], Dr[3];
     double la[3];  // round trips of the arms
 #pragma unroll
@@ -449,13 +451,14 @@ __device__ inline void transfer_links(const Sky<R> &S, const GeoView &gv, int m,
         const R om = (R)1 - kn, op = (R)1 + kn;  // 1 - k.n of the forward and of the reverse link
         const cx<R> Ef = expi_rev(rp[r] + hf * Lf * om);
         const cx<R> Eb = expi_rev(rp[s] + hf * Lb * op);
-        Gd[a] = cscale(cmul(Ef, amp), Lf * sinc_of(pf * Lf * om));
-        Gr[a] = cscale(cmul(Eb, amp), Lb * sinc_of(pf * Lb * op));
+        // the sincs as 2 pi sinc of arguments in revolutions; the 1 / (2 pi) goes into F below
+        Gd[a] = cscale(cmul(Ef, amp), Lf * sinc_rev2pi(hp * Lf * om));
+        Gr[a] = cscale(cmul(Eb, amp), Lb * sinc_rev2pi(hp * Lb * op));
         Dd[a] = expi_rev(-(rf * Lf));
         Dr[a] = expi_rev(-(rf * Lb));
         const double rr = frac_rev(0.5 * f * la[a]);
         const double rfold = rr > 0.25 ? 0.5 - rr : (rr < -0.25 ? -0.5 - rr : rr);
-        F[a] = cscale(expi_rev((R)(-rr)), (R)(kTwoPi * f) * sin_rev_accurate((R)rfold));
+        F[a] = cscale(expi_rev((R)(-rr)), rf * sin_rev_accurate((R)rfold));
     }
     // 0-based spacecraft: arm 0 = (0,1), arm 1 = (1,2), arm 2 = (2,0)
     const cx<R> G01 = Gd[0], G10 = Gr[0], G12 = Gd[1], G21 = Gr[1], G20 = Gd[2], G02 = Gr[2];
@@ -580,11 +583,6 @@ __device__ inline void fresnel_fg_accurate(double z, double &f, double &g) {
     }
 }
 
-template <class R>
-__device__ __forceinline__ R sgn(R v) {
-    return v > (R)0 ? (R)1 : (v < (R)0 ? (R)-1 : (R)0);
-}
-
 // Asymptotic Fresnel on both tranche edges and no bin frequency crossed (bin_is_fast):
 // h_j = i Q (e^{i phi_m}/(x - j) - e^{i phi_end}/(x - j + beta)).
 template <class R>
@@ -613,7 +611,6 @@ __device__ __forceinline__ cx<R> bin_full(const TrancheSpec<R> &ts, R xj, int j)
 #pragma clang fp contract(fast)
     R xj1 = xj + ts.beta;
     R v0 = ts.s * xj, v1 = ts.s * xj1;
-    R sg0 = sgn(v0), sg1 = sgn(v1);
     R f0, g0, f1, g1;
     if constexpr (FR == kFresnelAccurate) {
         double a, b;
@@ -627,15 +624,17 @@ __device__ __forceinline__ cx<R> bin_full(const TrancheSpec<R> &ts, R xj, int j)
         fresnel_fg(fabs(v0), j >= ts.j0lo && j <= ts.j0hi, f0, g0);
         fresnel_fg(fabs(v1), j >= ts.j1lo && j <= ts.j1hi, f1, g1);
     }
-    cx<R> t0 = cmul(cx<R>{sg0 * g0, sg0 * f0}, ts.E0);
-    cx<R> t1 = cmul(cx<R>{sg1 * g1, sg1 * f1}, ts.E1);
+    // The sign of each Fresnel argument is its sign bit (an argument of exactly 0 counts as positive: since
+    // f(0) = g(0) = 1/2, the edge term (1+i)/2 e^{i phi} it then adds is the stationary-phase term it removes,
+    // so the value is the same as with sgn 0 there).
+    cx<R> t0 = cmul(cx<R>{copysign(g0, v0), copysign(f0, v0)}, ts.E0);
+    cx<R> t1 = cmul(cx<R>{copysign(g1, v1), copysign(f1, v1)}, ts.E1);
     cx<R> h = csub(t0, t1);
-    R ds = sg1 - sg0;
-    if (ds != (R)0) {
-        // bin frequency crossed inside the tranche: stationary-phase term
+    if (std::signbit(v0) != std::signbit(v1)) {
+        // bin frequency crossed inside the tranche: stationary-phase term, (sgn v1 - sgn v0) / 2 = +-1
         double rv = frac_rev(ts.rev0 - (double)(xj * xj * ts.half_inv_beta));
         cx<R> e = expi_rev((R)rv);
-        R hh = ds * (R)0.5;
+        const R hh = std::signbit(v0) ? (R)1 : (R)-1;
         h.re += hh * (e.re - e.im);
         h.im += hh * (e.re + e.im);
     }
