@@ -132,10 +132,13 @@ __device__ inline void track_init(Track &T, double mc, double eta, double f0) {
 // per-template constants 5M, 8 pi M, 40M and eta are formed by div_rn (the same correctly
 // rounded quotients); 1/s and 1/(theta^4 theta) by rcp_rn and the roots by sqrt_pos (the same
 // correctly rounded results: every caller has t_c - t > 0 with q, s and theta far inside the normal range).
-__device__ inline void track_at(const Track &T, double t, double &Phi, double &f, double &fdot) {
+// s_out, if given, receives s = 1/theta (the VJP's tangents reuse it).
+__device__ inline void track_at(const Track &T, double t, double &Phi, double &f, double &fdot,
+                                double *s_out = nullptr) {
     double tau = T.tc - t;
     double q = div_rn(T.eta * tau, T.M5, T.r5M);
     double s = sqrt_pos(sqrt_pos(sqrt_pos(q)));
+    if (s_out) *s_out = s;
     double th = rcp_rn(s);
     double th2 = th * th, th3 = th2 * th, th4 = th2 * th2;
     double Pf = ((1.0 + T.a2 * th2) + T.a3 * th3) + T.a4 * th4;
@@ -164,8 +167,8 @@ __device__ __forceinline__ int track_step(const Track &T, double tm, double dT, 
 // the flag says so; the caller uses the values only where the flag is 0), which spares the wave the masked
 // branch and the zeroed outputs.  Same flag and, where it is 0, the same values as track_step.
 __device__ __forceinline__ int track_step_lanes(const Track &T, double tm, double dT, double df, double fnyq,
-                                                double &Phi, double &f, double &fdot) {
-    track_at(T, tm, Phi, f, fdot);
+                                                double &Phi, double &f, double &fdot, double *s_out = nullptr) {
+    track_at(T, tm, Phi, f, fdot, s_out);
     if (tm + dT >= T.tc) return kFlagMergeEnd;
     if ((f + fdot * dT >= fnyq - 11.0 * df) || (fdot * dT > 10.0 * df)) return kFlagBandEnd;
     return 0;

@@ -265,30 +265,33 @@ __device__ inline TrackTan track_tangents(const Track &T, double f0) {
     return G;
 }
 
-// Phase, frequency and chirp tangents at t < t_c (values come from track_at).
+// Phase, frequency and chirp tangents at t < t_c.  s = 1/theta comes from the forward's track_at (its theta is
+// rcp_rn(s)); the per-template divisors enter through their reciprocals and theta^-6 as s^6, since the
+// tangents need no correctly rounded quotients.
 struct TrackDual {
     double dPhi[2], df[2], dfdot[2];
 };
 
-__device__ inline TrackDual track_dual(const Track &T, const TrackTan &G, double t, double f) {
+__device__ inline TrackDual track_dual(const Track &T, const TrackTan &G, double t, double f, double s) {
     const double tau = T.tc - t;
-    const double q = (T.eta * tau) / (5.0 * T.M);
-    const double th = 1.0 / sqrt(sqrt(sqrt(q)));
+    const double itau = rcp_rn(tau);
+    const double th = rcp_rn(s);
     const double th2 = th * th, th3 = th2 * th, th4 = th2 * th2, th5 = th4 * th, th9 = th5 * th4;
+    const double s2 = s * s, s6 = (s2 * s2) * s2;  // theta^-6
     const double dPf = ((3.0 + (5.0 * T.a2) * th2) + (6.0 * T.a3) * th3) + (7.0 * T.a4) * th4;
     const double ddPf = ((10.0 * T.a2) * th + (18.0 * T.a3) * th2) + (28.0 * T.a4) * th3;
-    const double dfdth = (th2 / T.c8) * dPf;
-    const double dthdt = (T.eta * th9) / (40.0 * T.M);
+    const double dfdth = (th2 * T.rc8) * dPf;
+    const double dthdt = (T.eta * th9) * T.r40M;
     const double Pp = ((1.0 + T.b2 * th2) + T.b3 * th3) + T.b4 * th4;
     const double dPp = ((2.0 * T.b2) * th + (3.0 * T.b3) * th2) + (4.0 * T.b4) * th3;
-    const double dPhidth = (2.0 / T.eta) * (5.0 * Pp - th * dPp) / (th5 * th);
+    const double dPhidth = (2.0 * T.reta) * (5.0 * Pp - th * dPp) * s6;
     TrackDual D;
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
         const double mu = G.mu[p];
-        const double dth = -0.125 * th * (G.dtc[p] / tau - mu);
+        const double dth = -0.125 * th * (G.dtc[p] * itau - mu);
         D.df[p] = dfdth * dth - f * mu;
-        const double d_dfdth = ((2.0 * th * dPf + th2 * ddPf) / T.c8) * dth - dfdth * mu;
+        const double d_dfdth = ((2.0 * th * dPf + th2 * ddPf) * T.rc8) * dth - dfdth * mu;
         const double d_dthdt = dthdt * (9.0 * dth / th - mu);
         D.dfdot[p] = d_dfdth * dthdt + dfdth * d_dthdt;
         D.dPhi[p] = dPhidth * dth;
@@ -298,14 +301,16 @@ __device__ inline TrackDual track_dual(const Track &T, const TrackTan &G, double
 
 __device__ inline void dphi_at(const Track &T, const TrackTan &G, double t, double out[2]) {
     const double tau = T.tc - t;
-    const double q = (T.eta * tau) / (5.0 * T.M);
-    const double th = 1.0 / sqrt(sqrt(sqrt(q)));
-    const double th2 = th * th, th3 = th2 * th, th4 = th2 * th2, th5 = th4 * th;
+    const double itau = rcp_rn(tau);
+    const double s = sqrt_pos(sqrt_pos(sqrt_pos((T.eta * tau) * T.r5M)));
+    const double th = rcp_rn(s);
+    const double th2 = th * th, th3 = th2 * th, th4 = th2 * th2;
+    const double s2 = s * s, s6 = (s2 * s2) * s2;  // theta^-6
     const double Pp = ((1.0 + T.b2 * th2) + T.b3 * th3) + T.b4 * th4;
     const double dPp = ((2.0 * T.b2) * th + (3.0 * T.b3) * th2) + (4.0 * T.b4) * th3;
-    const double dPhidth = (2.0 / T.eta) * (5.0 * Pp - th * dPp) / (th5 * th);
+    const double dPhidth = (2.0 * T.reta) * (5.0 * Pp - th * dPp) * s6;
 #pragma unroll
-    for (int p = 0; p < 2; ++p) out[p] = dPhidth * (-0.125 * th * (G.dtc[p] / tau - G.mu[p]));
+    for (int p = 0; p < 2; ++p) out[p] = dPhidth * (-0.125 * th * (G.dtc[p] * itau - G.mu[p]));
 }
 
 // ------------------------------------------------------------------ response tangents
@@ -569,12 +574,25 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 2 : 1) void k_vjp_wave(VjpArg
             SkyD<R> S;
             sky_dual(S, a.ct[i], a.phi[i], a.psi[i], a.ci[i]);
             int m_end = a.Nt;
+            // FP32 form (two waves per SIMD): each chunk's track is evaluated during the previous chunk, beside
+            // that chunk's response tangents, so the dependent FP64 chain overlaps the FP32 work.  The FP64 form
+            // (one wave per SIMD, at its register limit) evaluates it at the top of its chunk, which measured faster.
+            constexpr bool kAhead = sizeof(R) == 4;
+            double Phi = 0.0, f = 0.0, fdot = 0.0, s_th = 1.0;
+            int code = 0;
+            if constexpr (kAhead) {
+                code = track_step_lanes(T, (double)(lane < a.Nt ? lane : a.Nt - 1) * a.dT, a.dT, a.df, a.fnyq, Phi, f,
+                                        fdot, &s_th);
+                code = lane < a.Nt ? code : 0;
+            }
             for (int m0 = 0; m0 < m_end; m0 += 64) {
                 const int m = m0 + lane;
                 const bool inr = m < a.Nt;
-                double Phi, f, fdot;
-                int code = track_step_lanes(T, (double)(inr ? m : a.Nt - 1) * a.dT, a.dT, a.df, a.fnyq, Phi, f, fdot);
-                code = inr ? code : 0;
+                if constexpr (!kAhead) {
+                    code = track_step_lanes(T, (double)(inr ? m : a.Nt - 1) * a.dT, a.dT, a.df, a.fnyq, Phi, f, fdot,
+                                            &s_th);
+                    code = inr ? code : 0;
+                }
                 const uint64_t viol = __ballot(code != 0);
                 int lim = a.Nt;
                 if (viol) {
@@ -583,34 +601,41 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 2 : 1) void k_vjp_wave(VjpArg
                 }
                 const bool active = inr && m < lim;
                 const double wm = active ? a.tranche_w[m] : 0.0;
+                // adjoint coefficients of this tranche's segment
+                double ar = 0.0, ai = 0.0, b = 0.0;
+                int sn = 0;
                 if (active && wm != 0.0) {
-                    // adjoint coefficients of this tranche's segment
-                    const int sn = (int)(((int64_t)m * ns) / a.Nt);
+                    sn = (int)(((int64_t)m * ns) / a.Nt);
                     const int64_t o = off + sn;
                     const double zr = a.seg_zn[3 * o], zi = a.seg_zn[3 * o + 1], Nn = a.seg_zn[3 * o + 2];
                     const double g = gs + (a.g_seg ? a.g_seg[o] : 0.0);
-                    double ar = 0.0, ai = 0.0, b = 0.0;
                     if (Nn > 0.0 && g != 0.0) {
                         const double iN = 1.0 / Nn;
                         ar = 4.0 * g * zr * iN;
                         ai = -4.0 * g * zi * iN;
                         b = 4.0 * g * (zr * zr + zi * zi) * iN * iN;
                     }
-                    if (ar != 0.0 || ai != 0.0 || b != 0.0) {
+                }
+                const bool work = ar != 0.0 || ai != 0.0 || b != 0.0;
+                // pixel and spectrum sums of the working lanes
+                R S1r[C], S1i[C], Ur[C][2], Ui[C][2];
+                R S2 = (R)0, Vr[2] = {(R)0, (R)0}, Vi[2] = {(R)0, (R)0};
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    S1r[c] = S1i[c] = (R)0;
+                    Ur[c][0] = Ur[c][1] = Ui[c][0] = Ui[c][1] = (R)0;
+                }
+                R dfr[2] = {(R)0, (R)0};
+                {
+                    if (work) {
                         const int m_ref = (int)(((int64_t)sn * a.Nt + ns - 1) / ns);
                         double dref[2];
                         dphi_at(T, TT, (double)m_ref * a.dT, dref);
-                        const TrackDual TD = track_dual(T, TT, (double)m * a.dT, f);
+                        const TrackDual TD = track_dual(T, TT, (double)m * a.dT, f, s_th);
+                        dfr[0] = (R)TD.df[0];
+                        dfr[1] = (R)TD.df[1];
                         SpecD<R> sp;
                         const int kc = spec_dual(sp, Phi, f, fdot, TD, dref, a.dT);
-                        // bin sums
-                        R S1r[C], S1i[C], Ur[C][2], Ui[C][2];
-                        R S2 = (R)0, Vr[2] = {(R)0, (R)0}, Vi[2] = {(R)0, (R)0};
-#pragma unroll
-                        for (int c = 0; c < C; ++c) {
-                            S1r[c] = S1i[c] = (R)0;
-                            Ur[c][0] = Ur[c][1] = Ui[c][0] = Ui[c][1] = (R)0;
-                        }
                         for (int j = -kHalfBins; j <= kHalfBins; ++j) {
                             const int k = kc + j;
                             if (k < 1 || k > kmax) continue;
@@ -647,6 +672,24 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 2 : 1) void k_vjp_wave(VjpArg
                                 }
                             }
                         }
+                    }
+                }
+                // this chunk's response tangents and the next chunk's track, for every lane (values of lanes
+                // without work are not used; the geometry row is clamped into the table)
+                CDn<4, R> Tc[3];
+                {
+                    double gm[kGeoRows];
+                    load_geo(a.geo, inr ? m : a.Nt - 1, a.Nt, gm);
+                    transfer_ae_dual<(C == 3)>(S, gm, f, Tc[0], Tc[1], Tc[2]);
+                    if constexpr (kAhead) {
+                        const int mn = m + 64;
+                        int cn = track_step_lanes(T, (double)(mn < a.Nt ? mn : a.Nt - 1) * a.dT, a.dT, a.df, a.fnyq, Phi,
+                                                  f, fdot, &s_th);
+                        code = mn < a.Nt ? cn : 0;
+                    }
+                }
+                if (work) {
+                    {
                         // tranche weight: H carries w_m
                         const R wr = (R)wm, w2 = wr * wr;
                         S2 *= w2;
@@ -655,12 +698,7 @@ __global__ __launch_bounds__(256, sizeof(R) == 4 ? 2 : 1) void k_vjp_wave(VjpArg
                             Vr[p] *= w2;
                             Vi[p] *= w2;
                         }
-                        CDn<4, R> Tc[3];
-                        double gm[kGeoRows];
-                        load_geo(a.geo, m, a.Nt, gm);
-                        transfer_ae_dual<(C == 3)>(S, gm, f, Tc[0], Tc[1], Tc[2]);
                         const R arr = (R)ar, air = (R)ai, br = (R)b;
-                        const R dfr[2] = {(R)TD.df[0], (R)TD.df[1]};
 #pragma unroll
                         for (int c = 0; c < C; ++c) {
                             const R tr = Tc[c].re.v, ti = Tc[c].im.v;
