@@ -70,6 +70,12 @@ struct VjpLaunch {
     double *g_params;
 };
 
+// Processing order: templates grouped by the frequency bin of f0, then by ln Mc in kOrderMcClasses classes
+// over [kOrderLnMcLo, kOrderLnMcHi) (clamped at the ends).
+constexpr int kOrderMcClasses = 256;
+constexpr double kOrderLnMcLo = -0.6931471805599453;  // ln 0.5
+constexpr double kOrderLnMcHi = 6.214608098422191;    // ln 500
+
 struct OrderLaunch {
     int M;
     double dt;
@@ -77,7 +83,7 @@ struct OrderLaunch {
     const double *mc, *eta, *f0, *ct, *ci;
     const double *ln_mc;
     int32_t *order;
-    uint32_t *ws;  // 2 (M/2 + 2) counters
+    uint32_t *ws;  // 2 ((M/2 + 1) kOrderMcClasses + 1) counters
 };
 
 struct FollowLaunch {

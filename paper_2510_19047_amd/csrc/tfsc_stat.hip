@@ -85,12 +85,17 @@ __global__ void k_layout_offsets(int64_t n, const int32_t *__restrict__ nseg, co
 // ------------------------------------------------------------------ processing order
 __global__ void k_zero_u32(uint32_t *p, int n);
 
-// Counting sort of the bank by the frequency bin of f0 (invalid rows last): bucket
-// histogram, exclusive scan, scatter.  Within a bucket the order follows the atomics.
-__device__ __forceinline__ int order_bucket(double f0, double dT, int K, bool ok) {
-    if (!ok) return K;
+// Counting sort of the bank by the frequency bin of f0 and, within it, by a class of ln Mc (invalid rows
+// last): bucket histogram, exclusive scan, scatter.  Templates adjacent in the order then share rows for
+// longer (similar chirps from the same start), so waves that run at the same time reuse each other's
+// pixel rows in L2.  Within a bucket the order follows the atomics.
+__device__ __forceinline__ int order_bucket(double f0, double mc, double dT, int K, bool ok) {
+    if (!ok) return K * kOrderMcClasses;
     const double b = floor(f0 * dT);
-    return b < 0.0 ? 0 : (b > (double)(K - 1) ? K - 1 : (int)b);
+    const int kb = b < 0.0 ? 0 : (b > (double)(K - 1) ? K - 1 : (int)b);
+    const double c = floor((log(mc) - kOrderLnMcLo) * (kOrderMcClasses / (kOrderLnMcHi - kOrderLnMcLo)));
+    const int mcl = c < 0.0 ? 0 : (c > (double)(kOrderMcClasses - 1) ? kOrderMcClasses - 1 : (int)c);
+    return kb * kOrderMcClasses + mcl;
 }
 
 __global__ void k_order_hist(int64_t n, const double *__restrict__ mc, const double *__restrict__ ln_mc,
@@ -100,30 +105,29 @@ __global__ void k_order_hist(int64_t n, const double *__restrict__ mc, const dou
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const bool ok = params_valid(bank_mc(mc, ln_mc, i), eta[i], f0[i], ct[i], ci[i]);
-    atomicAdd(count + order_bucket(f0[i], dT, K, ok), 1u);
+    atomicAdd(count + order_bucket(f0[i], ok ? bank_mc(mc, ln_mc, i) : 1.0, dT, K, ok), 1u);
 }
 
-// exclusive scan of count[0..nb) into cursor[0..nb), one block of 1024 threads
+// exclusive scan of count[0..nb) into cursor[0..nb), one block of 1024 threads: each thread sums a contiguous
+// run of nb / 1024 buckets, the block scans the 1024 run sums, and each thread writes its run's prefixes
 __global__ void k_order_scan(int nb, const uint32_t *__restrict__ count, uint32_t *__restrict__ cursor) {
     __shared__ uint32_t sh[1024];
-    __shared__ uint32_t carry;
-    if (threadIdx.x == 0) carry = 0;
+    const int per = (nb + 1023) / 1024;
+    const int lo = min((int)threadIdx.x * per, nb), hi = min(lo + per, nb);
+    uint32_t run = 0;
+    for (int b = lo; b < hi; ++b) run += count[b];
+    sh[threadIdx.x] = run;
     __syncthreads();
-    for (int base = 0; base < nb; base += 1024) {
-        const int idx = base + threadIdx.x;
-        const uint32_t v = idx < nb ? count[idx] : 0u;
-        sh[threadIdx.x] = v;
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t t = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0u;
         __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            const uint32_t t = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0u;
-            __syncthreads();
-            sh[threadIdx.x] += t;
-            __syncthreads();
-        }
-        if (idx < nb) cursor[idx] = carry + sh[threadIdx.x] - v;
+        sh[threadIdx.x] += t;
         __syncthreads();
-        if (threadIdx.x == 1023) carry += sh[1023];
-        __syncthreads();
+    }
+    uint32_t pos = sh[threadIdx.x] - run;
+    for (int b = lo; b < hi; ++b) {
+        cursor[b] = pos;
+        pos += count[b];
     }
 }
 
@@ -135,13 +139,13 @@ __global__ void k_order_scatter(int64_t n, const double *__restrict__ mc, const 
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const bool ok = params_valid(bank_mc(mc, ln_mc, i), eta[i], f0[i], ct[i], ci[i]);
-    const uint32_t pos = atomicAdd(cursor + order_bucket(f0[i], dT, K, ok), 1u);
+    const uint32_t pos = atomicAdd(cursor + order_bucket(f0[i], ok ? bank_mc(mc, ln_mc, i) : 1.0, dT, K, ok), 1u);
     order[pos] = (int32_t)i;
 }
 
 hipError_t launch_order(const OrderLaunch &L, hipStream_t st) {
     if (L.n == 0) return hipSuccess;
-    const int K = L.M / 2 + 1, nb = K + 1;
+    const int K = L.M / 2 + 1, nb = K * kOrderMcClasses + 1;
     const double dT = (double)L.M * L.dt;
     uint32_t *count = L.ws, *cursor = L.ws + nb;
     const unsigned blocks = (unsigned)((L.n + 255) / 256);

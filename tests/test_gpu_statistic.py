@@ -1,6 +1,8 @@
 """GPU parity of the statistic path against the FP64 oracle (HIP through the C ABI)."""
 import functools
 
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -253,7 +255,8 @@ def test_16bit_store_error_against_oracle(dtype, tol, layout):
 
 
 def test_device_processing_order():
-    """tfsc_processing_order: a permutation sorted by the f0 bin (invalid last); results do not depend on it."""
+    """tfsc_processing_order: a permutation sorted by the f0 bin (invalid last) and, within a bin, by classes of
+    ln Mc 1/256 of [ln 0.5, ln 500) wide; results do not depend on it."""
     tfsc = lib()
     d = small_data()
     g = d["grid"]
@@ -266,6 +269,12 @@ def test_device_processing_order():
     K = g.tranche_len // 2 + 1
     key = np.where(valid, np.clip(np.floor(b.f0 * g.tranche_dur), 0, K - 1), K)
     assert np.all(np.diff(key[order]) >= 0)
+    # within a bin, ln Mc never falls by a class width or more from one template to the next
+    width = (math.log(500.0) - math.log(0.5)) / 256
+    lnmc = np.log(b.mc)[order]
+    same = (np.diff(key[order]) == 0) & (key[order][1:] < K)
+    assert np.all(np.diff(lnmc)[same] > -width * (1 + 1e-9))
+    assert np.any(same)
     seg = tfsc.segment_layout(gridspec(g), bt)
     store = store_from_oracle(d, "f32")
     a = tfsc.bank_statistic(gridspec(g), store, bt, seg, precision="f32", schedule="wave")
