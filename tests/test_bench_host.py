@@ -51,7 +51,7 @@ def test_summarize_counters_medians_clock_and_calibrated_traffic(tmp_path, monke
                _row(d, CHOSEN, "SQ_INSTS_VALU_FMA_F32", 1.0e10), _row(d, CHOSEN, "SQ_INSTS_VALU_ADD_F64", 1.0e9)]
     _write(tmp_path / "p_sq", sq)
     bench.summarize_counters([str(tmp_path / "p_bytes"), str(tmp_path / "p_sq")], 1000020, "f32", "layer_ci",
-                             "f0 bin", "4x4", 2.0, 1.0)
+                             "f0 bin, ln Mc", "4x4", 2.0, 1.0)
     rec = {}
     for line in prof.read_text().splitlines():
         if ":" in line and not line.startswith("#"):
@@ -65,14 +65,14 @@ def test_summarize_counters_medians_clock_and_calibrated_traffic(tmp_path, monke
     assert float(rec["traffic_bytes"]) == pytest.approx(2.0e6 * 1024 * 2.0 + 2.0e3 * 1024 * 1.0)
     assert float(rec["flops"]) == pytest.approx(64 * (2 * 1.0e10 + 1.0e9 + 4.0e9 + 1.0e9))  # FMA x2, ADD, TRANS
     # the record is read back only for the same source, bank size, store, layout and order
-    p = bench.measured_profile(1000020, "f32", "layer_ci", "f0 bin")
+    p = bench.measured_profile(1000020, "f32", "layer_ci", "f0 bin, ln Mc")
     assert p is not None and p["valu_insts"] == pytest.approx(5.0e10)
-    assert bench.measured_profile(1000000, "f32", "layer_ci", "f0 bin") is None
-    assert bench.measured_profile(1000020, "i16", "layer_ci", "f0 bin") is None
+    assert bench.measured_profile(1000000, "f32", "layer_ci", "f0 bin, ln Mc") is None
+    assert bench.measured_profile(1000020, "i16", "layer_ci", "f0 bin, ln Mc") is None
     assert bench.measured_profile(1000020, "f32", "layer_ci", "bank") is None
     text = prof.read_text().replace(rec["source_sha256"], "0" * 64)
     prof.write_text(text)
-    assert bench.measured_profile(1000020, "f32", "layer_ci", "f0 bin") is None
+    assert bench.measured_profile(1000020, "f32", "layer_ci", "f0 bin, ln Mc") is None
 
 
 def test_alu_roofline_against_the_rated_issue_rate():
