@@ -1012,6 +1012,12 @@ def alu_roofline(prof, k_s):
                 "valu_insts_per_launch": prof["valu_insts"], "valu_issue_insts_per_launch": issue,
                 "valu_all_over_profile_clock_peak": round(prof["valu_insts"] / k_s / peak_clk, 4),
                 "issue_note": "issue count excludes the transcendental VALU instructions, which overlap the others"})
+    if prof.get("dispatch_ns_counter_run"):
+        # the counter run's own issue fraction: its instructions, its dispatch time and its clock
+        rec["issue_in_profile_run"] = round(issue / (prof["dispatch_ns_counter_run"] * 1e-9) / peak_clk, 4)
+        rec["profile_note"] = ("frac_at_profile_clock divides this run's rate by the counter run's clock; "
+                               "issue_in_profile_run is the counter run's own fraction (above 1: some counted "
+                               "instructions take fewer than 4 cycles)")
     if "flops" in prof:
         tf = prof["flops"] / k_s / 1e12
         peak_tf = SIMDS * 16 * 2 * NOMINAL_CLOCK_HZ / 1e12

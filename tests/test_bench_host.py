@@ -84,6 +84,10 @@ def test_alu_roofline_against_the_rated_issue_rate():
     # at the profile's own 2.0 GHz clock the same rate exceeds that clock's issue rate
     assert r["peak_at_profile_clock"] == pytest.approx(512.0) and r["frac_at_profile_clock"] == pytest.approx(1.2)
     assert r["flops"]["peak_tflops"] == pytest.approx(78.64, rel=1e-3) and r["flops"]["frac"] == pytest.approx(1.0, rel=1e-3)
+    # the counter run's own fraction uses its dispatch time: 6.144e10 in 0.125 s at 2.0 GHz is 0.96
+    r2 = bench.alu_roofline(dict(prof, dispatch_ns_counter_run=1.25e8), 0.1)
+    assert r2["issue_in_profile_run"] == pytest.approx(0.96)
+    assert "issue_in_profile_run" not in r
     # half the rate is half the rated peak; no profile gives no fraction
     assert bench.alu_roofline(prof, 0.2)["frac"] == pytest.approx(0.5)
     none = bench.alu_roofline(None, 0.1)
