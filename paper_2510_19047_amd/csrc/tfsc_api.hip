@@ -138,7 +138,10 @@ size_t ws_bytes_for(const tfsc_grid *g, int64_t n, int which) {
         case TFSC_WS_VJP:
             return stat_ws_bytes(g, n, true);
         case TFSC_WS_ORDER:
-            return align_up(sizeof(uint32_t) * 2 * ((size_t)(g->tranche_len / 2 + 1) * tfsc::kOrderMcClasses + 1));
+        {
+            const size_t nb = (size_t)(g->tranche_len / 2 + 1) * tfsc::kOrderMcClasses + 1;
+            return align_up(sizeof(uint32_t) * (2 * nb + (nb + 1023) / 1024));
+        }
         case TFSC_WS_TRANSFORM: {
             size_t K = (size_t)g->tranche_len / 2 + 1;
             return align_up(sizeof(float) * 2 * (size_t)g->n_channels * K * (size_t)g->n_tranches) +

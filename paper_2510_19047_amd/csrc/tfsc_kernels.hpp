@@ -83,7 +83,7 @@ struct OrderLaunch {
     const double *mc, *eta, *f0, *ct, *ci;
     const double *ln_mc;
     int32_t *order;
-    uint32_t *ws;  // 2 ((M/2 + 1) kOrderMcClasses + 1) counters
+    uint32_t *ws;  // 2 nb + ceil(nb / 1024) counters, nb = (M/2 + 1) kOrderMcClasses + 1
 };
 
 struct FollowLaunch {

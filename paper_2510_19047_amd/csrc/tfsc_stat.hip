@@ -108,15 +108,11 @@ __global__ void k_order_hist(int64_t n, const double *__restrict__ mc, const dou
     atomicAdd(count + order_bucket(f0[i], ok ? bank_mc(mc, ln_mc, i) : 1.0, dT, K, ok), 1u);
 }
 
-// exclusive scan of count[0..nb) into cursor[0..nb), one block of 1024 threads: each thread sums a contiguous
-// run of nb / 1024 buckets, the block scans the 1024 run sums, and each thread writes its run's prefixes
-__global__ void k_order_scan(int nb, const uint32_t *__restrict__ count, uint32_t *__restrict__ cursor) {
-    __shared__ uint32_t sh[1024];
-    const int per = (nb + 1023) / 1024;
-    const int lo = min((int)threadIdx.x * per, nb), hi = min(lo + per, nb);
-    uint32_t run = 0;
-    for (int b = lo; b < hi; ++b) run += count[b];
-    sh[threadIdx.x] = run;
+// Exclusive scan of count[0..nb) into cursor[0..nb) in three passes: each block of 1024 threads scans 1024
+// consecutive buckets (coalesced) and writes its total, one block scans the totals (at most 1024 of them), and
+// each block adds its offset.
+__device__ __forceinline__ uint32_t block_scan_inclusive_1024(uint32_t v, uint32_t *sh) {
+    sh[threadIdx.x] = v;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
         const uint32_t t = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0u;
@@ -124,11 +120,29 @@ __global__ void k_order_scan(int nb, const uint32_t *__restrict__ count, uint32_
         sh[threadIdx.x] += t;
         __syncthreads();
     }
-    uint32_t pos = sh[threadIdx.x] - run;
-    for (int b = lo; b < hi; ++b) {
-        cursor[b] = pos;
-        pos += count[b];
-    }
+    return sh[threadIdx.x];
+}
+
+__global__ void k_order_scan_local(int nb, const uint32_t *__restrict__ count, uint32_t *__restrict__ cursor,
+                                   uint32_t *__restrict__ block_tot) {
+    __shared__ uint32_t sh[1024];
+    const int b = blockIdx.x * 1024 + threadIdx.x;
+    const uint32_t v = b < nb ? count[b] : 0u;
+    const uint32_t inc = block_scan_inclusive_1024(v, sh);
+    if (b < nb) cursor[b] = inc - v;
+    if (threadIdx.x == 1023) block_tot[blockIdx.x] = inc;
+}
+
+__global__ void k_order_scan_top(int nblk, uint32_t *__restrict__ block_tot) {
+    __shared__ uint32_t sh[1024];
+    const uint32_t v = (int)threadIdx.x < nblk ? block_tot[threadIdx.x] : 0u;
+    const uint32_t inc = block_scan_inclusive_1024(v, sh);
+    if ((int)threadIdx.x < nblk) block_tot[threadIdx.x] = inc - v;
+}
+
+__global__ void k_order_scan_add(int nb, uint32_t *__restrict__ cursor, const uint32_t *__restrict__ block_off) {
+    const int b = blockIdx.x * 1024 + threadIdx.x;
+    if (b < nb) cursor[b] += block_off[blockIdx.x];
 }
 
 __global__ void k_order_scatter(int64_t n, const double *__restrict__ mc, const double *__restrict__ ln_mc,
@@ -147,12 +161,16 @@ hipError_t launch_order(const OrderLaunch &L, hipStream_t st) {
     if (L.n == 0) return hipSuccess;
     const int K = L.M / 2 + 1, nb = K * kOrderMcClasses + 1;
     const double dT = (double)L.M * L.dt;
-    uint32_t *count = L.ws, *cursor = L.ws + nb;
+    const int nblk = (nb + 1023) / 1024;  // at most 1024: K <= 2049 and 256 classes
+    if (nblk > 1024) return hipErrorInvalidValue;
+    uint32_t *count = L.ws, *cursor = L.ws + nb, *block_tot = L.ws + 2 * nb;
     const unsigned blocks = (unsigned)((L.n + 255) / 256);
     hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, st, count, nb);
     hipLaunchKernelGGL(k_order_hist, dim3(blocks), dim3(256), 0, st, L.n, L.mc, L.ln_mc, L.eta, L.f0, L.ct, L.ci, dT, K,
                        count);
-    hipLaunchKernelGGL(k_order_scan, dim3(1), dim3(1024), 0, st, nb, count, cursor);
+    hipLaunchKernelGGL(k_order_scan_local, dim3((unsigned)nblk), dim3(1024), 0, st, nb, count, cursor, block_tot);
+    hipLaunchKernelGGL(k_order_scan_top, dim3(1), dim3(1024), 0, st, nblk, block_tot);
+    hipLaunchKernelGGL(k_order_scan_add, dim3((unsigned)nblk), dim3(1024), 0, st, nb, cursor, block_tot);
     hipLaunchKernelGGL(k_order_scatter, dim3(blocks), dim3(256), 0, st, L.n, L.mc, L.ln_mc, L.eta, L.f0, L.ct, L.ci, dT, K,
                        cursor, L.order);
     return hipGetLastError();
