@@ -512,7 +512,7 @@ def statistic_vjp(grid: GridSpec, pixels: PixelStore, bank: BankTensors, seg: Se
 
 
 def processing_order(grid: GridSpec, bank: BankTensors, out: torch.Tensor | None = None) -> torch.Tensor:
-    """tfsc_processing_order: an int32 permutation grouping templates by the frequency bin of f0."""
+    """tfsc_processing_order: an int32 permutation grouping templates by the frequency bin of f0, then by ln Mc."""
     L = lib()
     dev = bank.device
     if out is None:

@@ -2,7 +2,7 @@
 
 * the batching bank (4M templates, Mc log-U[5, 100] Msun, f0 U[5, 50] mHz, about half merging in the window,
   tracks of 59 to 5,964 tranches) in the chosen form (GPU transform, FP32 channel-interleaved store, wave
-  schedule, f0-bin order) against the FP64 oracle on 1,200 sampled templates that include the shortest and
+  schedule, the device processing order) against the FP64 oracle on 1,200 sampled templates that include the shortest and
   longest tracks and templates merging in the window;
 * the FP64 VJP on 16 of the top 65,536 candidates of that bank (the differentiation workload's inputs)
   against the oracle's float64 autograd;
