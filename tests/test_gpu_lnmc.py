@@ -1,11 +1,14 @@
 """A bank given in ln Mc (tfsc_bank.ln_mc, the differentiable parameter of the VJP) through the C ABI: the
 same results as the bank given in Mc, to the rounding of exp (the device's FP64 exp is within an ulp of the
 host's), for the layout, the track, both statistic schedules, the VJP and the follow-up step."""
+import math
+
 import numpy as np
 import pytest
 import torch
 
 from gpu_common import gridspec, lib, note, rel, small_data, store_from_oracle
+from oracle import track as otrk
 
 pytestmark = pytest.mark.gpu
 
@@ -48,6 +51,29 @@ def test_ln_mc_bank_gives_the_mc_bank_results():
             e = np.abs(gl - ga) / np.maximum(np.abs(ga), floor)
             note(f"  VJP: max rel {e.max():.2e}")
             assert e.max() < 1e-6
+
+
+def test_ln_mc_bank_processing_order():
+    """The processing order of a bank given in ln Mc sorts by the f0 bin and, within a bin, by ln Mc classes
+    1/256 of [ln 0.5, ln 500) wide, as for the bank given in Mc."""
+    tfsc = lib()
+    d = small_data()
+    g = d["grid"]
+    b = d["bank"]
+    bt, bl = _banks(tfsc, b)
+    K = g.tranche_len // 2 + 1
+    valid = otrk.params_valid(b.mc, b.eta, b.f0, b.cos_theta, b.cos_iota)
+    key = np.where(valid, np.clip(np.floor(b.f0 * g.tranche_dur), 0, K - 1), K)
+    width = (math.log(500.0) - math.log(0.5)) / 256
+    with np.errstate(invalid="ignore"):
+        lnmc = np.log(b.mc)
+    for bank in (bt, bl):
+        order = tfsc.processing_order(gridspec(g), bank).cpu().numpy()
+        assert np.array_equal(np.sort(order), np.arange(len(b)))
+        assert np.all(np.diff(key[order]) >= 0)
+        same = (np.diff(key[order]) == 0) & (key[order][1:] < K)
+        assert np.any(same)
+        assert np.all(np.diff(lnmc[order])[same] > -width * (1 + 1e-9))
 
 
 def test_follow_up_step_moves_ln_mc():
