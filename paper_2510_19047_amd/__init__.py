@@ -536,16 +536,25 @@ def follow_up_step(grid: GridSpec, bank: BankTensors, seg: SegmentLayout, stat: 
 
 
 def follow_up(grid: GridSpec, pixels: PixelStore, bank: BankTensors, steps: int = 50, lr_scale: float = 0.5,
-              nseg_fixed: int = 0, precision: str = "f32", vjp_precision: str = "f64"):
+              nseg_fixed: int = 0, precision: str = "f32", vjp_precision: str = "f64", sort: bool = True):
     """Gradient-ascent follow-up of a candidate set: ``steps`` rounds of statistic, VJP and Adam step.
 
     ``precision`` is the statistic's arithmetic and ``vjp_precision`` the VJP's.  The segment layout is fixed
     at the candidates' initial parameters.  Returns (initial Upsilon, best Upsilon, best parameters [n][5] =
-    (mc, f0, cos theta, phi, psi)).  ``bank`` is not modified.
+    (mc, f0, cos theta, phi, psi)), in the order of ``bank``, which is not modified.  ``sort`` works on a copy
+    of the candidates in the processing order (f0 bin, then ln Mc), so that the statistic and VJP waves that
+    run together read neighbouring pixel rows; every template's arithmetic is its own, so the results are the
+    same either way.
     """
     dev = bank.device
-    work = BankTensors(*(None if getattr(bank, k) is None else getattr(bank, k).clone() for k in BankTensors.FIELDS),
-                       ln_mc=None if bank.ln_mc is None else bank.ln_mc.clone())
+    perm = processing_order(grid, bank).long() if sort and bank.n > 1 else None
+
+    def take(t):
+        if t is None:
+            return None
+        return (t[perm] if perm is not None else t).clone()
+
+    work = BankTensors(*(take(getattr(bank, k)) for k in BankTensors.FIELDS), ln_mc=take(bank.ln_mc))
     seg = segment_layout(grid, work, nseg_fixed)
     state = torch.empty((work.n, 16), dtype=torch.float64, device=dev)
     ones = torch.ones(work.n, dtype=torch.float64, device=dev)
@@ -561,7 +570,12 @@ def follow_up(grid: GridSpec, pixels: PixelStore, bank: BankTensors, steps: int 
             break
         statistic_vjp(grid, pixels, work, seg, res.seg_zn, g_stat=ones, precision=vjp_precision, out=gp)
         follow_up_step(grid, work, seg, res.stat, gp, state, lr_scale, step)
-    return first, state[:, 10].clone(), state[:, 11:16].clone()
+    best, params = state[:, 10].clone(), state[:, 11:16].clone()
+    if perm is not None:
+        inv = torch.empty_like(perm)
+        inv[perm] = torch.arange(perm.numel(), device=dev)
+        first, best, params = first[inv], best[inv], params[inv]
+    return first, best, params
 
 
 def tile_max(stat: torch.Tensor, tile: torch.Tensor, n_tiles: int, out: tuple | None = None):
