@@ -2,9 +2,11 @@
 // tranche is Tukey-windowed and Fourier transformed once; per-tranche PSD;
 // tranches overlapping gaps are excluded).
 //
-// One block handles TB consecutive tranches of one channel: each tranche is
-// windowed into LDS, transformed by a radix-2 Stockham FFT (natural order in
-// and out, twiddles from a per-block LDS table), whitened, and parked in an
+// One block handles TB consecutive tranches of one channel: each pair of
+// tranches is windowed into LDS as the real and imaginary parts of one complex
+// sequence, transformed by a radix-2 Stockham FFT (natural order in and out,
+// twiddles from a per-block LDS table), split into the two tranches' spectra,
+// whitened, and parked in an
 // LDS tile [K][TB]; the tile is then written so that the TB tranches of a
 // frequency layer are contiguous (LAYER_MAJOR, or LAYER_MAJOR_CI with the channels of a
 // pixel adjacent) or the K bins of a tranche are contiguous (TRANCHE_MAJOR).  16-bit stores go through an FP32 staging
@@ -57,11 +59,15 @@ __global__ __launch_bounds__(256) void k_transform(TransformLaunch L, double w2)
     const XT *x = reinterpret_cast<const XT *>(L.x) + (size_t)c * M * Nt;
     __syncthreads();
 
-    for (int tt = 0; tt < TB; ++tt) {
+    // Two real tranches per complex FFT: z = x_m + i x_{m+1}, whose transform Z gives
+    // X_m[k] = (Z[k] + conj Z[M-k]) / 2 and X_{m+1}[k] = (Z[k] - conj Z[M-k]) / (2i).
+    static_assert(TB % 2 == 0, "tranches are transformed in pairs");
+    for (int tt = 0; tt < TB; tt += 2) {
         const int m = m0 + tt;
         if (m >= Nt) break;  // uniform across the block
+        const bool two = m + 1 < Nt;
         for (int n = threadIdx.x; n < M; n += blockDim.x)
-            bufA[n] = {(R)x[(size_t)m * M + n] * win[n], (R)0};
+            bufA[n] = {(R)x[(size_t)m * M + n] * win[n], two ? (R)x[(size_t)(m + 1) * M + n] * win[n] : (R)0};
         __syncthreads();
         cx<R> *src = bufA, *dst = bufB;
         for (int Ns = 1; Ns < M; Ns <<= 1) {
@@ -79,14 +85,18 @@ __global__ __launch_bounds__(256) void k_transform(TransformLaunch L, double w2)
             src = dst;
             dst = t;
         }
-        const bool keep = L.keep[m] != 0;
-        const double mu = L.psd_tf ? 1.0 : L.mu[m];
         for (int k = threadIdx.x; k < K; k += blockDim.x) {
-            const double S = L.psd_tf ? L.psd_tf[(size_t)k * Nt + m] : L.psd0[k] * mu;
-            // a bin whose PSD is not positive and finite (DC or Nyquist may carry 0 or inf)
-            // gets pixel 0 rather than inf or NaN; its template weight is 0 as well
-            double sc = keep && psd_ok(S) ? sqrt(2.0 * L.dt / ((double)M * w2 * S)) : 0.0;
-            tile[(size_t)k * TB + tt] = cscale(src[k], (R)sc);
+            const cx<R> zk = src[k], zn = src[(M - k) & (M - 1)];
+            const cx<R> X[2] = {{(R)0.5 * (zk.re + zn.re), (R)0.5 * (zk.im - zn.im)},
+                                {(R)0.5 * (zk.im + zn.im), (R)0.5 * (zn.re - zk.re)}};
+            for (int j = 0; j < (two ? 2 : 1); ++j) {
+                const int mj = m + j;
+                const double S = L.psd_tf ? L.psd_tf[(size_t)k * Nt + mj] : L.psd0[k] * L.mu[mj];
+                // a bin whose PSD is not positive and finite (DC or Nyquist may carry 0 or inf)
+                // gets pixel 0 rather than inf or NaN; its template weight is 0 as well
+                const double sc = L.keep[mj] != 0 && psd_ok(S) ? sqrt(2.0 * L.dt / ((double)M * w2 * S)) : 0.0;
+                tile[(size_t)k * TB + tt + j] = cscale(X[j], (R)sc);
+            }
         }
         __syncthreads();
     }
