@@ -887,6 +887,9 @@ def batching_run(args, tfsc, ti, grid, g, psd_d, mu_d, keep_d, kw, chosen_ms_per
         stat0 = rg.results[0].stat
         top = torch.topk(torch.nan_to_num(stat0, nan=-1.0), 65536).indices
         sub = tfsc.BankTensors(*(getattr(bank, k)[top].contiguous() for k in tfsc.BankTensors.FIELDS))
+        # the candidates in processing order (f0 bin, then ln Mc), as the follow-up runs them
+        perm = tfsc.processing_order(grid, sub).long()
+        sub = tfsc.BankTensors(*(getattr(sub, k)[perm].contiguous() for k in tfsc.BankTensors.FIELDS))
         store0 = rg.stores[0]
         # one forward and one VJP on the candidates, each timed with events on the launch stream
         sseg = tfsc.segment_layout(grid, sub)
